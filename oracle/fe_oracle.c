@@ -1,0 +1,584 @@
+/*
+ * fe_oracle.c -- plain FP64 CPU oracle for the stabilised natural-convection
+ * finite-element operator.  TEST INFRASTRUCTURE ONLY: the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark call it; the product path
+ * (the HIP library) never links or loads it, and shares no code with it.
+ *
+ * What it computes (Alexandersen, Sigmund & Aage, "Large scale three-dimensional
+ * topology optimisation of heat sinks cooled by natural convection"):
+ *
+ *   - the residual R(x; gamma) of the stabilised weak form of the composite
+ *     Navier-Stokes-Brinkman / Boussinesq / convection-diffusion equations
+ *     (Sec. 2, Eqs. BoussDimless-a..c), discretised with trilinear equal-order
+ *     hexahedra and element-constant design (Sec. 4), with SUPG/PSPG
+ *     stabilisation using the single element parameter tau of the appendix
+ *     (Eqs. stabFacs_globalDefinition, stabFacs_SimpleDefinition);
+ *   - its exact directional derivative J v, including the variation of tau with
+ *     the element velocity vector (the consistent Jacobian of Sec. 4 and the
+ *     appendix's d tau / d u_e);
+ *   - J^T w, formed from the element Jacobian matrices (each column an exact
+ *     directional derivative along a unit vector), transposed;
+ *   - lambda^T dR/dgamma_e for the design sensitivities (appendix, d tau / d gamma).
+ *
+ * Every routine is a straight element loop with shape-function tables and no
+ * sum factorisation, blocking or fusion, so that it can be read against the
+ * equations.  Readings of the paper where it is silent (weak form signs,
+ * quadrature, thermal tau, Dirichlet elimination) are the ones listed in the
+ * design notes, restated at each routine below.
+ *
+ * Parity status: residual, J v, J^T w and lambda^T dR/dgamma are pinned by the
+ * CPU tests (central finite differences, brute-force dense Jacobians, textbook
+ * stiffness/mass matrices, invariants, a manufactured solution).
+ *
+ * Layout: x[5*n + f], n = i + (nx+1)*(j + (ny+1)*k), f = u,v,w,p,T;
+ * element e = i + nx*(j + ny*k); mask[5*n+f] = 1 marks a prescribed DOF.
+ * phys = {Pr, Gr, Ck, qf, alpha_max, q_alpha, eg_x, eg_y, eg_z}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NF 5
+#define NEN 8
+#define NED (NEN * NF)
+
+typedef struct {
+    double h, Pr, Gr, Ck, qf, amax, qa, eg[3];
+    double B; /* buoyancy coefficient Gr * Pr^2 (Eq. BoussDimless-a) */
+    double W; /* Gauss weight times Jacobian determinant, (h/2)^3 */
+    double N[8][8];     /* N[g][a]: shape function a at Gauss point g */
+    double dN[8][8][3]; /* physical gradient of N_a at Gauss point g */
+    double xg[8][3];    /* Gauss point offset from the element origin */
+} ctx_t;
+
+/* 2x2x2 Gauss-Legendre rule on the cube [ih,(i+1)h]x..., points at the
+ * reference coordinates +-1/sqrt(3), unit weights; local node a = ax+2ay+4az
+ * sits at reference coordinate 2*a_d - 1 in direction d. */
+static void ctx_init(ctx_t *c, double h, const double *phys)
+{
+    c->h = h;
+    c->Pr = phys[0]; c->Gr = phys[1]; c->Ck = phys[2]; c->qf = phys[3];
+    c->amax = phys[4]; c->qa = phys[5];
+    c->eg[0] = phys[6]; c->eg[1] = phys[7]; c->eg[2] = phys[8];
+    c->B = c->Gr * c->Pr * c->Pr;
+    c->W = (h / 2) * (h / 2) * (h / 2);
+    const double q = 1.0 / sqrt(3.0);
+    for (int g = 0; g < 8; ++g) {
+        double xi[3];
+        for (int d = 0; d < 3; ++d) {
+            xi[d] = ((g >> d) & 1) ? q : -q;
+            c->xg[g][d] = 0.5 * h * (1.0 + xi[d]);
+        }
+        for (int a = 0; a < 8; ++a) {
+            double f[3], s[3];
+            for (int d = 0; d < 3; ++d) {
+                s[d] = ((a >> d) & 1) ? 1.0 : -1.0;
+                f[d] = 0.5 * (1.0 + s[d] * xi[d]);
+            }
+            c->N[g][a] = f[0] * f[1] * f[2];
+            for (int d = 0; d < 3; ++d) {
+                double prod = 0.5 * s[d] * (2.0 / h);
+                for (int d2 = 0; d2 < 3; ++d2)
+                    if (d2 != d) prod *= f[d2];
+                c->dN[g][a][d] = prod;
+            }
+        }
+    }
+}
+
+/* Material interpolation (Eqs. conducint and alphaint). */
+static double alpha_of(const ctx_t *c, double g) { return c->amax * (1.0 - g) / (1.0 + c->qa * g); }
+static double K_of(const ctx_t *c, double g)
+{
+    return (g * (c->Ck * (1.0 + c->qf) - 1.0) + 1.0) / (c->Ck * (1.0 + c->qf * g));
+}
+static double dalpha_of(const ctx_t *c, double g)
+{
+    double den = 1.0 + c->qa * g;
+    return -c->amax * (1.0 + c->qa) / (den * den);
+}
+static double dK_of(const ctx_t *c, double g)
+{
+    double den = 1.0 + c->qf * g;
+    return (1.0 + c->qf) * (c->Ck - 1.0) / (c->Ck * den * den);
+}
+
+/* Stabilisation parameters of the appendix.  tau combines the convective
+ * limit 4h/|u_e| (u_e = the element's 24 nodal velocity values), the viscous
+ * limit h^2/(4Pr) and the Brinkman limit 1/alpha_e by the inverse-square sum;
+ * 1/tau_1^2 is written as |u_e|^2/(16 h^2) so that u_e = 0 is regular.  The
+ * thermal parameter combines the convective limit with the diffusive limit
+ * h^2/(4K_e) (the "similar" thermal definition, read with K_e for Pr and no
+ * Brinkman term). */
+static void taus(const ctx_t *c, double U2, double alpha, double K, double *tau, double *tauT)
+{
+    double h = c->h, h2 = h * h, h4 = h2 * h2;
+    *tau = 1.0 / sqrt(U2 / (16.0 * h2) + 16.0 * c->Pr * c->Pr / h4 + alpha * alpha);
+    *tauT = 1.0 / sqrt(U2 / (16.0 * h2) + 16.0 * K * K / h4);
+}
+
+typedef struct {
+    double u[3], G[3][3], p, dp[3], T, dT[3];
+} fields_t;
+
+static void interp(const ctx_t *c, int g, const double xe[NEN][NF], fields_t *F)
+{
+    memset(F, 0, sizeof(*F));
+    for (int a = 0; a < NEN; ++a) {
+        double Na = c->N[g][a];
+        for (int i = 0; i < 3; ++i) {
+            F->u[i] += Na * xe[a][i];
+            for (int j = 0; j < 3; ++j) F->G[i][j] += c->dN[g][a][j] * xe[a][i];
+        }
+        F->p += Na * xe[a][3];
+        F->T += Na * xe[a][4];
+        for (int j = 0; j < 3; ++j) {
+            F->dp[j] += c->dN[g][a][j] * xe[a][3];
+            F->dT[j] += c->dN[g][a][j] * xe[a][4];
+        }
+    }
+}
+
+/* Element residual.  Strong residuals at a Gauss point (the viscous second
+ * derivative is left out of the stabilisation residual, a reading):
+ *   rM_i = u_j dj u_i + di p + alpha u_i + B eg_i T - fM_i
+ *   rT   = u_j dj T - s - fT
+ * Weak form (Galerkin + SUPG weight tau u.grad N_a + PSPG weight tau grad N_a):
+ *   R_{u_i,a} = sum_g W [ N_a (u_j G_ij + alpha u_i + B eg_i T - fM_i)
+ *                        + Pr dj N_a (G_ij + G_ji) - di N_a p + tau (u.grad N_a) rM_i ]
+ *   R_{p,a}   = sum_g W [ N_a G_jj + tau di N_a rM_i ]
+ *   R_{T,a}   = sum_g W [ N_a (u.grad T - s - fT) + K dj N_a dj T + tauT (u.grad N_a) rT ]
+ * ``forc`` (NULL for the physical problem) holds a manufactured forcing
+ * (fM_x, fM_y, fM_z, fT) at the 8 Gauss points of the element. */
+static void elem_residual(const ctx_t *c, const double xe[NEN][NF], double alpha, double K,
+                          double s, const double *forc, double Re[NEN][NF])
+{
+    double U2 = 0.0;
+    for (int a = 0; a < NEN; ++a)
+        for (int i = 0; i < 3; ++i) U2 += xe[a][i] * xe[a][i];
+    double tau, tauT;
+    taus(c, U2, alpha, K, &tau, &tauT);
+    memset(Re, 0, sizeof(double) * NED);
+    for (int g = 0; g < 8; ++g) {
+        fields_t F;
+        interp(c, g, xe, &F);
+        double fM[3] = {0, 0, 0}, fT = 0;
+        if (forc) {
+            for (int i = 0; i < 3; ++i) fM[i] = forc[4 * g + i];
+            fT = forc[4 * g + 3];
+        }
+        double conv[3], rM[3];
+        for (int i = 0; i < 3; ++i) {
+            conv[i] = 0;
+            for (int j = 0; j < 3; ++j) conv[i] += F.u[j] * F.G[i][j];
+            rM[i] = conv[i] + F.dp[i] + alpha * F.u[i] + c->B * c->eg[i] * F.T - fM[i];
+        }
+        double udT = 0;
+        for (int j = 0; j < 3; ++j) udT += F.u[j] * F.dT[j];
+        double rT = udT - s - fT;
+        double divu = F.G[0][0] + F.G[1][1] + F.G[2][2];
+        for (int a = 0; a < NEN; ++a) {
+            double Na = c->N[g][a];
+            const double *dNa = c->dN[g][a];
+            double udN = F.u[0] * dNa[0] + F.u[1] * dNa[1] + F.u[2] * dNa[2];
+            for (int i = 0; i < 3; ++i) {
+                double visc = 0;
+                for (int j = 0; j < 3; ++j) visc += dNa[j] * (F.G[i][j] + F.G[j][i]);
+                Re[a][i] += c->W * (Na * (conv[i] + alpha * F.u[i] + c->B * c->eg[i] * F.T - fM[i])
+                                    + c->Pr * visc - dNa[i] * F.p + tau * udN * rM[i]);
+            }
+            double pspg = dNa[0] * rM[0] + dNa[1] * rM[1] + dNa[2] * rM[2];
+            Re[a][3] += c->W * (Na * divu + tau * pspg);
+            double diff = dNa[0] * F.dT[0] + dNa[1] * F.dT[1] + dNa[2] * F.dT[2];
+            Re[a][4] += c->W * (Na * (udT - s - fT) + K * diff + tauT * udN * rT);
+        }
+    }
+}
+
+/* Element directional derivative dRe = (dRe/dxe) ve, written term by term
+ * from the residual above.  With U2 = |u_e|^2 the element parameters vary as
+ *   dtau  = -tau^3  (u_e . du_e) / (16 h^2),
+ *   dtauT = -tauT^3 (u_e . du_e) / (16 h^2),
+ * which is the appendix's d tau / d u_e applied to du_e. */
+static void elem_jv(const ctx_t *c, const double xe[NEN][NF], const double ve[NEN][NF],
+                    double alpha, double K, double s, const double *forc, double dRe[NEN][NF])
+{
+    double U2 = 0.0, udu = 0.0;
+    for (int a = 0; a < NEN; ++a)
+        for (int i = 0; i < 3; ++i) {
+            U2 += xe[a][i] * xe[a][i];
+            udu += xe[a][i] * ve[a][i];
+        }
+    double tau, tauT;
+    taus(c, U2, alpha, K, &tau, &tauT);
+    double h2 = c->h * c->h;
+    double dtau = -tau * tau * tau * udu / (16.0 * h2);
+    double dtauT = -tauT * tauT * tauT * udu / (16.0 * h2);
+    memset(dRe, 0, sizeof(double) * NED);
+    for (int g = 0; g < 8; ++g) {
+        fields_t F, D;
+        interp(c, g, xe, &F);
+        interp(c, g, ve, &D);
+        double fM[3] = {0, 0, 0}, fT = 0;
+        if (forc) {
+            for (int i = 0; i < 3; ++i) fM[i] = forc[4 * g + i];
+            fT = forc[4 * g + 3];
+        }
+        double rM[3], drM[3], dgal[3];
+        for (int i = 0; i < 3; ++i) {
+            double conv = 0, dconv = 0;
+            for (int j = 0; j < 3; ++j) {
+                conv += F.u[j] * F.G[i][j];
+                dconv += D.u[j] * F.G[i][j] + F.u[j] * D.G[i][j];
+            }
+            rM[i] = conv + F.dp[i] + alpha * F.u[i] + c->B * c->eg[i] * F.T - fM[i];
+            drM[i] = dconv + D.dp[i] + alpha * D.u[i] + c->B * c->eg[i] * D.T;
+            dgal[i] = dconv + alpha * D.u[i] + c->B * c->eg[i] * D.T;
+        }
+        double rT = -s - fT, drT = 0;
+        for (int j = 0; j < 3; ++j) {
+            rT += F.u[j] * F.dT[j];
+            drT += D.u[j] * F.dT[j] + F.u[j] * D.dT[j];
+        }
+        double ddivu = D.G[0][0] + D.G[1][1] + D.G[2][2];
+        for (int a = 0; a < NEN; ++a) {
+            double Na = c->N[g][a];
+            const double *dNa = c->dN[g][a];
+            double udN = F.u[0] * dNa[0] + F.u[1] * dNa[1] + F.u[2] * dNa[2];
+            double dudN = D.u[0] * dNa[0] + D.u[1] * dNa[1] + D.u[2] * dNa[2];
+            for (int i = 0; i < 3; ++i) {
+                double visc = 0;
+                for (int j = 0; j < 3; ++j) visc += dNa[j] * (D.G[i][j] + D.G[j][i]);
+                dRe[a][i] += c->W * (Na * dgal[i] + c->Pr * visc - dNa[i] * D.p
+                                     + dtau * udN * rM[i] + tau * dudN * rM[i] + tau * udN * drM[i]);
+            }
+            double pspg = 0, dpspg = 0;
+            for (int i = 0; i < 3; ++i) {
+                pspg += dNa[i] * rM[i];
+                dpspg += dNa[i] * drM[i];
+            }
+            dRe[a][3] += c->W * (Na * ddivu + dtau * pspg + tau * dpspg);
+            double ddiff = dNa[0] * D.dT[0] + dNa[1] * D.dT[1] + dNa[2] * D.dT[2];
+            dRe[a][4] += c->W * (Na * drT + K * ddiff + dtauT * udN * rT + tauT * dudN * rT
+                                 + tauT * udN * drT);
+        }
+    }
+}
+
+/* Element Jacobian Ke[r][col] = d Re[r] / d xe[col], column by column as the
+ * exact directional derivative along the unit vector of that column. */
+static void elem_jacobian(const ctx_t *c, const double xe[NEN][NF], double alpha, double K,
+                          double s, const double *forc, double Ke[NED][NED])
+{
+    double ve[NEN][NF], col[NEN][NF];
+    for (int cidx = 0; cidx < NED; ++cidx) {
+        memset(ve, 0, sizeof(ve));
+        ve[cidx / NF][cidx % NF] = 1.0;
+        elem_jv(c, xe, ve, alpha, K, s, forc, col);
+        for (int r = 0; r < NED; ++r) Ke[r][cidx] = col[r / NF][r % NF];
+    }
+}
+
+/* Element design derivative dRe/dgamma_e = alpha'(gamma_e) dRe/dalpha + K'(gamma_e) dRe/dK.
+ * tau depends on alpha through its Brinkman limit, d tau/d alpha = -tau^3 alpha,
+ * and tauT on K, d tauT/dK = -tauT^3 16 K / h^4.  (The closed form printed in the
+ * appendix for d tau/d gamma_e carries an extra factor alpha_e^2; the derivative
+ * of the printed definition of tau is used, and the tests confirm it against
+ * finite differences.) */
+static void elem_dRdgamma(const ctx_t *c, const double xe[NEN][NF], double gam, double s,
+                          double dRe[NEN][NF])
+{
+    double alpha = alpha_of(c, gam), K = K_of(c, gam);
+    double da = dalpha_of(c, gam), dK = dK_of(c, gam);
+    double U2 = 0.0;
+    for (int a = 0; a < NEN; ++a)
+        for (int i = 0; i < 3; ++i) U2 += xe[a][i] * xe[a][i];
+    double tau, tauT;
+    taus(c, U2, alpha, K, &tau, &tauT);
+    double h = c->h, h4 = h * h * h * h;
+    double dtau_da = -tau * tau * tau * alpha;
+    double dtauT_dK = -tauT * tauT * tauT * 16.0 * K / h4;
+    memset(dRe, 0, sizeof(double) * NED);
+    for (int g = 0; g < 8; ++g) {
+        fields_t F;
+        interp(c, g, xe, &F);
+        double rM[3];
+        for (int i = 0; i < 3; ++i) {
+            double conv = 0;
+            for (int j = 0; j < 3; ++j) conv += F.u[j] * F.G[i][j];
+            rM[i] = conv + F.dp[i] + alpha * F.u[i] + c->B * c->eg[i] * F.T;
+        }
+        double rT = -s;
+        for (int j = 0; j < 3; ++j) rT += F.u[j] * F.dT[j];
+        for (int a = 0; a < NEN; ++a) {
+            double Na = c->N[g][a];
+            const double *dNa = c->dN[g][a];
+            double udN = F.u[0] * dNa[0] + F.u[1] * dNa[1] + F.u[2] * dNa[2];
+            for (int i = 0; i < 3; ++i) {
+                double dR_da = Na * F.u[i] + dtau_da * udN * rM[i] + tau * udN * F.u[i];
+                dRe[a][i] += c->W * da * dR_da;
+            }
+            double dRp_da = 0;
+            for (int i = 0; i < 3; ++i) dRp_da += dtau_da * dNa[i] * rM[i] + tau * dNa[i] * F.u[i];
+            dRe[a][3] += c->W * da * dRp_da;
+            double diff = dNa[0] * F.dT[0] + dNa[1] * F.dT[1] + dNa[2] * F.dT[2];
+            dRe[a][4] += c->W * dK * (diff + dtauT_dK * udN * rT);
+        }
+    }
+}
+
+/* ---- global assembly ------------------------------------------------------ */
+
+static inline int64_t node_of(int nx, int ny, int i, int j, int k)
+{
+    return (int64_t)i + (int64_t)(nx + 1) * ((int64_t)j + (int64_t)(ny + 1) * k);
+}
+
+static void elem_nodes(int nx, int ny, int i, int j, int k, int64_t nodes[NEN])
+{
+    for (int a = 0; a < NEN; ++a)
+        nodes[a] = node_of(nx, ny, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+}
+
+static void gather(const double *x, const int64_t nodes[NEN], double xe[NEN][NF])
+{
+    for (int a = 0; a < NEN; ++a)
+        for (int f = 0; f < NF; ++f) xe[a][f] = x[NF * nodes[a] + f];
+}
+
+/* Directions are gathered with their prescribed entries set to zero, so the
+ * assembled Jacobian is J = [[J_ff, 0], [0, I]] (symmetric elimination). */
+static void gather_masked(const double *v, const uint8_t *mask, const int64_t nodes[NEN],
+                          double ve[NEN][NF])
+{
+    for (int a = 0; a < NEN; ++a)
+        for (int f = 0; f < NF; ++f) {
+            int64_t d = NF * nodes[a] + f;
+            ve[a][f] = (mask && mask[d]) ? 0.0 : v[d];
+        }
+}
+
+static void scatter_add(double *r, const int64_t nodes[NEN], const double Re[NEN][NF])
+{
+    for (int a = 0; a < NEN; ++a)
+        for (int f = 0; f < NF; ++f) r[NF * nodes[a] + f] += Re[a][f];
+}
+
+/* Element slabs k and k+2 share no node, so the element loop runs in two
+ * passes (even k, then odd k), each parallel over its slabs. */
+#define FOR_ELEMENTS_SLAB_COLOURED(nx, ny, nz, ...)                      \
+    for (int colour = 0; colour < 2; ++colour) {                          \
+        _Pragma("omp parallel for schedule(dynamic, 1)")                  \
+        for (int k = colour; k < (nz); k += 2)                            \
+            for (int j = 0; j < (ny); ++j)                                \
+                for (int i = 0; i < (nx); ++i) { __VA_ARGS__ }            \
+    }
+
+int or_residual(int nx, int ny, int nz, double h, const double *phys, const uint8_t *mask,
+                const double *x, const double *gamma, const double *s, const double *forcing,
+                double *r)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    int64_t ndof = (int64_t)NF * (nx + 1) * (ny + 1) * (nz + 1);
+    memset(r, 0, sizeof(double) * ndof);
+    FOR_ELEMENTS_SLAB_COLOURED(nx, ny, nz, {
+        int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+        int64_t nodes[NEN];
+        double xe[NEN][NF], Re[NEN][NF];
+        elem_nodes(nx, ny, i, j, k, nodes);
+        gather(x, nodes, xe);
+        elem_residual(&c, xe, alpha_of(&c, gamma[e]), K_of(&c, gamma[e]), s[e],
+                      forcing ? forcing + 32 * e : NULL, Re);
+        scatter_add(r, nodes, Re);
+    })
+    if (mask)
+        for (int64_t d = 0; d < ndof; ++d)
+            if (mask[d]) r[d] = 0.0;
+    return 0;
+}
+
+int or_jvp(int nx, int ny, int nz, double h, const double *phys, const uint8_t *mask,
+           const double *x, const double *gamma, const double *s, const double *forcing,
+           const double *v, double *jv)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    int64_t ndof = (int64_t)NF * (nx + 1) * (ny + 1) * (nz + 1);
+    memset(jv, 0, sizeof(double) * ndof);
+    FOR_ELEMENTS_SLAB_COLOURED(nx, ny, nz, {
+        int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+        int64_t nodes[NEN];
+        double xe[NEN][NF], ve[NEN][NF], dRe[NEN][NF];
+        elem_nodes(nx, ny, i, j, k, nodes);
+        gather(x, nodes, xe);
+        gather_masked(v, mask, nodes, ve);
+        elem_jv(&c, xe, ve, alpha_of(&c, gamma[e]), K_of(&c, gamma[e]), s[e],
+                forcing ? forcing + 32 * e : NULL, dRe);
+        scatter_add(jv, nodes, dRe);
+    })
+    if (mask)
+        for (int64_t d = 0; d < ndof; ++d)
+            if (mask[d]) jv[d] = v[d];
+    return 0;
+}
+
+/* J^T w = sum_e Ke^T w_e with the element Jacobian above; prescribed entries of
+ * w are dropped (they multiply the zero columns of the eliminated rows) and the
+ * prescribed rows of the result are w itself. */
+int or_jtvp(int nx, int ny, int nz, double h, const double *phys, const uint8_t *mask,
+            const double *x, const double *gamma, const double *s, const double *forcing,
+            const double *w, double *jtw)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    int64_t ndof = (int64_t)NF * (nx + 1) * (ny + 1) * (nz + 1);
+    memset(jtw, 0, sizeof(double) * ndof);
+    FOR_ELEMENTS_SLAB_COLOURED(nx, ny, nz, {
+        int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+        int64_t nodes[NEN];
+        double xe[NEN][NF], we[NEN][NF], out[NEN][NF];
+        double Ke[NED][NED];
+        elem_nodes(nx, ny, i, j, k, nodes);
+        gather(x, nodes, xe);
+        gather_masked(w, mask, nodes, we);
+        elem_jacobian(&c, xe, alpha_of(&c, gamma[e]), K_of(&c, gamma[e]), s[e],
+                      forcing ? forcing + 32 * e : NULL, Ke);
+        for (int col = 0; col < NED; ++col) {
+            double acc = 0;
+            for (int r = 0; r < NED; ++r) acc += Ke[r][col] * we[r / NF][r % NF];
+            out[col / NF][col % NF] = acc;
+        }
+        scatter_add(jtw, nodes, out);
+    })
+    if (mask)
+        for (int64_t d = 0; d < ndof; ++d)
+            if (mask[d]) jtw[d] = w[d];
+    return 0;
+}
+
+/* g_e = lambda_e^T dRe/dgamma_e, prescribed entries of lambda dropped (their
+ * residual rows are identically zero). */
+int or_dRdgamma(int nx, int ny, int nz, double h, const double *phys, const uint8_t *mask,
+                const double *x, const double *gamma, const double *s, const double *lambda,
+                double *g_out)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+                int64_t nodes[NEN];
+                double xe[NEN][NF], le[NEN][NF], dRe[NEN][NF];
+                elem_nodes(nx, ny, i, j, k, nodes);
+                gather(x, nodes, xe);
+                gather_masked(lambda, mask, nodes, le);
+                elem_dRdgamma(&c, xe, gamma[e], s[e], dRe);
+                double acc = 0;
+                for (int a = 0; a < NEN; ++a)
+                    for (int f = 0; f < NF; ++f) acc += le[a][f] * dRe[a][f];
+                g_out[e] = acc;
+            }
+    return 0;
+}
+
+/* Raw (unmasked) element Jacobians, Ke_out[e][40][40], row/column index a*5+f. */
+int or_element_jacobians(int nx, int ny, int nz, double h, const double *phys, const double *x,
+                         const double *gamma, const double *s, const double *forcing,
+                         double *Ke_out)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+                int64_t nodes[NEN];
+                double xe[NEN][NF];
+                elem_nodes(nx, ny, i, j, k, nodes);
+                gather(x, nodes, xe);
+                elem_jacobian(&c, xe, alpha_of(&c, gamma[e]), K_of(&c, gamma[e]), s[e],
+                              forcing ? forcing + 32 * e : NULL,
+                              (double(*)[NED])(Ke_out + (int64_t)e * NED * NED));
+            }
+    return 0;
+}
+
+/* Single-element entry points for the closed-form tests. */
+int or_element_residual(double h, const double *phys, const double *xe, double gam, double s,
+                        double *Re)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    elem_residual(&c, (const double(*)[NF])xe, alpha_of(&c, gam), K_of(&c, gam), s, NULL,
+                  (double(*)[NF])Re);
+    return 0;
+}
+
+int or_element_dRdgamma(double h, const double *phys, const double *xe, double gam, double s,
+                        double *dRe)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    elem_dRdgamma(&c, (const double(*)[NF])xe, gam, s, (double(*)[NF])dRe);
+    return 0;
+}
+
+int or_material(const double *phys, int n, const double *gamma, double *alpha, double *K,
+                double *dalpha, double *dK)
+{
+    ctx_t c;
+    ctx_init(&c, 1.0, phys);
+    for (int i = 0; i < n; ++i) {
+        alpha[i] = alpha_of(&c, gamma[i]);
+        K[i] = K_of(&c, gamma[i]);
+        dalpha[i] = dalpha_of(&c, gamma[i]);
+        dK[i] = dK_of(&c, gamma[i]);
+    }
+    return 0;
+}
+
+int or_taus(double h, const double *phys, double U2, double alpha, double K, double *out)
+{
+    ctx_t c;
+    ctx_init(&c, h, phys);
+    taus(&c, U2, alpha, K, &out[0], &out[1]);
+    return 0;
+}
+
+/* Gauss point coordinates of every element, [n_el][8][3], for the
+ * manufactured-solution forcing. */
+int or_gauss_points(int nx, int ny, int nz, double h, double *xg)
+{
+    ctx_t c;
+    double phys[9] = {1, 0, 1, 0, 0, 0, 0, 0, -1};
+    ctx_init(&c, h, phys);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int64_t e = i + (int64_t)nx * (j + (int64_t)ny * k);
+                for (int g = 0; g < 8; ++g) {
+                    xg[24 * e + 3 * g + 0] = i * h + c.xg[g][0];
+                    xg[24 * e + 3 * g + 1] = j * h + c.xg[g][1];
+                    xg[24 * e + 3 * g + 2] = k * h + c.xg[g][2];
+                }
+            }
+    return 0;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
