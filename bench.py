@@ -1,0 +1,192 @@
+"""Benchmark of the matrix-free Newton-Krylov state solve on one MI355X.
+
+Workload: 64x64x64 trilinear hex elements (1,373,125 DOF), Gr = 1e4, Pr = 1,
+k_s/k_f = 10, alpha_max = 1e4, q = 1, design from a seeded smoothed Gaussian
+random field thresholded to 40 % solid, heat source in the central quarter,
+walls no-slip and T = 0, pressure pinned at node 0.
+
+One step = the whole hot path on that input:
+  residual, Newton solve to 1e-8 in FP64 (FP64 Krylov operator), J v products
+  at the converged state in FP64 and in FP32, Newton solve to 1e-8 in mixed
+  precision (FP32 Krylov operator and preconditioner, FP64 refinement).
+
+Prints one JSON line.  ``value`` is the FP64 J v throughput in GDOF/s; the solve
+times, the FP32 rate and the mixed-vs-FP64 error ride along.  ``roofline``
+describes the FP64 element kernel of J v, timed with HIP events on the stream
+it runs on; ``cpu_baseline`` times the CPU oracle's J v on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Floating-point work of one FP64 element J v evaluation (modal 2x2x2 Gauss
+# pass, see the kernel design notes), counted from the kernel's instruction
+# stream: FMA = 2 flops, add/mul = 1.
+FLOPS_PER_ELEM_JV = float(os.environ.get("FE_FLOPS_PER_ELEM_JV", "0")) or None
+PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
+# Algorithmic HBM bytes of one FP64 J v: x, v read and J v written (5 values per
+# node each), gamma and s read (one value per element each).
+def jv_bytes(n_nodes, n_el, word=8):
+    return 15 * word * n_nodes + 16 * n_el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--jv-reps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "domain decomposition is a design, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1508_04596_amd import fe, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = inputs.config(2)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    g = torch.from_numpy(p.gamma).to(dev)
+    s = torch.from_numpy(p.s).to(dev)
+    n_dof, n_el, n_nodes = p.n_dof, p.n_el, p.n_nodes
+    vdir = torch.from_numpy(inputs.random_direction(p, 1, mask=p.mask_solve)).to(dev)
+    out64 = torch.empty(n_dof, dtype=torch.float64, device=dev)
+    out32 = torch.empty(n_dof, dtype=torch.float32, device=dev)
+    r = torch.empty(n_dof, dtype=torch.float64, device=dev)
+    opts64 = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="fp64", verbose=1 if args.verbose else 0)
+    optsmx = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed", verbose=1 if args.verbose else 0)
+    stream = torch.cuda.current_stream()
+
+    def step(rec):
+        x64 = torch.zeros(n_dof, dtype=torch.float64, device=dev)
+        fe.fe_residual(prob, x64, g, s, r)
+        t0 = time.perf_counter()
+        rep64 = fe.newton_solve(prob, g, s, x64, opts64)
+        t_solve64 = time.perf_counter() - t0
+        # J v at the converged state, FP64 then FP32
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        x32 = x64.float()
+        v32 = vdir.float()
+        e0.record(stream)
+        for _ in range(args.jv_reps):
+            fe.fe_jvp(prob, x64, g, s, vdir, out64)
+        e1.record(stream)
+        for _ in range(args.jv_reps):
+            fe.fe_jvp(prob, x32, g, s, v32, out32)
+        e2.record(stream)
+        xm = torch.zeros(n_dof, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        repmx = fe.newton_solve(prob, g, s, xm, optsmx)
+        t_solvemx = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        rec.update(t_jv64=e0.elapsed_time(e1) * 1e-3 / args.jv_reps,
+                   t_jv32=e1.elapsed_time(e2) * 1e-3 / args.jv_reps,
+                   t_solve64=t_solve64, t_solvemx=t_solvemx, rep64=rep64, repmx=repmx,
+                   mixed_vs_fp64=float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)),
+                   jv32_vs_jv64=float(torch.linalg.norm(out32.double() - out64) /
+                                      torch.linalg.norm(out64)))
+        # backward error of the mixed solution measured with the FP64 residual
+        fe.fe_residual(prob, xm, g, s, r)
+        rec["mixed_res_rel"] = float(torch.linalg.norm(r)) / rep64["res0"]
+
+    rec = {}
+    for _ in range(args.warmup):
+        step(rec)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rr = {}
+        step(rr)
+        recs.append(rr)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    t_jv64 = float(np.median([q["t_jv64"] for q in recs]))
+    t_jv32 = float(np.median([q["t_jv32"] for q in recs]))
+    last = recs[-1]
+    value = n_dof / t_jv64 / 1e9
+
+    roof = None
+    bytes_alg = jv_bytes(n_nodes, n_el)
+    if FLOPS_PER_ELEM_JV:
+        achieved = FLOPS_PER_ELEM_JV * n_el / t_jv64
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                "kernel": "fe_jvp FP64 (element pass + shared-node pass)",
+                "flops_per_elem": FLOPS_PER_ELEM_JV,
+                "hbm_alg_GBps": bytes_alg / t_jv64 / 1e9,
+                "hbm_alg_frac": bytes_alg / t_jv64 / PEAK_HBM}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_alg / t_jv64 / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": bytes_alg / t_jv64 / PEAK_HBM, "traffic": None,
+                "kernel": "fe_jvp FP64 (element pass + shared-node pass)"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, args.cpu_seconds)
+
+    line = {
+        "metric": "Jv GDOF/s + Newton solve time to 1e-8 (FP64 vs mixed); p50/p99 serve latency",
+        "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid "
+                               "smoothed random design; 1000 Jv FP64 + 1000 Jv FP32 at x*, "
+                               "Newton to 1e-8 FP64 and mixed",
+                   "jv_reps": args.jv_reps},
+        "jv_fp64_ms": t_jv64 * 1e3, "jv_fp32_ms": t_jv32 * 1e3,
+        "jv_fp32_gdofs": n_dof / t_jv32 / 1e9,
+        "solve_fp64_s": last["t_solve64"], "solve_mixed_s": last["t_solvemx"],
+        "newton_its_fp64": last["rep64"]["newton_its"], "krylov_its_fp64": last["rep64"]["lin_its"],
+        "newton_its_mixed": last["repmx"]["newton_its"], "krylov_its_mixed": last["repmx"]["lin_its"],
+        "solve_fp64_phase_s": {k: last["rep64"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
+        "solve_mixed_phase_s": {k: last["repmx"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
+        "mixed_vs_fp64_rel": last["mixed_vs_fp64"], "mixed_res_rel": last["mixed_res_rel"],
+        "jv32_vs_jv64_rel": last["jv32_vs_jv64"],
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    prob.close()
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(p, seconds):
+    """The oracle's FP64 J v on this host's cores, repeated for about ``seconds``."""
+    import oracle
+    from paper_1508_04596_amd import inputs
+    x = inputs.random_state(p, 2001, mask=p.mask_solve)
+    v = inputs.random_direction(p, 1, mask=p.mask_solve)
+    oracle.jvp(p, x, v, mask="solve")  # warm
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.jvp(p, x, v, mask="solve")
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": p.n_dof * n / el / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} FP64 J v products of the CPU oracle on the same 64^3 problem "
+                      f"({el:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

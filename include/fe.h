@@ -1,0 +1,203 @@
+/*
+ * fe.h -- C-ABI of the MI355X (gfx950) matrix-free Newton-Krylov state solver
+ * for density-based topology optimisation of heat sinks cooled by natural
+ * convection (Alexandersen, Sigmund & Aage, arXiv:1508.04596).
+ *
+ * The library evaluates, on one GPU, the residual of the stabilised weak form of
+ * the composite steady Navier-Stokes-Brinkman / Boussinesq / convection-diffusion
+ * equations (Sec. "Governing equations", Eqs. BoussDimless-a..c), discretised
+ * with trilinear equal-order hexahedra on a structured grid with element-
+ * constant design (Sec. "Finite element formulation"), SUPG/PSPG stabilised with
+ * the element parameter tau of Appendix "Stabilisation parameters"; its
+ * consistent Jacobian-vector product (including the variation of tau), the
+ * transposed product and the design derivative for adjoint sensitivities; the
+ * damped Newton / flexible GMRES state solve of Sec. "Numerical implementation";
+ * and a continuous-batching solve server.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid:    nx*ny*nz cubic elements of edge h.  Element e = i + nx*(j + ny*k);
+ *          node n = i + (nx+1)*(j + (ny+1)*k).  All of nx, ny, nz >= 1.
+ * State:   node-major interleaved, x[5*n + f] with f = 0..4 = (u, v, w, p, T).
+ *          n_dof = 5*(nx+1)*(ny+1)*(nz+1).
+ * Design:  gamma[e] (1 = fluid, 0 = solid), s_elem[e] heat source, FP64.
+ * Mask:    dof_mask[5*n + f] = 1 marks a prescribed DOF whose value in x is the
+ *          Dirichlet value.  Prescribed rows are eliminated symmetrically:
+ *          R_d = 0, (J v)_d = v_d, (J^T w)_d = w_d, and directions are gathered
+ *          with their prescribed entries set to 0 (J = [[J_ff, 0], [0, I]]).
+ * Memory:  every array argument of fe_* / newton_solve is a DEVICE pointer owned
+ *          by the caller; the library reads or writes it during the call (in
+ *          stream order) and never keeps or frees it.  Outputs are overwritten,
+ *          never accumulated.  Inputs are not modified.  The problem handle owns
+ *          its workspace, released by fe_problem_destroy.
+ * Streams: calls are ordered on the given stream (0 = the null stream).
+ *          newton_solve and fe_adjoint_solve make host decisions and therefore
+ *          synchronise that stream before they return.
+ * Errors:  0 = FE_OK; > 0 non-fatal states; < 0 errors.  No exception crosses
+ *          the ABI; fe_last_error() returns a thread-local message for the last
+ *          failing call on the calling thread.
+ * Threads: a problem handle must not be used by two threads at once.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FE_OK = 0,
+    FE_PENDING = 1,        /* serve_poll: request not finished yet */
+    FE_NOT_CONVERGED = 2,  /* solver stopped at its iteration limit; report filled */
+    FE_EINVAL = -1,        /* bad argument: null pointer, bad size, unknown ticket */
+    FE_ENOMEM = -2,        /* device or host allocation failed */
+    FE_EHIP = -3,          /* a HIP runtime call failed */
+    FE_ENAN = -4,          /* NaN or Inf met in a residual or Krylov norm */
+    FE_ESTATE = -5         /* handle in a state that does not allow the call */
+};
+
+typedef struct { int32_t nx, ny, nz; double h; } fe_grid;
+
+/* Dimensionless parameters (Sec. "Governing equations" and Eqs. conducint,
+ * alphaint): Prandtl and Grashof numbers, conductivity ratio C_k = k_f/k_s,
+ * conductivity convexity q_f, maximum impermeability alpha_bar and its convexity
+ * q_alpha, unit gravity direction e^g.  The buoyancy coefficient is Gr*Pr^2. */
+typedef struct { double Pr, Gr, Ck, qf, alpha_max, q_alpha; double eg[3]; } fe_phys;
+
+typedef enum { FE_FP64 = 0, FE_FP32 = 1 } fe_prec;
+
+typedef struct fe_problem fe_problem;
+
+/* Create a problem on the current device.  dof_mask: device uint8[n_dof] as
+ * above, copied into the handle (NULL: nothing prescribed).  Returns FE_EINVAL
+ * for non-positive sizes or h <= 0, FE_ENOMEM / FE_EHIP on device failures. */
+int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
+                      fe_problem **out);
+int fe_problem_destroy(fe_problem *p);
+/* Replace the physical parameters of an existing handle (e.g. Gr continuation). */
+int fe_problem_set_phys(fe_problem *p, const fe_phys *phys);
+int64_t fe_problem_ndof(const fe_problem *p);
+
+/* R(x; gamma, s): residual of the stabilised weak form, prescribed rows 0.
+ * x: FP64[n_dof]; gamma, s_elem: FP64[n_el]; r: FP64[n_dof]. */
+int fe_residual(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                double *r, hipStream_t stream);
+
+/* jv = J(x) v: the exact directional derivative of R (consistent Jacobian,
+ * Sec. "Finite element formulation": the variation of tau with the element
+ * velocity vector, Appendix "Stabilisation parameters", is included).
+ * prec = FE_FP64: x, v, jv are double*.  prec = FE_FP32: x, v, jv are float*;
+ * arithmetic and accumulation in FP32 (gamma and s_elem stay FP64 inputs). */
+int fe_jvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma, const double *s_elem,
+           const void *v, void *jv, hipStream_t stream);
+
+/* jtw = J(x)^T w, the exact transpose of fe_jvp's operator, evaluated element by
+ * element in reverse mode with every element quantity recomputed from x. */
+int fe_adjoint_jtvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma,
+                    const double *s_elem, const void *w, void *jtw, hipStream_t stream);
+
+/* g_elem[e] = lambda^T dR/dgamma_e (FP64[n_el]); the material interpolation of
+ * Eqs. conducint / alphaint and the design derivative of tau enter through
+ * alpha'(gamma_e) and K'(gamma_e).  Prescribed entries of lambda are ignored. */
+int fe_dR_dgamma(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                 const double *lambda, double *g_elem, hipStream_t stream);
+
+/* Thermal compliance f = integral over the source of s*T (Sec. "Optimisation
+ * problem"), evaluated exactly for trilinear T: f = sum_e s_e h^3/8 sum_a T_a.
+ * f_host: host double (may be NULL); dfdx: device FP64[n_dof] or NULL, receives
+ * df/dx with prescribed entries 0.  Synchronises the stream when f_host != NULL. */
+int fe_compliance(fe_problem *p, const double *x, const double *s_elem, double *f_host,
+                  double *dfdx, hipStream_t stream);
+
+typedef struct {
+    double rtol_newton;     /* stop when |R|_2 <= rtol_newton |R(x0)|_2 (default 1e-8) */
+    double rtol_lin;        /* FGMRES relative tolerance per Newton step (default 1e-5) */
+    int max_newton;         /* default 50 */
+    int restart;            /* FGMRES restart length m, 1..64 (default 30) */
+    int max_lin;            /* Krylov iterations per linear solve (default 3000) */
+    int n_refine;           /* mixed mode: iterative-refinement sweeps (default 3) */
+    fe_prec krylov_op_prec; /* FE_FP64, or FE_FP32 for FP32 J v and preconditioner */
+    double ls_lambda_min;   /* lower clamp of the line-search factor (default 0.05) */
+    int verbose;            /* 0 silent, 1 one line per Newton step on stderr */
+} fe_solve_opts;
+
+typedef struct {
+    int newton_its, lin_its_total, status;  /* status: FE_OK / FE_NOT_CONVERGED / error */
+    double res0, res_final, lambda_last;
+    double t_total_s;                       /* wall time of the call */
+    double t_jv_s, t_prec_s, t_orth_s, t_res_s, t_setup_s; /* stream time per phase */
+    int lin_its[64];                        /* Krylov iterations of the first 64 Newton steps */
+    double res_hist[65];                    /* |R| after each Newton step, [0] = |R(x0)| */
+} fe_solve_report;
+
+/* Fill opts with the defaults listed above. */
+void fe_solve_opts_default(fe_solve_opts *opts);
+
+/* Damped Newton (Sec. "Solving the non-linear system"): each step solves
+ * J delta = -R with right-preconditioned flexible GMRES (Sec. "Solving the
+ * linear systems") using a nodal 5x5 block-Jacobi preconditioner, Gram-Schmidt,
+ * Hessenberg and Givens in FP64; then the damping factor is the minimiser of a
+ * quadratic fitted to |R|^2 at 0, 1/2 and 1 times the step.  x_inout: device
+ * FP64[n_dof], the initial vector on entry (its prescribed entries hold the
+ * Dirichlet values), the solution on exit.  With krylov_op_prec = FE_FP32 the
+ * Krylov operator and preconditioner run in FP32 and the linear residual is
+ * refined with FP64 J v.  Returns FE_OK, FE_NOT_CONVERGED (x_inout holds the
+ * last iterate) or an error; report may be NULL. */
+int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, double *x_inout,
+                 const fe_solve_opts *opts, fe_solve_report *report, hipStream_t stream);
+
+/* Adjoint solve J(x)^T lambda = rhs with FGMRES on fe_adjoint_jtvp's operator
+ * and the transposed block-Jacobi preconditioner; rtol_lin of opts applies.
+ * All arrays device FP64. */
+int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                     const double *rhs, double *lambda, const fe_solve_opts *opts,
+                     fe_solve_report *report, hipStream_t stream);
+
+/* Nodal 5x5 diagonal blocks of J(x) (the block-Jacobi preconditioner of the
+ * linear solves before inversion): D[25*n + 5*f + g] = dR_{n,f}/dx_{n,g}, with
+ * the identity in place of prescribed rows and columns.  D: device FP64[25*n_nodes]. */
+int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                      double *D, hipStream_t stream);
+
+/* Damping factor of the quadratic line search for scripted residual norms
+ * phi(l) = |R(x + l delta)|^2 at l = 0, 1/2, 1 (host-only helper). */
+double fe_line_search_lambda(double phi0, double phi_half, double phi1, double lambda_min);
+
+/* Device bytes newton_solve allocates for a grid (for memory admission). */
+int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts);
+
+/* ---- continuous-batching server ------------------------------------------
+ * Requests (grid, parameters, design, source, options) are copied in at
+ * submit and queued.  A scheduler thread admits queued requests in arrival
+ * order while the device memory they need fits in hbm_budget_bytes and fewer
+ * than max_active are running, keeps every admitted problem's state in device
+ * memory, and advances all of them together: each phase (residual, J v,
+ * preconditioner, orthogonalisation) is one batched launch over the table of
+ * active problems.  Finished requests retire and free their memory at once.
+ * Walls (u, v, w, T = 0 on every boundary node) and the pressure pin at node 0
+ * are applied to every request; the initial state is 0. */
+typedef struct fe_server fe_server;
+int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
+/* gamma_host, s_host: host FP64[n_el]; copied.  Returns at once with a ticket. */
+int serve_submit(fe_server *s, const fe_grid *grid, const fe_phys *phys, const double *gamma_host,
+                 const double *s_host, const fe_solve_opts *opts, uint64_t *ticket);
+/* FE_PENDING while queued or running; otherwise the request's final status
+ * (FE_OK, FE_NOT_CONVERGED or an error) with x_host_out (host FP64[n_dof], may
+ * be NULL) and report filled.  A finished ticket can be polled again. */
+int serve_poll(fe_server *s, uint64_t ticket, double *x_host_out, fe_solve_report *report);
+/* Timestamps (seconds, server clock) of submit, admit and completion. */
+int serve_times(fe_server *s, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+int serve_destroy(fe_server *s);
+
+const char *fe_last_error(void);
+const char *fe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_H */

@@ -1,0 +1,273 @@
+// C-ABI entry points: problem handle, operators, objective.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string("HIP error ") + hipGetErrorString(e) + " in " + what);
+    return e == hipErrorOutOfMemory ? FE_ENOMEM : FE_EHIP;
+}
+
+Geo make_geo(const fe_grid &g, const fe_phys &ph)
+{
+    Geo o;
+    o.nx = g.nx;
+    o.ny = g.ny;
+    o.nz = g.nz;
+    o.ntx = (g.nx + TX - 1) / TX;
+    o.nty = (g.ny + TY - 1) / TY;
+    o.ntz = (g.nz + TZ - 1) / TZ;
+    o.h = g.h;
+    o.Pr = ph.Pr;
+    o.B = ph.Gr * ph.Pr * ph.Pr;
+    for (int d = 0; d < 3; ++d) o.eg[d] = ph.eg[d];
+    o.Ck = ph.Ck;
+    o.qf = ph.qf;
+    o.amax = ph.alpha_max;
+    o.qa = ph.q_alpha;
+    return o;
+}
+
+static int check_grid(const fe_grid *g)
+{
+    if (!g) {
+        set_error("grid is NULL");
+        return FE_EINVAL;
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->h > 0.0) || !std::isfinite(g->h)) {
+        set_error("grid sizes must be >= 1 and h > 0");
+        return FE_EINVAL;
+    }
+    const int64_t nn = (int64_t)(g->nx + 1) * (g->ny + 1) * (g->nz + 1);
+    if (nn > (int64_t)1 << 31) {
+        set_error("grid too large: node count exceeds 2^31");
+        return FE_EINVAL;
+    }
+    return FE_OK;
+}
+
+static int check_phys(const fe_phys *ph)
+{
+    if (!ph) {
+        set_error("phys is NULL");
+        return FE_EINVAL;
+    }
+    if (!(ph->Ck > 0.0) || !std::isfinite(ph->Pr) || !std::isfinite(ph->Gr) ||
+        !std::isfinite(ph->alpha_max)) {
+        set_error("phys: Ck must be > 0 and Pr, Gr, alpha_max finite");
+        return FE_EINVAL;
+    }
+    return FE_OK;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+const char *fe_version(void) { return "fe-hip 1.0 (gfx950)"; }
+
+int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
+                      fe_problem **out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return FE_EINVAL;
+    }
+    *out = nullptr;
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    rc = check_phys(phys);
+    if (rc) return rc;
+    fe_problem *p = new (std::nothrow) fe_problem();
+    if (!p) return FE_ENOMEM;
+    p->grid = *grid;
+    p->phys = *phys;
+    p->geo = make_geo(*grid, *phys);
+    p->nn = n_nodes(p->geo);
+    p->ne = n_elem(p->geo);
+    p->ndof = NF * p->nn;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t slot_bytes = (size_t)n_tiles(p->geo) * BOXN * NF * sizeof(double);
+    if ((e = hipMalloc(&p->nmask, p->nn)) != hipSuccess ||
+        (e = hipMalloc(&p->dof_mask, p->ndof)) != hipSuccess ||
+        (e = hipMalloc(&p->slots, slot_bytes)) != hipSuccess ||
+        (e = hipMalloc(&p->partial, sizeof(double) * 66 * RED_BLOCKS)) != hipSuccess ||
+        (e = hipMalloc(&p->scal, sizeof(double) * 256)) != hipSuccess) {
+        fe_problem_destroy(p);
+        return hip_fail(e, "hipMalloc (problem)");
+    }
+    if (dof_mask)
+        e = hipMemcpy(p->dof_mask, dof_mask, p->ndof, hipMemcpyDeviceToDevice);
+    else
+        e = hipMemset(p->dof_mask, 0, p->ndof);
+    if (e == hipSuccess) e = launch_node_mask(p->dof_mask, p->nmask, p->nn, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fe_problem_destroy(p);
+        return hip_fail(e, "fe_problem_create mask setup");
+    }
+    *out = p;
+    return FE_OK;
+}
+
+void fe_free_solver_ws(fe_problem *p);  // fe_solver.cpp
+
+int fe_problem_destroy(fe_problem *p)
+{
+    if (!p) return FE_OK;
+    fe_free_solver_ws(p);
+    (void)hipFree(p->nmask);
+    (void)hipFree(p->dof_mask);
+    (void)hipFree(p->slots);
+    (void)hipFree(p->slots25);
+    (void)hipFree(p->partial);
+    (void)hipFree(p->scal);
+    delete p;
+    return FE_OK;
+}
+
+int fe_problem_set_phys(fe_problem *p, const fe_phys *phys)
+{
+    if (!p) {
+        set_error("problem is NULL");
+        return FE_EINVAL;
+    }
+    int rc = check_phys(phys);
+    if (rc) return rc;
+    p->phys = *phys;
+    p->geo = make_geo(p->grid, *phys);
+    return FE_OK;
+}
+
+int64_t fe_problem_ndof(const fe_problem *p) { return p ? p->ndof : -1; }
+
+int fe_residual(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                double *r, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !r) {
+        set_error("fe_residual: NULL argument");
+        return FE_EINVAL;
+    }
+    FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, x, (const double *)nullptr, gamma,
+                                              s_elem, p->nmask, r, p->slots, stream)));
+    return FE_OK;
+}
+
+int fe_jvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma, const double *s_elem,
+           const void *v, void *jv, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !v || !jv) {
+        set_error("fe_jvp: NULL argument");
+        return FE_EINVAL;
+    }
+    if (prec == FE_FP64) {
+        FE_CHECK_HIP((launch_elem<double, double>(OP_JV, p->geo, (const double *)x,
+                                                  (const double *)v, gamma, s_elem, p->nmask,
+                                                  (double *)jv, p->slots, stream)));
+    } else if (prec == FE_FP32) {
+        FE_CHECK_HIP((launch_elem<float, float>(OP_JV, p->geo, (const float *)x, (const float *)v,
+                                                gamma, s_elem, p->nmask, (float *)jv,
+                                                (float *)p->slots, stream)));
+    } else {
+        set_error("fe_jvp: unknown precision");
+        return FE_EINVAL;
+    }
+    return FE_OK;
+}
+
+int fe_adjoint_jtvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma,
+                    const double *s_elem, const void *w, void *jtw, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !w || !jtw) {
+        set_error("fe_adjoint_jtvp: NULL argument");
+        return FE_EINVAL;
+    }
+    if (prec == FE_FP64) {
+        FE_CHECK_HIP((launch_elem<double, double>(OP_JTV, p->geo, (const double *)x,
+                                                  (const double *)w, gamma, s_elem, p->nmask,
+                                                  (double *)jtw, p->slots, stream)));
+    } else if (prec == FE_FP32) {
+        FE_CHECK_HIP((launch_elem<float, float>(OP_JTV, p->geo, (const float *)x, (const float *)w,
+                                                gamma, s_elem, p->nmask, (float *)jtw,
+                                                (float *)p->slots, stream)));
+    } else {
+        set_error("fe_adjoint_jtvp: unknown precision");
+        return FE_EINVAL;
+    }
+    return FE_OK;
+}
+
+int fe_dR_dgamma(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                 const double *lambda, double *g_elem, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !lambda || !g_elem) {
+        set_error("fe_dR_dgamma: NULL argument");
+        return FE_EINVAL;
+    }
+    FE_CHECK_HIP(launch_dRdgamma(p->geo, x, lambda, gamma, s_elem, p->nmask, g_elem, stream));
+    return FE_OK;
+}
+
+int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                      double *D, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !D) {
+        set_error("fe_block_diagonal: NULL argument");
+        return FE_EINVAL;
+    }
+    if (!p->slots25) {
+        const size_t b = (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double);
+        FE_CHECK_HIP(hipMalloc(&p->slots25, b));
+    }
+    FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, D, p->slots25, stream));
+    return FE_OK;
+}
+
+int fe_compliance(fe_problem *p, const double *x, const double *s_elem, double *f_host,
+                  double *dfdx, hipStream_t stream)
+{
+    if (!p || !x || !s_elem) {
+        set_error("fe_compliance: NULL argument");
+        return FE_EINVAL;
+    }
+    FE_CHECK_HIP(launch_compliance(p->geo, x, s_elem, p->nmask, dfdx, p->partial, stream));
+    if (f_host) {
+        FE_CHECK_HIP(launch_reduce(p->partial, 1, p->scal, nullptr, false, stream));
+        FE_CHECK_HIP(hipMemcpyAsync(f_host, p->scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+        FE_CHECK_HIP(hipStreamSynchronize(stream));
+    }
+    return FE_OK;
+}
+
+double fe_line_search_lambda(double phi0, double phi_half, double phi1, double lambda_min)
+{
+    // quadratic q(l) = phi0 + c1 l + c2 l^2 through l = 0, 1/2, 1
+    const double c2 = 2.0 * (phi1 - 2.0 * phi_half + phi0);
+    const double c1 = phi1 - phi0 - c2;
+    if (c2 > 0.0) {
+        double l = -c1 / (2.0 * c2);
+        if (l > 1.0) l = 1.0;
+        if (l < lambda_min) l = lambda_min;
+        return l;
+    }
+    return (phi_half < phi1) ? 0.5 : 1.0;
+}
+
+}  // extern "C"

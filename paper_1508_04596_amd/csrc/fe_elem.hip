@@ -1,0 +1,949 @@
+// Element kernels of the stabilised natural-convection operator on gfx950.
+//
+// One workgroup (256 threads, 4 wave64) owns a tile of 8x8x4 elements, one
+// element per thread.  The tile's 9x9x5 node box of the state (and of the
+// direction) is staged in LDS with coalesced loads, field-major so that the
+// per-thread gathers of the element corners are bank-conflict free.  Each
+// thread evaluates its element with the 2x2x2 Gauss rule in registers: nodal
+// values are turned into the tensor-product modal basis {1, xi, eta, zeta, ...}
+// by a three-pass butterfly, so the value and the three derivatives at a Gauss
+// point are signed sums of eight modal coefficients; the test-function side is
+// accumulated in the same modal basis and turned back into nodal rows by the
+// inverse butterfly.  Element rows are summed into an LDS node accumulator in
+// eight ordered sub-steps (one per element corner, so no two threads touch the
+// same node within a sub-step).  Nodes whose elements all lie in the tile are
+// written directly; nodes on faces shared with neighbouring tiles write their
+// partial sums to per-tile slots that a second kernel adds in a fixed tile
+// order.  No atomics: results are bitwise reproducible and independent of the
+// launch order.
+//
+// Weak form, stabilisation and linearisation: Sec. "Finite element formulation"
+// and Appendix "Stabilisation parameters" (tau from the convective, viscous and
+// Brinkman limits; its variation with the element velocity vector enters the
+// consistent Jacobian).  The viscous second derivative is left out of the
+// strong residual used by SUPG/PSPG.
+#include "fe_internal.h"
+
+namespace fe {
+namespace {
+
+constexpr double QG = 0.57735026918962576451;  // Gauss abscissa 1/sqrt(3)
+
+template <typename T>
+struct EC {
+    T W;        // (h/2)^3, Gauss weight times Jacobian determinant
+    T gs;       // 2/(h*q): physical derivative of a modal sum at a Gauss point
+    T Pr, B, eg0, eg1, eg2;
+    T inv16h2;  // 1/(16 h^2): |u_e|^2/(16 h^2) is 1/tau_1^2
+    T cvisc;    // 16 Pr^2 / h^4 = 1/tau_2^2
+    T c16h4;    // 16 / h^4: K^2 * c16h4 = 1/tau_2T^2
+    T q0, q1, q2, q3;  // q^|m| / 8 for the modal scaling
+};
+
+template <typename T>
+__device__ __forceinline__ EC<T> make_ec(const Geo &g)
+{
+    EC<T> c;
+    double h = g.h;
+    c.W = (T)(0.125 * h * h * h);
+    c.gs = (T)(2.0 / (h * QG));
+    c.Pr = (T)g.Pr;
+    c.B = (T)g.B;
+    c.eg0 = (T)g.eg[0];
+    c.eg1 = (T)g.eg[1];
+    c.eg2 = (T)g.eg[2];
+    c.inv16h2 = (T)(1.0 / (16.0 * h * h));
+    c.cvisc = (T)(16.0 * g.Pr * g.Pr / (h * h * h * h));
+    c.c16h4 = (T)(16.0 / (h * h * h * h));
+    c.q0 = (T)0.125;
+    c.q1 = (T)(0.125 * QG);
+    c.q2 = (T)(0.125 / 3.0);
+    c.q3 = (T)(0.125 * QG / 3.0);
+    return c;
+}
+
+// Material interpolation (Eqs. conducint, alphaint) and derivatives.
+__device__ __forceinline__ double alpha_of(const Geo &g, double y) { return g.amax * (1.0 - y) / (1.0 + g.qa * y); }
+__device__ __forceinline__ double K_of(const Geo &g, double y)
+{
+    return (y * (g.Ck * (1.0 + g.qf) - 1.0) + 1.0) / (g.Ck * (1.0 + g.qf * y));
+}
+__device__ __forceinline__ double dalpha_of(const Geo &g, double y)
+{
+    double d = 1.0 + g.qa * y;
+    return -g.amax * (1.0 + g.qa) / (d * d);
+}
+__device__ __forceinline__ double dK_of(const Geo &g, double y)
+{
+    double d = 1.0 + g.qf * y;
+    return (1.0 + g.qf) * (g.Ck - 1.0) / (g.Ck * d * d);
+}
+
+__device__ __forceinline__ float rsqrt_t(float a) { return 1.0f / sqrtf(a); }
+__device__ __forceinline__ double rsqrt_t(double a) { return 1.0 / sqrt(a); }
+
+// nodal -> scaled modal coefficients: c[m] = q^|m|/8 * sum_a S[a][m] f[a],
+// S[a][m] = prod_d s_{a,d}^{m_d}, s = -1 / +1 at the low / high node.
+template <typename T>
+__device__ __forceinline__ void to_modal(T f[8], const EC<T> &c)
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int bit = 1 << d;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (!(a & bit)) {
+                T lo = f[a], hi = f[a | bit];
+                f[a] = lo + hi;
+                f[a | bit] = hi - lo;
+            }
+    }
+    f[0] *= c.q0;
+    f[1] *= c.q1; f[2] *= c.q1; f[4] *= c.q1;
+    f[3] *= c.q2; f[5] *= c.q2; f[6] *= c.q2;
+    f[7] *= c.q3;
+}
+
+// Value and physical gradient at Gauss point G (bits = +/- side per direction).
+template <int G, typename T>
+__device__ __forceinline__ void eval_vg(const T m[8], T gs, T &val, T &dx, T &dy, T &dz)
+{
+    constexpr T sx = (G & 1) ? T(1) : T(-1);
+    constexpr T sy = (G & 2) ? T(1) : T(-1);
+    constexpr T sz = (G & 4) ? T(1) : T(-1);
+    T t1 = sx * m[1], t2 = sy * m[2], t3 = (sx * sy) * m[3], t4 = sz * m[4];
+    T t5 = (sx * sz) * m[5], t6 = (sy * sz) * m[6], t7 = (sx * sy * sz) * m[7];
+    T ax = (t1 + t3) + (t5 + t7);
+    T ay = (t2 + t3) + (t6 + t7);
+    T az = (t4 + t5) + (t6 + t7);
+    val = ((m[0] + t2) + (t4 + t6)) + ax;
+    dx = (sx * gs) * ax;
+    dy = (sy * gs) * ay;
+    dz = (sz * gs) * az;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ void eval_g(const T m[8], T gs, T &dx, T &dy, T &dz)
+{
+    T v;
+    eval_vg<G>(m, gs, v, dx, dy, dz);
+}
+
+// Y[m] += S[G][m] * (c + gs * sum_{d in m} s_d C_d): the modal test-side sum.
+template <int G, typename T>
+__device__ __forceinline__ void accum(T Y[8], T c, T Cx, T Cy, T Cz, T gs)
+{
+    constexpr T sx = (G & 1) ? T(1) : T(-1);
+    constexpr T sy = (G & 2) ? T(1) : T(-1);
+    constexpr T sz = (G & 4) ? T(1) : T(-1);
+    T px = (sx * gs) * Cx, py = (sy * gs) * Cy, pz = (sz * gs) * Cz;
+    T e1 = c + px, e2 = c + py, e4 = c + pz;
+    T e3 = e1 + py, e5 = e1 + pz, e6 = e2 + pz, e7 = e3 + pz;
+    Y[0] += c;
+    Y[1] += sx * e1;
+    Y[2] += sy * e2;
+    Y[3] += (sx * sy) * e3;
+    Y[4] += sz * e4;
+    Y[5] += (sx * sz) * e5;
+    Y[6] += (sy * sz) * e6;
+    Y[7] += (sx * sy * sz) * e7;
+}
+
+// Modal test-side sums -> nodal rows: out_a = W sum_m S[a][m] q^|m|/8 Y[m].
+template <typename T>
+__device__ __forceinline__ void from_modal(T Y[8], const EC<T> &c)
+{
+    T w0 = c.W * c.q0, w1 = c.W * c.q1, w2 = c.W * c.q2, w3 = c.W * c.q3;
+    Y[0] *= w0;
+    Y[1] *= w1; Y[2] *= w1; Y[4] *= w1;
+    Y[3] *= w2; Y[5] *= w2; Y[6] *= w2;
+    Y[7] *= w3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int bit = 1 << d;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (!(a & bit)) {
+                T lo = Y[a], hi = Y[a | bit];
+                Y[a] = lo - hi;
+                Y[a | bit] = lo + hi;
+            }
+    }
+}
+
+// ---- tile staging -------------------------------------------------------------
+
+template <typename T>
+struct TileSmem {
+    T x[NF][BOXN];
+    T v[NF][BOXN];
+    T o[NF][BOXN];
+};
+
+struct TileIdx {
+    int btx, bty, btz, tile;
+    int li, lj, lk;      // this thread's element in the tile
+    int i, j, k;         // global element
+    bool valid;
+    int nb[8];           // node-box index of the element's corners
+};
+
+__device__ __forceinline__ TileIdx tile_index(const Geo &g)
+{
+    TileIdx t;
+    t.tile = blockIdx.x;
+    t.btx = t.tile % g.ntx;
+    int r = t.tile / g.ntx;
+    t.bty = r % g.nty;
+    t.btz = r / g.nty;
+    int th = threadIdx.x;
+    t.li = th % TX;
+    t.lj = (th / TX) % TY;
+    t.lk = th / (TX * TY);
+    t.i = t.btx * TX + t.li;
+    t.j = t.bty * TY + t.lj;
+    t.k = t.btz * TZ + t.lk;
+    t.valid = (t.i < g.nx) && (t.j < g.ny) && (t.k < g.nz);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+        t.nb[a] = (t.li + (a & 1)) + BX * ((t.lj + ((a >> 1) & 1)) + BY * (t.lk + ((a >> 2) & 1)));
+    return t;
+}
+
+__device__ __forceinline__ int64_t gnode(const Geo &g, int I, int J, int K)
+{
+    return (int64_t)I + (int64_t)(g.nx + 1) * ((int64_t)J + (int64_t)(g.ny + 1) * K);
+}
+
+// Stage the node box of x (and of the masked direction v) in LDS; zero the
+// output accumulator.
+template <typename T, int NVO>
+__device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
+                                      const T *__restrict__ v, const uint8_t *__restrict__ nmask,
+                                      T (*sx)[BOXN], T (*sv)[BOXN], T *so)
+{
+    const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
+    for (int idx = threadIdx.x; idx < BOXN * NF; idx += NTHR) {
+        int nb = idx / NF, f = idx - nb * NF;
+        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        T xv = T(0), vv = T(0);
+        if (I <= g.nx && J <= g.ny && K <= g.nz) {
+            int64_t gn = gnode(g, I, J, K);
+            xv = x[NF * gn + f];
+            if (v) {
+                vv = v[NF * gn + f];
+                if ((nmask[gn] >> f) & 1) vv = T(0);
+            }
+        }
+        sx[f][nb] = xv;
+        if (sv) sv[f][nb] = vv;
+    }
+    if (NVO > 0)
+        for (int idx = threadIdx.x; idx < BOXN * NVO; idx += NTHR) so[idx] = T(0);
+}
+
+// Is node coordinate I (local lx) shared with the neighbouring tile in that direction?
+__device__ __forceinline__ bool shared_dir(int l, int I, int n, int T_)
+{
+    return (l == 0 && I > 0) || (l == T_ && I < n);
+}
+
+// ---- element bodies -------------------------------------------------------------
+
+// Residual rows of one element (Galerkin + SUPG + PSPG, see header comment).
+template <typename T>
+__device__ __forceinline__ void elem_residual(const EC<T> &c, const T (*sx)[BOXN], const int nb[8],
+                                              T alpha, T Kc, T s, T out[NF][8])
+{
+    T mu[3][8], mp[8], mT[8];
+    T U2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T xa = sx[i][nb[a]];
+            U2 += xa * xa;
+            mu[i][a] = xa;
+        }
+        to_modal(mu[i], c);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        mp[a] = sx[3][nb[a]];
+        mT[a] = sx[4][nb[a]];
+    }
+    to_modal(mp, c);
+    to_modal(mT, c);
+    const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
+    const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) out[f][m] = T(0);
+    const T gs = c.gs;
+#define FE_RES_GP(G)                                                                         \
+    {                                                                                        \
+        T u[3], Gd[3][3];                                                                    \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
+            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+        T pv, gp0, gp1, gp2, Tv, gT0, gT1, gT2;                                              \
+        eval_vg<G>(mp, gs, pv, gp0, gp1, gp2);                                               \
+        eval_vg<G>(mT, gs, Tv, gT0, gT1, gT2);                                               \
+        T conv[3], rM[3];                                                                    \
+        const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
+        const T gpv[3] = {gp0, gp1, gp2};                                                    \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            conv[i] = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2];                   \
+            T gal = conv[i] + alpha * u[i] + c.B * egv[i] * Tv;                              \
+            rM[i] = gal + gpv[i];                                                            \
+            conv[i] = gal;                                                                   \
+        }                                                                                    \
+        T rT = u[0] * gT0 + u[1] * gT1 + u[2] * gT2 - s;                                     \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            T tr = tau * rM[i];                                                              \
+            T C0 = c.Pr * (Gd[i][0] + Gd[0][i]) + u[0] * tr;                                 \
+            T C1 = c.Pr * (Gd[i][1] + Gd[1][i]) + u[1] * tr;                                 \
+            T C2 = c.Pr * (Gd[i][2] + Gd[2][i]) + u[2] * tr;                                 \
+            if (i == 0) C0 -= pv;                                                            \
+            if (i == 1) C1 -= pv;                                                            \
+            if (i == 2) C2 -= pv;                                                            \
+            accum<G>(out[i], conv[i], C0, C1, C2, gs);                                       \
+        }                                                                                    \
+        accum<G>(out[3], Gd[0][0] + Gd[1][1] + Gd[2][2], tau * rM[0], tau * rM[1],           \
+                 tau * rM[2], gs);                                                           \
+        T trT = tauT * rT;                                                                   \
+        accum<G>(out[4], rT, Kc * gT0 + u[0] * trT, Kc * gT1 + u[1] * trT,                   \
+                 Kc * gT2 + u[2] * trT, gs);                                                 \
+    }
+    FE_RES_GP(0) FE_RES_GP(1) FE_RES_GP(2) FE_RES_GP(3)
+    FE_RES_GP(4) FE_RES_GP(5) FE_RES_GP(6) FE_RES_GP(7)
+#undef FE_RES_GP
+#pragma unroll
+    for (int f = 0; f < NF; ++f) from_modal(out[f], c);
+}
+
+// Directional derivative J_e v_e (exact linearisation, including d tau).
+template <typename T>
+__device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
+                                        const int nb[8], T alpha, T Kc, T s, T out[NF][8])
+{
+    T mu[3][8], md[3][8], mp[8], mT[8], mdp[8], mdT[8];
+    T U2 = T(0), udu = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T xa = sx[i][nb[a]], va = sv[i][nb[a]];
+            U2 += xa * xa;
+            udu += xa * va;
+            mu[i][a] = xa;
+            md[i][a] = va;
+        }
+        to_modal(mu[i], c);
+        to_modal(md[i], c);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        mp[a] = sx[3][nb[a]];
+        mT[a] = sx[4][nb[a]];
+        mdp[a] = sv[3][nb[a]];
+        mdT[a] = sv[4][nb[a]];
+    }
+    to_modal(mp, c);
+    to_modal(mT, c);
+    to_modal(mdp, c);
+    to_modal(mdT, c);
+    const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
+    const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
+    const T dtau = -(tau * tau * tau) * udu * c.inv16h2;
+    const T dtauT = -(tauT * tauT * tauT) * udu * c.inv16h2;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) out[f][m] = T(0);
+    const T gs = c.gs;
+#define FE_JV_GP(G)                                                                          \
+    {                                                                                        \
+        T u[3], Gd[3][3], du[3], dG[3][3];                                                   \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg<G>(md[i], gs, du[i], dG[i][0], dG[i][1], dG[i][2]);                      \
+        }                                                                                    \
+        T gp[3], Tv, gT[3], dpv, gdp[3], dTv, gdT[3];                                        \
+        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_vg<G>(mdp, gs, dpv, gdp[0], gdp[1], gdp[2]);                                    \
+        eval_vg<G>(mdT, gs, dTv, gdT[0], gdT[1], gdT[2]);                                    \
+        const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
+        T rM[3], dgal[3], A[3], Bm[3];                                                       \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            T conv = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2];                    \
+            T dconv = du[0] * Gd[i][0] + du[1] * Gd[i][1] + du[2] * Gd[i][2]                 \
+                    + u[0] * dG[i][0] + u[1] * dG[i][1] + u[2] * dG[i][2];                   \
+            rM[i] = conv + gp[i] + alpha * u[i] + c.B * egv[i] * Tv;                         \
+            dgal[i] = dconv + alpha * du[i] + c.B * egv[i] * dTv;                            \
+            T drM = dgal[i] + gdp[i];                                                        \
+            A[i] = dtau * rM[i] + tau * drM;                                                 \
+            Bm[i] = tau * rM[i];                                                             \
+        }                                                                                    \
+        T rT = u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2] - s;                               \
+        T drT = du[0] * gT[0] + du[1] * gT[1] + du[2] * gT[2]                                \
+              + u[0] * gdT[0] + u[1] * gdT[1] + u[2] * gdT[2];                               \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            T C0 = c.Pr * (dG[i][0] + dG[0][i]) + u[0] * A[i] + du[0] * Bm[i];               \
+            T C1 = c.Pr * (dG[i][1] + dG[1][i]) + u[1] * A[i] + du[1] * Bm[i];               \
+            T C2 = c.Pr * (dG[i][2] + dG[2][i]) + u[2] * A[i] + du[2] * Bm[i];               \
+            if (i == 0) C0 -= dpv;                                                           \
+            if (i == 1) C1 -= dpv;                                                           \
+            if (i == 2) C2 -= dpv;                                                           \
+            accum<G>(out[i], dgal[i], C0, C1, C2, gs);                                       \
+        }                                                                                    \
+        accum<G>(out[3], dG[0][0] + dG[1][1] + dG[2][2], A[0], A[1], A[2], gs);              \
+        T AT = dtauT * rT + tauT * drT, BT = tauT * rT;                                      \
+        accum<G>(out[4], drT, Kc * gdT[0] + u[0] * AT + du[0] * BT,                          \
+                 Kc * gdT[1] + u[1] * AT + du[1] * BT, Kc * gdT[2] + u[2] * AT + du[2] * BT, \
+                 gs);                                                                        \
+    }
+    FE_JV_GP(0) FE_JV_GP(1) FE_JV_GP(2) FE_JV_GP(3)
+    FE_JV_GP(4) FE_JV_GP(5) FE_JV_GP(6) FE_JV_GP(7)
+#undef FE_JV_GP
+#pragma unroll
+    for (int f = 0; f < NF; ++f) from_modal(out[f], c);
+}
+
+// Transposed product J_e^T w_e in one reverse pass with recomputed state:
+// adjoint test fields Lambda (velocity rows), Pi (pressure rows), Theta
+// (temperature rows) are interpolated from w_e; the multipliers of the varied
+// strong residuals are mu = tau (u.grad Lambda + grad Pi) and muT = tauT u.grad Theta;
+// the element-level tau variation is applied after the Gauss loop.
+template <typename T>
+__device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
+                                         const int nb[8], T alpha, T Kc, T s, T out[NF][8])
+{
+    T mu[3][8], mL[3][8], mp[8], mT[8], mP[8], mTh[8];
+    T U2 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T xa = sx[i][nb[a]];
+            U2 += xa * xa;
+            mu[i][a] = xa;
+            mL[i][a] = sv[i][nb[a]];
+        }
+        to_modal(mu[i], c);
+        to_modal(mL[i], c);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        mp[a] = sx[3][nb[a]];
+        mT[a] = sx[4][nb[a]];
+        mP[a] = sv[3][nb[a]];
+        mTh[a] = sv[4][nb[a]];
+    }
+    to_modal(mp, c);
+    to_modal(mT, c);
+    to_modal(mP, c);
+    to_modal(mTh, c);
+    const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
+    const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
+    T Aacc = T(0), ATacc = T(0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) out[f][m] = T(0);
+    const T gs = c.gs;
+#define FE_JTV_GP(G)                                                                         \
+    {                                                                                        \
+        T u[3], Gd[3][3], L[3], LG[3][3];                                                    \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg<G>(mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
+        }                                                                                    \
+        T gp[3], Tv, gT[3], Pv, gP[3], Th, gTh[3];                                           \
+        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_vg<G>(mP, gs, Pv, gP[0], gP[1], gP[2]);                                         \
+        eval_vg<G>(mTh, gs, Th, gTh[0], gTh[1], gTh[2]);                                     \
+        const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
+        T rM[3], uL[3], mI[3], LM[3];                                                        \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            rM[i] = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2] + gp[i]             \
+                  + alpha * u[i] + c.B * egv[i] * Tv;                                        \
+            uL[i] = u[0] * LG[i][0] + u[1] * LG[i][1] + u[2] * LG[i][2];                     \
+            T q = uL[i] + gP[i];                                                             \
+            mI[i] = tau * q;                                                                 \
+            Aacc += q * rM[i];                                                               \
+            LM[i] = L[i] + mI[i];                                                            \
+        }                                                                                    \
+        T rT = u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2] - s;                               \
+        T uTh = u[0] * gTh[0] + u[1] * gTh[1] + u[2] * gTh[2];                               \
+        ATacc += uTh * rT;                                                                   \
+        T ThM = Th + tauT * uTh;                                                             \
+        T trT = tauT * rT;                                                                   \
+        _Pragma("unroll") for (int j = 0; j < 3; ++j) {                                      \
+            T cj = LM[0] * Gd[0][j] + LM[1] * Gd[1][j] + LM[2] * Gd[2][j] + alpha * LM[j]    \
+                 + tau * (LG[0][j] * rM[0] + LG[1][j] * rM[1] + LG[2][j] * rM[2])            \
+                 + trT * gTh[j] + ThM * gT[j];                                               \
+            T C0 = LM[j] * u[0] + c.Pr * (LG[j][0] + LG[0][j]);                              \
+            T C1 = LM[j] * u[1] + c.Pr * (LG[j][1] + LG[1][j]);                              \
+            T C2 = LM[j] * u[2] + c.Pr * (LG[j][2] + LG[2][j]);                              \
+            if (j == 0) C0 += Pv;                                                            \
+            if (j == 1) C1 += Pv;                                                            \
+            if (j == 2) C2 += Pv;                                                            \
+            accum<G>(out[j], cj, C0, C1, C2, gs);                                            \
+        }                                                                                    \
+        accum<G>(out[3], -(LG[0][0] + LG[1][1] + LG[2][2]), mI[0], mI[1], mI[2], gs);        \
+        accum<G>(out[4], c.B * (egv[0] * LM[0] + egv[1] * LM[1] + egv[2] * LM[2]),           \
+                 Kc * gTh[0] + ThM * u[0], Kc * gTh[1] + ThM * u[1], Kc * gTh[2] + ThM * u[2], \
+                 gs);                                                                        \
+    }
+    FE_JTV_GP(0) FE_JTV_GP(1) FE_JTV_GP(2) FE_JTV_GP(3)
+    FE_JTV_GP(4) FE_JTV_GP(5) FE_JTV_GP(6) FE_JTV_GP(7)
+#undef FE_JTV_GP
+#pragma unroll
+    for (int f = 0; f < NF; ++f) from_modal(out[f], c);
+    // d tau / d u_e and d tauT / d u_e contributions: -(tau^3 A + tauT^3 A_T) u_e / (16 h^2)
+    const T coef = -(tau * tau * tau * Aacc + tauT * tauT * tauT * ATacc) * c.W * c.inv16h2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) out[i][a] += coef * sx[i][nb[a]];
+}
+
+// ---- tile kernel: element loop + ordered LDS accumulation + face slots ---------
+
+template <typename Tin, typename Tout, int OP>
+__global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
+                                               const Tin *__restrict__ v,
+                                               const double *__restrict__ gamma,
+                                               const double *__restrict__ src,
+                                               const uint8_t *__restrict__ nmask,
+                                               Tout *__restrict__ out, Tout *__restrict__ slots)
+{
+    using T = Tin;
+    __shared__ TileSmem<T> S;
+    const TileIdx t = tile_index(g);
+    stage<T, NF>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
+                 (OP == OP_RES) ? nullptr : S.v, &S.o[0][0]);
+    __syncthreads();
+
+    T R[NF][8];
+    if (t.valid) {
+        const EC<T> c = make_ec<T>(g);
+        const int64_t e = (int64_t)t.i + (int64_t)g.nx * ((int64_t)t.j + (int64_t)g.ny * t.k);
+        const double y = gamma[e];
+        const T alpha = (T)alpha_of(g, y), Kc = (T)K_of(g, y), s = (T)src[e];
+        if (OP == OP_RES)
+            elem_residual<T>(c, S.x, t.nb, alpha, Kc, s, R);
+        else if (OP == OP_JV)
+            elem_jv<T>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
+        else
+            elem_jtv<T>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
+    }
+    // ordered accumulation: in sub-step a every thread adds its corner-a row
+    // to a distinct node of the box
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        if (t.valid) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) S.o[f][t.nb[a]] += R[f][a];
+        }
+        __syncthreads();
+    }
+    // write-out: complete nodes to out, shared ones to the tile's slots
+    const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
+    for (int nb = threadIdx.x; nb < BOXN; nb += NTHR) {
+        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        if (I > g.nx || J > g.ny || K > g.nz) continue;
+        bool sh = shared_dir(lx, I, g.nx, TX) || shared_dir(ly, J, g.ny, TY) ||
+                  shared_dir(lz, K, g.nz, TZ);
+        if (sh) {
+            Tout *sl = slots + ((int64_t)t.tile * BOXN + nb) * NF;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) sl[f] = (Tout)S.o[f][nb];
+        } else {
+            int64_t gn = gnode(g, I, J, K);
+            uint8_t m = nmask[gn];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                Tout val = (Tout)S.o[f][nb];
+                if ((m >> f) & 1) val = (OP == OP_RES) ? Tout(0) : (Tout)v[NF * gn + f];
+                out[NF * gn + f] = val;
+            }
+        }
+    }
+}
+
+// Tiles containing node coordinate I along one direction, in increasing order.
+__device__ __forceinline__ int tiles_of(int I, int n, int T_, int nt, int tl[2], int ll[2])
+{
+    if (I % T_ == 0 && I > 0 && I < n) {
+        tl[0] = I / T_ - 1; ll[0] = T_;
+        tl[1] = I / T_;     ll[1] = 0;
+        return 2;
+    }
+    int t = I / T_;
+    if (t >= nt) t = nt - 1;
+    tl[0] = t; ll[0] = I - t * T_;
+    return 1;
+}
+
+// Sum the slot partials of nodes shared between tiles, in a fixed tile order.
+template <typename Tv, typename Tout, int NV, int OP>
+__global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__ slots,
+                                                 const uint8_t *__restrict__ nmask,
+                                                 const Tv *__restrict__ v, Tout *__restrict__ out)
+{
+    const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    const int64_t gn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gn >= nn) return;
+    const int I = (int)(gn % (g.nx + 1));
+    const int64_t r = gn / (g.nx + 1);
+    const int J = (int)(r % (g.ny + 1));
+    const int K = (int)(r / (g.ny + 1));
+    int tx[2], lx[2], ty[2], ly[2], tz[2], lz[2];
+    int cx = tiles_of(I, g.nx, TX, g.ntx, tx, lx);
+    int cy = tiles_of(J, g.ny, TY, g.nty, ty, ly);
+    int cz = tiles_of(K, g.nz, TZ, g.ntz, tz, lz);
+    if (cx == 1 && cy == 1 && cz == 1) return;  // written by its only tile
+    Tout acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = Tout(0);
+    for (int a = 0; a < cz; ++a)
+        for (int b = 0; b < cy; ++b)
+            for (int cc = 0; cc < cx; ++cc) {
+                int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[b] + (int64_t)g.nty * tz[a]);
+                int nb = lx[cc] + BX * (ly[b] + BY * lz[a]);
+                const Tout *sl = slots + (tile * BOXN + nb) * NV;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) acc[q] += sl[q];
+            }
+    const uint8_t m = nmask[gn];
+    if (NV == NF) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            Tout val = acc[f];
+            if ((m >> f) & 1) val = (OP == OP_RES) ? Tout(0) : (Tout)v[NF * gn + f];
+            out[NF * gn + f] = val;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int f2 = 0; f2 < NF; ++f2) {
+                Tout val = acc[f * NF + f2];
+                if (((m >> f) & 1) || ((m >> f2) & 1)) val = (f == f2) ? Tout(1) : Tout(0);
+                out[gn * 25 + f * NF + f2] = val;
+            }
+    }
+}
+
+// ---- design derivative: one output per element, no scatter ---------------------
+
+__global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restrict__ x,
+                                                   const double *__restrict__ lam,
+                                                   const double *__restrict__ gamma,
+                                                   const double *__restrict__ src,
+                                                   const uint8_t *__restrict__ nmask,
+                                                   double *__restrict__ gout)
+{
+    using T = double;
+    __shared__ T sx[NF][BOXN];
+    __shared__ T sl[NF][BOXN];
+    const TileIdx t = tile_index(g);
+    stage<T, 0>(g, t, x, lam, nmask, sx, sl, nullptr);
+    __syncthreads();
+    if (!t.valid) return;
+    const EC<T> c = make_ec<T>(g);
+    const int64_t e = (int64_t)t.i + (int64_t)g.nx * ((int64_t)t.j + (int64_t)g.ny * t.k);
+    const double y = gamma[e];
+    const T alpha = alpha_of(g, y), Kc = K_of(g, y), s = src[e];
+    const T da = dalpha_of(g, y), dK = dK_of(g, y);
+    T mu[3][8], mL[3][8], mp[8], mT[8], mP[8], mTh[8];
+    T U2 = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            T xa = sx[i][t.nb[a]];
+            U2 += xa * xa;
+            mu[i][a] = xa;
+            mL[i][a] = sl[i][t.nb[a]];
+        }
+        to_modal(mu[i], c);
+        to_modal(mL[i], c);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        mp[a] = sx[3][t.nb[a]];
+        mT[a] = sx[4][t.nb[a]];
+        mP[a] = sl[3][t.nb[a]];
+        mTh[a] = sl[4][t.nb[a]];
+    }
+    to_modal(mp, c);
+    to_modal(mT, c);
+    to_modal(mP, c);
+    to_modal(mTh, c);
+    const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
+    const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
+    const T dtau_da = -(tau * tau * tau) * alpha;                 // d tau / d alpha
+    const T dtauT_dK = -(tauT * tauT * tauT) * Kc * c.c16h4;      // d tauT / d K
+    T ga = 0, gk = 0;
+    const T gs = c.gs;
+#define FE_DG_GP(G)                                                                          \
+    {                                                                                        \
+        T u[3], Gd[3][3], L[3], LG[3][3];                                                    \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg<G>(mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
+        }                                                                                    \
+        T gp[3], Tv, gT[3], gP[3], gTh[3];                                                   \
+        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_g<G>(mP, gs, gP[0], gP[1], gP[2]);                                              \
+        eval_g<G>(mTh, gs, gTh[0], gTh[1], gTh[2]);                                          \
+        const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
+            T rM = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2] + gp[i]              \
+                 + alpha * u[i] + c.B * egv[i] * Tv;                                         \
+            T q = u[0] * LG[i][0] + u[1] * LG[i][1] + u[2] * LG[i][2] + gP[i];               \
+            ga += L[i] * u[i] + dtau_da * q * rM + tau * q * u[i];                           \
+        }                                                                                    \
+        T rT = u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2] - s;                               \
+        T uTh = u[0] * gTh[0] + u[1] * gTh[1] + u[2] * gTh[2];                               \
+        gk += gTh[0] * gT[0] + gTh[1] * gT[1] + gTh[2] * gT[2] + dtauT_dK * uTh * rT;        \
+    }
+    FE_DG_GP(0) FE_DG_GP(1) FE_DG_GP(2) FE_DG_GP(3)
+    FE_DG_GP(4) FE_DG_GP(5) FE_DG_GP(6) FE_DG_GP(7)
+#undef FE_DG_GP
+    gout[e] = c.W * (da * ga + dK * gk);
+}
+
+// ---- nodal 5x5 diagonal blocks of J -----------------------------------------------
+
+// Shape function of local node a and its physical gradient at Gauss point G.
+template <int G>
+__device__ __forceinline__ void shape_at(int a, double h, double &N, double dN[3])
+{
+    const double q = QG;
+    double f[3], sgn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double sg = ((G >> d) & 1) ? q : -q;
+        sgn[d] = ((a >> d) & 1) ? 1.0 : -1.0;
+        f[d] = 0.5 * (1.0 + sgn[d] * sg);
+    }
+    N = f[0] * f[1] * f[2];
+    dN[0] = (sgn[0] / h) * f[1] * f[2];
+    dN[1] = (sgn[1] / h) * f[0] * f[2];
+    dN[2] = (sgn[2] / h) * f[0] * f[1];
+}
+
+__global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restrict__ x,
+                                                    const double *__restrict__ gamma,
+                                                    const double *__restrict__ src,
+                                                    const uint8_t *__restrict__ nmask,
+                                                    double *__restrict__ D,
+                                                    double *__restrict__ slots)
+{
+    using T = double;
+    __shared__ T sx[NF][BOXN];
+    __shared__ T so[25 * BOXN];
+    const TileIdx t = tile_index(g);
+    stage<T, 25>(g, t, x, (const double *)nullptr, nmask, sx, nullptr, so);
+    __syncthreads();
+    const EC<T> c = make_ec<T>(g);
+    T alpha = 0, Kc = 1, s = 0, tau = 0, tauT = 0;
+    T mu[3][8], mp[8], mT[8];
+    if (t.valid) {
+        const int64_t e = (int64_t)t.i + (int64_t)g.nx * ((int64_t)t.j + (int64_t)g.ny * t.k);
+        const double y = gamma[e];
+        alpha = alpha_of(g, y);
+        Kc = K_of(g, y);
+        s = src[e];
+        T U2 = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                T xa = sx[i][t.nb[a]];
+                U2 += xa * xa;
+                mu[i][a] = xa;
+            }
+            to_modal(mu[i], c);
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            mp[a] = sx[3][t.nb[a]];
+            mT[a] = sx[4][t.nb[a]];
+        }
+        to_modal(mp, c);
+        to_modal(mT, c);
+        tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
+        tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
+    }
+    const double h = g.h;
+    for (int a = 0; a < 8; ++a) {
+        if (t.valid) {
+            T blk[25];
+#pragma unroll
+            for (int q = 0; q < 25; ++q) blk[q] = 0;
+            T ua[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ua[i] = sx[i][t.nb[a]];
+#define FE_BD_GP(G)                                                                          \
+    {                                                                                        \
+        T u[3], Gd[3][3], gp[3], Tv, gT[3];                                                  \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
+            eval_vg<G>(mu[i], c.gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                     \
+        eval_g<G>(mp, c.gs, gp[0], gp[1], gp[2]);                                            \
+        eval_vg<G>(mT, c.gs, Tv, gT[0], gT[1], gT[2]);                                       \
+        T N, dN[3];                                                                          \
+        shape_at<G>(a, h, N, dN);                                                            \
+        const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
+        T rM[3];                                                                             \
+        _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
+            rM[i] = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2] + gp[i]             \
+                  + alpha * u[i] + c.B * egv[i] * Tv;                                        \
+        T rT = u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2] - s;                               \
+        T udN = u[0] * dN[0] + u[1] * dN[1] + u[2] * dN[2];                                  \
+        _Pragma("unroll") for (int fc = 0; fc < NF; ++fc) {                                  \
+            /* direction: unit vector on (node a, field fc) */                               \
+            T du[3] = {0, 0, 0}, dG[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};               \
+            T dpv = 0, gdp[3] = {0, 0, 0}, dTv = 0, gdT[3] = {0, 0, 0};                      \
+            T dtau = 0, dtauT = 0;                                                           \
+            if (fc < 3) {                                                                    \
+                du[fc] = N;                                                                  \
+                dG[fc][0] = dN[0]; dG[fc][1] = dN[1]; dG[fc][2] = dN[2];                     \
+                dtau = -(tau * tau * tau) * ua[fc] * c.inv16h2;                              \
+                dtauT = -(tauT * tauT * tauT) * ua[fc] * c.inv16h2;                          \
+            } else if (fc == 3) {                                                            \
+                dpv = N; gdp[0] = dN[0]; gdp[1] = dN[1]; gdp[2] = dN[2];                     \
+            } else {                                                                         \
+                dTv = N; gdT[0] = dN[0]; gdT[1] = dN[1]; gdT[2] = dN[2];                     \
+            }                                                                                \
+            T A[3], Bm[3], dgal[3];                                                          \
+            _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                  \
+                T dconv = du[0] * Gd[i][0] + du[1] * Gd[i][1] + du[2] * Gd[i][2]             \
+                        + u[0] * dG[i][0] + u[1] * dG[i][1] + u[2] * dG[i][2];               \
+                dgal[i] = dconv + alpha * du[i] + c.B * egv[i] * dTv;                        \
+                A[i] = dtau * rM[i] + tau * (dgal[i] + gdp[i]);                              \
+                Bm[i] = tau * rM[i];                                                         \
+            }                                                                                \
+            T dudN = du[0] * dN[0] + du[1] * dN[1] + du[2] * dN[2];                          \
+            _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                  \
+                T visc = c.Pr * ((dG[i][0] + dG[0][i]) * dN[0] + (dG[i][1] + dG[1][i]) * dN[1] \
+                                 + (dG[i][2] + dG[2][i]) * dN[2]);                           \
+                blk[i * NF + fc] += c.W * (N * dgal[i] + visc - dN[i] * dpv + udN * A[i]     \
+                                           + dudN * Bm[i]);                                  \
+            }                                                                                \
+            blk[3 * NF + fc] += c.W * (N * (dG[0][0] + dG[1][1] + dG[2][2])                  \
+                                       + dN[0] * A[0] + dN[1] * A[1] + dN[2] * A[2]);        \
+            T drT = du[0] * gT[0] + du[1] * gT[1] + du[2] * gT[2]                            \
+                  + u[0] * gdT[0] + u[1] * gdT[1] + u[2] * gdT[2];                           \
+            T AT = dtauT * rT + tauT * drT, BT = tauT * rT;                                  \
+            blk[4 * NF + fc] += c.W * (N * drT + Kc * (dN[0] * gdT[0] + dN[1] * gdT[1]       \
+                                                       + dN[2] * gdT[2])                     \
+                                       + udN * AT + dudN * BT);                              \
+        }                                                                                    \
+    }
+            FE_BD_GP(0) FE_BD_GP(1) FE_BD_GP(2) FE_BD_GP(3)
+            FE_BD_GP(4) FE_BD_GP(5) FE_BD_GP(6) FE_BD_GP(7)
+#undef FE_BD_GP
+#pragma unroll
+            for (int q = 0; q < 25; ++q) so[q * BOXN + t.nb[a]] += blk[q];
+        }
+        __syncthreads();
+    }
+    const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
+    for (int nb = threadIdx.x; nb < BOXN; nb += NTHR) {
+        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        if (I > g.nx || J > g.ny || K > g.nz) continue;
+        bool sh = shared_dir(lx, I, g.nx, TX) || shared_dir(ly, J, g.ny, TY) ||
+                  shared_dir(lz, K, g.nz, TZ);
+        if (sh) {
+            double *sl = slots + ((int64_t)t.tile * BOXN + nb) * 25;
+            for (int q = 0; q < 25; ++q) sl[q] = so[q * BOXN + nb];
+        } else {
+            int64_t gn = gnode(g, I, J, K);
+            uint8_t m = nmask[gn];
+            for (int f = 0; f < NF; ++f)
+                for (int f2 = 0; f2 < NF; ++f2) {
+                    double val = so[(f * NF + f2) * BOXN + nb];
+                    if (((m >> f) & 1) || ((m >> f2) & 1)) val = (f == f2) ? 1.0 : 0.0;
+                    D[gn * 25 + f * NF + f2] = val;
+                }
+        }
+    }
+}
+
+}  // namespace
+
+// ---- launchers ----------------------------------------------------------------------
+
+template <typename Tin, typename Tout>
+hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, const double *gamma,
+                       const double *s, const uint8_t *nmask, Tout *out, Tout *slots,
+                       hipStream_t st)
+{
+    const dim3 grid((unsigned)n_tiles(g)), block(NTHR);
+    const int64_t nn = n_nodes(g);
+    const dim3 cgrid((unsigned)((nn + 255) / 256)), cblock(256);
+    switch (op) {
+    case OP_RES:
+        hipLaunchKernelGGL((k_elem<Tin, Tout, OP_RES>), grid, block, 0, st, g, x, v, gamma, s,
+                           nmask, out, slots);
+        hipLaunchKernelGGL((k_combine<Tin, Tout, NF, OP_RES>), cgrid, cblock, 0, st, g,
+                           (const Tout *)slots, nmask, v, out);
+        break;
+    case OP_JV:
+        hipLaunchKernelGGL((k_elem<Tin, Tout, OP_JV>), grid, block, 0, st, g, x, v, gamma, s,
+                           nmask, out, slots);
+        hipLaunchKernelGGL((k_combine<Tin, Tout, NF, OP_JV>), cgrid, cblock, 0, st, g,
+                           (const Tout *)slots, nmask, v, out);
+        break;
+    case OP_JTV:
+        hipLaunchKernelGGL((k_elem<Tin, Tout, OP_JTV>), grid, block, 0, st, g, x, v, gamma, s,
+                           nmask, out, slots);
+        hipLaunchKernelGGL((k_combine<Tin, Tout, NF, OP_JTV>), cgrid, cblock, 0, st, g,
+                           (const Tout *)slots, nmask, v, out);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_elem<double, double>(ElemOp, const Geo &, const double *, const double *,
+                                                const double *, const double *, const uint8_t *,
+                                                double *, double *, hipStream_t);
+template hipError_t launch_elem<float, float>(ElemOp, const Geo &, const float *, const float *,
+                                              const double *, const double *, const uint8_t *,
+                                              float *, float *, hipStream_t);
+template hipError_t launch_elem<float, double>(ElemOp, const Geo &, const float *, const float *,
+                                               const double *, const double *, const uint8_t *,
+                                               double *, double *, hipStream_t);
+
+hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
+                           const double *s, const uint8_t *nmask, double *gout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dRdgamma, dim3((unsigned)n_tiles(g)), dim3(NTHR), 0, st, g, x, lam, gamma,
+                       s, nmask, gout);
+    return hipGetLastError();
+}
+
+hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, const double *s,
+                            const uint8_t *nmask, double *D, double *slots, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_blockdiag, dim3((unsigned)n_tiles(g)), dim3(NTHR), 0, st, g, x, gamma, s,
+                       nmask, D, slots);
+    const int64_t nn = n_nodes(g);
+    hipLaunchKernelGGL((k_combine<double, double, 25, OP_RES>), dim3((unsigned)((nn + 255) / 256)),
+                       dim3(256), 0, st, g, (const double *)slots, nmask, (const double *)nullptr,
+                       D);
+    return hipGetLastError();
+}
+
+}  // namespace fe

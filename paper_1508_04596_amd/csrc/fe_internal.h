@@ -1,0 +1,123 @@
+// Internal declarations of the HIP state-solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fe.h"
+
+namespace fe {
+
+constexpr int NF = 5;  // unknowns per node: u, v, w, p, T
+
+// Element tile processed by one workgroup: TX*TY*TZ elements, one per thread.
+constexpr int TX = 8, TY = 8, TZ = 4;
+constexpr int NTHR = TX * TY * TZ;  // 256 threads = 4 wave64
+constexpr int BX = TX + 1, BY = TY + 1, BZ = TZ + 1;
+constexpr int BOXN = BX * BY * BZ;  // nodes of the tile's node box (405)
+
+// Grid geometry and physical constants, passed by value to every element kernel.
+struct Geo {
+    int nx, ny, nz;     // elements
+    int ntx, nty, ntz;  // tiles
+    double h, Pr, B;    // B = Gr * Pr^2 (buoyancy coefficient)
+    double eg[3];
+    double Ck, qf, amax, qa;
+};
+
+Geo make_geo(const fe_grid &g, const fe_phys &ph);
+
+inline int64_t n_nodes(const Geo &g) { return (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1); }
+inline int64_t n_elem(const Geo &g) { return (int64_t)g.nx * g.ny * g.nz; }
+inline int64_t n_tiles(const Geo &g) { return (int64_t)g.ntx * g.nty * g.ntz; }
+
+// Which element operator a tile kernel evaluates.
+enum ElemOp { OP_RES = 0, OP_JV = 1, OP_JTV = 2 };
+
+// ---- element kernel launchers (fe_elem.hip) --------------------------------
+// x, v: node vectors of type Tin; out: node vector of type Tout; nmask: per
+// node bit mask (bit f set = DOF f prescribed); slots: tile-face partial sums,
+// n_tiles * BOXN * 5 values of Tout.
+template <typename Tin, typename Tout>
+hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, const double *gamma,
+                       const double *s, const uint8_t *nmask, Tout *out, Tout *slots,
+                       hipStream_t st);
+hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
+                           const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
+// Raw nodal 5x5 diagonal blocks of J (row-major [n][25]), masked rows/cols set
+// to the identity; slots must hold n_tiles * BOXN * 25 doubles.
+hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, const double *s,
+                            const uint8_t *nmask, double *D, double *slots, hipStream_t st);
+
+// ---- vector kernels (fe_vec.hip) ------------------------------------------
+constexpr int RED_BLOCKS = 512;   // partial sums per reduction (fixed => deterministic)
+constexpr int RED_THREADS = 256;
+
+hipError_t launch_node_mask(const uint8_t *dof_mask, uint8_t *nmask, int64_t nn, hipStream_t st);
+// Invert 5x5 blocks in place (FP64) and optionally write an FP32 copy.
+hipError_t launch_invert_blocks(double *D, float *D32, int64_t nn, hipStream_t st);
+// z = D v per node (D row-major 5x5); Tin/Tout/Tm = vector, output, matrix types;
+// the transposed variant applies D^T.
+template <typename Tm, typename Tin, typename Tout>
+hipError_t launch_block_apply(const Tm *D, const Tin *v, Tout *z, int64_t nn, bool transpose,
+                              const double *scale_dev, hipStream_t st);
+// partial[j*RED_BLOCKS + b] = block b's share of <V_j, w>, j < k; V_j = V + j*ld.
+hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
+                           double *partial, hipStream_t st);
+// w -= sum_j h[j] V_j (h on device), and, if partial != NULL, partial sums of
+// <V_j, w_new> for j < k2 (k2 may differ from k) or of <w_new, w_new> when k2 == -1.
+hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h, double *w,
+                             int64_t n, int k2, double *partial, hipStream_t st);
+// out[j] = sum_b partial[j*RED_BLOCKS + b] (+ add[j] if add != NULL), j < k,
+// summed in a fixed order; if sqrt_last, out[k-1] = sqrt(out[k-1]).
+hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
+                         bool sqrt_last, hipStream_t st);
+hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st);
+// y = a*x + b*y with scalars from device pointers (NULL pointer = constant given)
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
+// y = x + lam*d
+hipError_t launch_xpld(int64_t n, const double *x, double lam, const double *d, double *y,
+                       hipStream_t st);
+// y = x / s[0] (s on device)
+hipError_t launch_scale_div(int64_t n, const double *x, const double *s, double *y,
+                            hipStream_t st);
+// y += sum_j c[j] Z_j with Z of type Tz (c on device)
+template <typename Tz>
+hipError_t launch_combine(const Tz *Z, int64_t ld, int k, const double *c, double *y, int64_t n,
+                          hipStream_t st);
+template <typename Ta, typename Tb>
+hipError_t launch_cast(const Ta *a, Tb *b, int64_t n, hipStream_t st);
+hipError_t launch_compliance(const Geo &g, const double *x, const double *s,
+                             const uint8_t *nmask, double *dfdx, double *partial,
+                             hipStream_t st);
+
+// ---- errors ----------------------------------------------------------------
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+struct SolverWs;
+
+}  // namespace fe
+
+struct fe_problem {
+    fe_grid grid;
+    fe_phys phys;
+    fe::Geo geo;
+    int device;
+    int64_t nn, ne, ndof;
+    uint8_t *nmask = nullptr;     // per node: bit f = DOF f prescribed
+    uint8_t *dof_mask = nullptr;  // per DOF copy of the caller's mask
+    double *slots = nullptr;      // tile-face partial sums (5 values / node box entry)
+    double *slots25 = nullptr;    // block-diagonal partial sums (25 values)
+    double *partial = nullptr;    // reduction partials, 66 * RED_BLOCKS
+    double *scal = nullptr;       // device scalars
+    fe::SolverWs *ws = nullptr;    // Newton/FGMRES workspace (allocated on first solve)
+};
+
+#define FE_CHECK_HIP(call)                                        \
+    do {                                                          \
+        hipError_t _e = (call);                                   \
+        if (_e != hipSuccess) return fe::hip_fail(_e, #call);     \
+    } while (0)

@@ -1,0 +1,540 @@
+// Host-driven solvers over the device kernels: flexible GMRES with classical
+// Gram-Schmidt (two passes) in FP64, damped Newton with the quadratic L2 line
+// search (Sec. "Solving the non-linear system"), the adjoint solve, and the
+// FP32-operator / FP64-residual refinement used in mixed mode.
+//
+// The Krylov basis V, the Hessenberg matrix, the Givens rotations and every
+// norm are FP64.  One Arnoldi step runs entirely on the device; the host reads
+// back one Hessenberg column (j+2 numbers) per step to update the Givens
+// rotations and test convergence.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "fe_internal.h"
+
+using namespace fe;
+
+namespace fe {
+
+struct SolverWs {
+    int m = 0;           // restart length the buffers were sized for
+    bool mixed = false;  // FP32 copies allocated
+    int64_t ndof = 0, nn = 0;
+    double *R = nullptr, *Rh = nullptr, *R1 = nullptr, *xt = nullptr, *delta = nullptr;
+    double *rhs = nullptr, *V = nullptr, *Z = nullptr, *D = nullptr, *tmp = nullptr;
+    float *Z32 = nullptr, *D32 = nullptr, *x32 = nullptr;
+    double *hbuf = nullptr;  // device: h1[65] | h2[65] | beta
+    double *ydev = nullptr;  // device: combination coefficients
+    double *hhost = nullptr; // pinned host copy of hbuf / y
+    hipEvent_t ev[8] = {};
+};
+
+static void free_ws(SolverWs *w)
+{
+    if (!w) return;
+    double *d[] = {w->R, w->Rh, w->R1, w->xt, w->delta, w->rhs, w->V, w->Z, w->D, w->tmp,
+                   w->hbuf, w->ydev};
+    for (double *q : d) (void)hipFree(q);
+    (void)hipFree(w->Z32);
+    (void)hipFree(w->D32);
+    (void)hipFree(w->x32);
+    if (w->hhost) (void)hipHostFree(w->hhost);
+    for (auto &e : w->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete w;
+}
+
+static int64_t ws_bytes(int64_t ndof, int64_t nn, int m, bool mixed)
+{
+    int64_t b = 0;
+    b += 7 * ndof * 8;                 // R, Rh, R1, xt, delta, rhs, tmp
+    b += (int64_t)(m + 1) * ndof * 8;  // V
+    b += (int64_t)m * ndof * 8;        // Z (FP64; the adjoint solve always uses it)
+    if (mixed) b += (int64_t)m * ndof * 4;  // Z32
+    b += nn * 25 * 8;                  // D
+    if (mixed) b += nn * 25 * 4 + ndof * 4;  // D32, x32
+    b += 2 * 256 * 8;
+    return b;
+}
+
+static int ensure_ws(fe_problem *p, int m, bool mixed)
+{
+    SolverWs *w = p->ws;
+    if (w && w->m >= m && (w->mixed || !mixed)) return FE_OK;
+    free_ws(w);
+    p->ws = nullptr;
+    w = new SolverWs();
+    w->m = m;
+    w->mixed = mixed;
+    w->ndof = p->ndof;
+    w->nn = p->nn;
+    const size_t nb = sizeof(double) * p->ndof;
+    hipError_t e = hipSuccess;
+    double **vecs[] = {&w->R, &w->Rh, &w->R1, &w->xt, &w->delta, &w->rhs, &w->tmp};
+    for (double **q : vecs)
+        if (e == hipSuccess) e = hipMalloc(q, nb);
+    if (e == hipSuccess) e = hipMalloc(&w->V, nb * (m + 1));
+    if (e == hipSuccess) e = hipMalloc(&w->Z, nb * m);
+    if (e == hipSuccess && mixed) e = hipMalloc(&w->Z32, sizeof(float) * p->ndof * m);
+    if (e == hipSuccess) e = hipMalloc(&w->D, sizeof(double) * 25 * p->nn);
+    if (e == hipSuccess && mixed) e = hipMalloc(&w->D32, sizeof(float) * 25 * p->nn);
+    if (e == hipSuccess && mixed) e = hipMalloc(&w->x32, sizeof(float) * p->ndof);
+    if (e == hipSuccess) e = hipMalloc(&w->hbuf, sizeof(double) * 256);
+    if (e == hipSuccess) e = hipMalloc(&w->ydev, sizeof(double) * 256);
+    if (e == hipSuccess) e = hipHostMalloc(&w->hhost, sizeof(double) * 256);
+    for (auto &ev : w->ev)
+        if (e == hipSuccess) e = hipEventCreate(&ev);
+    if (e == hipSuccess && !p->slots25)
+        e = hipMalloc(&p->slots25, (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double));
+    if (e != hipSuccess) {
+        free_ws(w);
+        return hip_fail(e, "hipMalloc (solver workspace)");
+    }
+    p->ws = w;
+    return FE_OK;
+}
+
+// ||a||_2 (device reduction, host result; synchronises the stream)
+static int norm2(fe_problem *p, const double *a, hipStream_t st, double *out)
+{
+    FE_CHECK_HIP(launch_norm2_partial(a, p->ndof, p->partial, st));
+    FE_CHECK_HIP(launch_reduce(p->partial, 1, p->scal, nullptr, true, st));
+    FE_CHECK_HIP(hipMemcpyAsync(p->ws->hhost, p->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    FE_CHECK_HIP(hipStreamSynchronize(st));
+    *out = p->ws->hhost[0];
+    return FE_OK;
+}
+
+// Linear operator / preconditioner callbacks for one FGMRES solve.
+struct LinSys {
+    // z_j = M v_j (v FP64, z in the Krylov-vector type of the solve)
+    std::function<hipError_t(const double *v, void *z)> prec;
+    // w = A z (z in the Krylov-vector type), w FP64
+    std::function<hipError_t(const void *z, double *w)> op_z;
+    // w = A x with x FP64 (true residual)
+    std::function<hipError_t(const double *x, double *w)> op64;
+    bool z32 = false;  // Krylov vectors z_j stored in FP32
+};
+
+struct LinStats {
+    int its = 0;
+    bool converged = false;
+    double t_jv = 0, t_prec = 0, t_orth = 0;
+    double res_true = 0;
+};
+
+// Solve A x = b for x (x = 0 on entry) to |b - A x| <= rtol |b|, FGMRES(m).
+// Mixed mode (z32): the Arnoldi process uses the FP32 operator; each cycle
+// ends with the true FP64 residual b - A x, and cycles continue while it is
+// above the target, at most n_refine cycles beyond the first convergence.
+static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, double rtol, int m,
+                  int max_its, int n_refine, hipStream_t st, LinStats *stats, int verbose)
+{
+    SolverWs *w = p->ws;
+    const int64_t n = p->ndof;
+    const int64_t ld = n;
+    FE_CHECK_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+    double beta0;
+    int rc = norm2(p, b, st, &beta0);
+    if (rc) return rc;
+    if (!std::isfinite(beta0)) {
+        set_error("non-finite right-hand side in FGMRES");
+        return FE_ENAN;
+    }
+    stats->its = 0;
+    stats->converged = false;
+    if (beta0 == 0.0) {
+        stats->converged = true;
+        return FE_OK;
+    }
+    const double target = rtol * beta0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    const double *r = b;  // residual of the current cycle (b on the first cycle)
+    double beta = beta0;
+    int refine_left = n_refine;
+    bool first = true;
+    while (true) {
+        // v0 = r / beta
+        w->hhost[200] = beta;
+        FE_CHECK_HIP(hipMemcpyAsync(w->hbuf + 130, w->hhost + 200, sizeof(double),
+                                    hipMemcpyHostToDevice, st));
+        FE_CHECK_HIP(launch_scale_div(n, r, w->hbuf + 130, w->V, st));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        double res = beta;
+        bool breakdown = false;
+        for (j = 0; j < m; ++j) {
+            double *vj = w->V + (int64_t)j * ld;
+            double *vn = w->V + (int64_t)(j + 1) * ld;
+            void *zj = L.z32 ? (void *)(w->Z32 + (int64_t)j * ld) : (void *)(w->Z + (int64_t)j * ld);
+            FE_CHECK_HIP(hipEventRecord(w->ev[0], st));
+            FE_CHECK_HIP(L.prec(vj, zj));
+            FE_CHECK_HIP(hipEventRecord(w->ev[1], st));
+            FE_CHECK_HIP(L.op_z(zj, vn));
+            FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
+            const int k = j + 1;
+            FE_CHECK_HIP(launch_multidot(w->V, ld, k, vn, n, p->partial, st));
+            FE_CHECK_HIP(launch_reduce(p->partial, k, w->hbuf, nullptr, false, st));
+            FE_CHECK_HIP(launch_update_dot(w->V, ld, k, w->hbuf, vn, n, k, p->partial, st));
+            FE_CHECK_HIP(launch_reduce(p->partial, k, w->hbuf + 65, nullptr, false, st));
+            FE_CHECK_HIP(launch_update_dot(w->V, ld, k, w->hbuf + 65, vn, n, -1, p->partial, st));
+            FE_CHECK_HIP(launch_reduce(p->partial, 1, w->hbuf + 130, nullptr, true, st));
+            FE_CHECK_HIP(launch_scale_div(n, vn, w->hbuf + 130, vn, st));
+            FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
+            FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * 131,
+                                        hipMemcpyDeviceToHost, st));
+            FE_CHECK_HIP(hipStreamSynchronize(st));
+            float ms;
+            if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) stats->t_prec += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, w->ev[1], w->ev[2]) == hipSuccess) stats->t_jv += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
+            const double *hh = w->hhost;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[65 + i];
+            const double hn = hh[130];
+            if (!std::isfinite(hn)) {
+                set_error("non-finite Krylov norm");
+                return FE_ENAN;
+            }
+            // apply previous rotations to column j
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[(size_t)j * m + j];
+            double den = std::hypot(a, hn);
+            if (den == 0.0) {
+                cs[j] = 1.0;
+                sn[j] = 0.0;
+            } else {
+                cs[j] = a / den;
+                sn[j] = hn / den;
+            }
+            H[(size_t)j * m + j] = cs[j] * a + sn[j] * hn;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            res = std::fabs(g[j + 1]);
+            stats->its++;
+            if (hn <= 1e-300 * beta0) breakdown = true;
+            if (res <= target || stats->its >= max_its || breakdown) {
+                ++j;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular j x j), x += Z y
+        const int kk = j;
+        for (int i = kk - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int c = i + 1; c < kk; ++c) s -= H[(size_t)i * m + c] * y[c];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        std::memcpy(w->hhost, y.data(), sizeof(double) * kk);
+        FE_CHECK_HIP(hipMemcpyAsync(w->ydev, w->hhost, sizeof(double) * kk, hipMemcpyHostToDevice, st));
+        if (L.z32)
+            FE_CHECK_HIP(launch_combine<float>(w->Z32, ld, kk, w->ydev, x, n, st));
+        else
+            FE_CHECK_HIP(launch_combine<double>(w->Z, ld, kk, w->ydev, x, n, st));
+        const bool est_conv = res <= target;
+        const bool need_true = L.z32 || !est_conv;
+        if (stats->its >= max_its && !est_conv) break;
+        if (!need_true) {
+            stats->converged = true;
+            stats->res_true = res;
+            break;
+        }
+        // true residual r = b - A x (FP64 operator)
+        FE_CHECK_HIP(L.op64(x, w->tmp));
+        FE_CHECK_HIP(launch_axpby(n, 1.0, b, -1.0, w->tmp, st));
+        rc = norm2(p, w->tmp, st, &beta);
+        if (rc) return rc;
+        stats->res_true = beta;
+        if (verbose > 1)
+            fprintf(stderr, "  fgmres cycle: its %d est %.3e true %.3e target %.3e\n", stats->its,
+                    res / beta0, beta / beta0, rtol);
+        if (beta <= target) {
+            stats->converged = true;
+            break;
+        }
+        if (est_conv) {
+            if (refine_left-- <= 0) break;
+        }
+        if (stats->its >= max_its || breakdown) break;
+        // next cycle solves A d = r and adds d to x: keep x, restart from r
+        // (x accumulates across cycles since each cycle adds Z y to it)
+        r = w->tmp;
+        (void)first;
+        first = false;
+        // r lives in tmp; the next cycle's v0 = r / beta copies it into V before
+        // tmp is reused for the following true residual.
+    }
+    return FE_OK;
+}
+
+}  // namespace fe
+
+extern "C" {
+
+void fe_free_solver_ws(fe_problem *p)
+{
+    if (p && p->ws) {
+        free_ws(p->ws);
+        p->ws = nullptr;
+    }
+}
+
+void fe_solve_opts_default(fe_solve_opts *o)
+{
+    if (!o) return;
+    o->rtol_newton = 1e-8;
+    o->rtol_lin = 1e-5;
+    o->max_newton = 50;
+    o->restart = 30;
+    o->max_lin = 3000;
+    o->n_refine = 3;
+    o->krylov_op_prec = FE_FP64;
+    o->ls_lambda_min = 0.05;
+    o->verbose = 0;
+}
+
+int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
+{
+    if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return -1;
+    fe_solve_opts d;
+    fe_solve_opts_default(&d);
+    if (!opts) opts = &d;
+    const int64_t nn = (int64_t)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
+    const int64_t ndof = NF * nn;
+    const int64_t ntile = (int64_t)((grid->nx + TX - 1) / TX) * ((grid->ny + TY - 1) / TY) *
+                          ((grid->nz + TZ - 1) / TZ);
+    int64_t b = ws_bytes(ndof, nn, opts->restart, opts->krylov_op_prec == FE_FP32);
+    b += ntile * BOXN * (NF + 25) * 8;  // slots
+    b += nn + ndof + 66 * RED_BLOCKS * 8 + 256 * 8;
+    return b;
+}
+
+static void fill_report(fe_solve_report *rep, const fe_solve_report &r)
+{
+    if (rep) *rep = r;
+}
+
+int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, double *x,
+                 const fe_solve_opts *opts_in, fe_solve_report *report, hipStream_t st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !gamma || !s_elem || !x) {
+        set_error("newton_solve: NULL argument");
+        return FE_EINVAL;
+    }
+    fe_solve_opts opts;
+    fe_solve_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.restart < 1 || opts.restart > 64 || opts.max_newton < 0 || opts.max_lin < 1 ||
+        !(opts.rtol_newton >= 0) || !(opts.rtol_lin > 0)) {
+        set_error("newton_solve: invalid options (restart 1..64, max_lin >= 1, rtol_lin > 0)");
+        return FE_EINVAL;
+    }
+    const bool mixed = opts.krylov_op_prec == FE_FP32;
+    int rc = ensure_ws(p, opts.restart, mixed);
+    if (rc) return rc;
+    SolverWs *w = p->ws;
+    const int64_t n = p->ndof;
+    fe_solve_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+
+    double *R = w->R, *Rh = w->Rh, *R1 = w->R1;
+    FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, x, (const double *)nullptr, gamma,
+                                              s_elem, p->nmask, R, p->slots, st)));
+    double r0, rn;
+    rc = norm2(p, R, st, &r0);
+    if (rc) return rc;
+    rep.res0 = r0;
+    rep.res_hist[0] = r0;
+    if (!std::isfinite(r0)) {
+        set_error("non-finite initial residual");
+        rep.status = FE_ENAN;
+        fill_report(report, rep);
+        return FE_ENAN;
+    }
+    rn = r0;
+    LinSys L;
+    L.z32 = mixed;
+    L.prec = [&](const double *v, void *z) -> hipError_t {
+        if (mixed)
+            return launch_block_apply<float, double, float>(w->D32, v, (float *)z, p->nn, false,
+                                                            nullptr, st);
+        return launch_block_apply<double, double, double>(w->D, v, (double *)z, p->nn, false,
+                                                          nullptr, st);
+    };
+    L.op_z = [&](const void *z, double *out) -> hipError_t {
+        if (mixed)
+            return launch_elem<float, double>(OP_JV, p->geo, w->x32, (const float *)z, gamma,
+                                              s_elem, p->nmask, out, p->slots, st);
+        return launch_elem<double, double>(OP_JV, p->geo, x, (const double *)z, gamma, s_elem,
+                                           p->nmask, out, p->slots, st);
+    };
+    L.op64 = [&](const double *v, double *out) -> hipError_t {
+        return launch_elem<double, double>(OP_JV, p->geo, x, v, gamma, s_elem, p->nmask, out,
+                                           p->slots, st);
+    };
+    int status = FE_NOT_CONVERGED;
+    double lam = 1.0;
+    while (true) {
+        if (rn <= opts.rtol_newton * r0) {
+            status = FE_OK;
+            break;
+        }
+        if (rep.newton_its >= opts.max_newton) break;
+        hipEvent_t e0 = w->ev[4], e1 = w->ev[5];
+        FE_CHECK_HIP(hipEventRecord(e0, st));
+        FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
+        FE_CHECK_HIP(launch_invert_blocks(w->D, mixed ? w->D32 : nullptr, p->nn, st));
+        if (mixed) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+        FE_CHECK_HIP(launch_axpby(n, -1.0, R, 0.0, w->rhs, st));
+        FE_CHECK_HIP(hipEventRecord(e1, st));
+        LinStats ls;
+        rc = fgmres(p, L, w->rhs, w->delta, opts.rtol_lin, opts.restart, opts.max_lin,
+                    mixed ? opts.n_refine : 0, st, &ls, opts.verbose);
+        if (rc) {
+            rep.status = rc;
+            fill_report(report, rep);
+            return rc;
+        }
+        float ms;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) rep.t_setup_s += ms * 1e-3;
+        rep.t_jv_s += ls.t_jv;
+        rep.t_prec_s += ls.t_prec;
+        rep.t_orth_s += ls.t_orth;
+        if (rep.newton_its < 64) rep.lin_its[rep.newton_its] = ls.its;
+        rep.lin_its_total += ls.its;
+        // line search on phi(l) = |R(x + l delta)|^2 at l = 1/2 and 1
+        FE_CHECK_HIP(hipEventRecord(e0, st));
+        double nh, n1;
+        FE_CHECK_HIP(launch_xpld(n, x, 0.5, w->delta, w->xt, st));
+        FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, w->xt, (const double *)nullptr,
+                                                  gamma, s_elem, p->nmask, Rh, p->slots, st)));
+        rc = norm2(p, Rh, st, &nh);
+        if (rc) return rc;
+        FE_CHECK_HIP(launch_xpld(n, x, 1.0, w->delta, w->xt, st));
+        FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, w->xt, (const double *)nullptr,
+                                                  gamma, s_elem, p->nmask, R1, p->slots, st)));
+        rc = norm2(p, R1, st, &n1);
+        if (rc) return rc;
+        const double phi0 = rn * rn, phih = nh * nh, phi1 = n1 * n1;
+        if (!std::isfinite(phih) && !std::isfinite(phi1)) {
+            set_error("non-finite residual in the line search");
+            rep.status = FE_ENAN;
+            fill_report(report, rep);
+            return FE_ENAN;
+        }
+        if (!std::isfinite(phi1))
+            lam = 0.5;
+        else if (!std::isfinite(phih))
+            lam = 1.0;
+        else
+            lam = fe_line_search_lambda(phi0, phih, phi1, opts.ls_lambda_min);
+        if (lam == 1.0) {
+            FE_CHECK_HIP(hipMemcpyAsync(x, w->xt, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            std::swap(R, R1);
+            rn = n1;
+        } else if (lam == 0.5) {
+            FE_CHECK_HIP(launch_xpld(n, x, 0.5, w->delta, x, st));
+            std::swap(R, Rh);
+            rn = nh;
+        } else {
+            FE_CHECK_HIP(launch_xpld(n, x, lam, w->delta, x, st));
+            FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, x, (const double *)nullptr,
+                                                      gamma, s_elem, p->nmask, R, p->slots, st)));
+            rc = norm2(p, R, st, &rn);
+            if (rc) return rc;
+        }
+        FE_CHECK_HIP(hipEventRecord(e1, st));
+        FE_CHECK_HIP(hipEventSynchronize(e1));
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) rep.t_res_s += ms * 1e-3;
+        rep.newton_its++;
+        if (rep.newton_its <= 64) rep.res_hist[rep.newton_its] = rn;
+        rep.lambda_last = lam;
+        if (opts.verbose)
+            fprintf(stderr, "newton %2d  |R| %.6e  rel %.3e  lambda %.3f  lin_its %d%s\n",
+                    rep.newton_its, rn, rn / r0, lam, ls.its, ls.converged ? "" : " (lin not conv)");
+        if (!std::isfinite(rn)) {
+            set_error("non-finite residual");
+            rep.status = FE_ENAN;
+            fill_report(report, rep);
+            return FE_ENAN;
+        }
+    }
+    // keep the buffer rotation consistent for the next call
+    w->R = R;
+    w->Rh = Rh;
+    w->R1 = R1;
+    FE_CHECK_HIP(hipStreamSynchronize(st));
+    rep.res_final = rn;
+    rep.status = status;
+    rep.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_report(report, rep);
+    if (status != FE_OK) set_error("newton_solve: not converged within max_newton");
+    return status;
+}
+
+int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                     const double *rhs, double *lambda, const fe_solve_opts *opts_in,
+                     fe_solve_report *report, hipStream_t st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !x || !gamma || !s_elem || !rhs || !lambda) {
+        set_error("fe_adjoint_solve: NULL argument");
+        return FE_EINVAL;
+    }
+    fe_solve_opts opts;
+    fe_solve_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.restart < 1 || opts.restart > 64 || opts.max_lin < 1 || !(opts.rtol_lin > 0)) {
+        set_error("fe_adjoint_solve: invalid options");
+        return FE_EINVAL;
+    }
+    int rc = ensure_ws(p, opts.restart, false);
+    if (rc) return rc;
+    SolverWs *w = p->ws;
+    fe_solve_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
+    FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
+    LinSys L;
+    L.z32 = false;
+    L.prec = [&](const double *v, void *z) -> hipError_t {
+        return launch_block_apply<double, double, double>(w->D, v, (double *)z, p->nn, true,
+                                                          nullptr, st);
+    };
+    L.op_z = [&](const void *z, double *out) -> hipError_t {
+        return launch_elem<double, double>(OP_JTV, p->geo, x, (const double *)z, gamma, s_elem,
+                                           p->nmask, out, p->slots, st);
+    };
+    L.op64 = [&](const double *v, double *out) -> hipError_t {
+        return launch_elem<double, double>(OP_JTV, p->geo, x, v, gamma, s_elem, p->nmask, out,
+                                           p->slots, st);
+    };
+    LinStats ls;
+    rc = fgmres(p, L, rhs, lambda, opts.rtol_lin, opts.restart, opts.max_lin, 0, st, &ls,
+                opts.verbose);
+    if (rc) return rc;
+    FE_CHECK_HIP(hipStreamSynchronize(st));
+    rep.lin_its_total = ls.its;
+    rep.lin_its[0] = ls.its;
+    rep.status = ls.converged ? FE_OK : FE_NOT_CONVERGED;
+    rep.res_final = ls.res_true;
+    rep.t_jv_s = ls.t_jv;
+    rep.t_prec_s = ls.t_prec;
+    rep.t_orth_s = ls.t_orth;
+    rep.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_report(report, rep);
+    if (!ls.converged) set_error("fe_adjoint_solve: FGMRES not converged");
+    return rep.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// Vector kernels of the Krylov / Newton loops on gfx950.
+//
+// Reductions are deterministic: a fixed grid of RED_BLOCKS workgroups each sums
+// a fixed strided range (wave64 shuffles, then LDS across the four waves) into
+// one partial per workgroup; a second kernel adds the partials in a fixed tree
+// order.  Multi-dot products for classical Gram-Schmidt keep up to 64 running
+// sums per thread in registers, so the basis vectors are streamed once per
+// pass; the update w -= V h is fused with the next pass's dot products.
+#include "fe_internal.h"
+
+namespace fe {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum KMAX per-thread accumulators over the workgroup; thread 0 writes them.
+template <int KMAX>
+__device__ __forceinline__ void block_sums(double (&acc)[KMAX], int k, double *partial)
+{
+    __shared__ double red[RED_THREADS / 64][KMAX];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        if (j < k) {
+            double s = wave_sum(acc[j]);
+            if (lane == 0) red[wv][j] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < KMAX && (int)threadIdx.x < k) {
+        const int j = threadIdx.x;
+        double s = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+        partial[(int64_t)j * RED_BLOCKS + blockIdx.x] = s;
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(RED_THREADS) void k_multidot(const double *__restrict__ V, int64_t ld,
+                                                          int k, const double *__restrict__ w,
+                                                          int64_t n, double *__restrict__ partial)
+{
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) acc[j] += V[j * ld + i] * wi;
+    }
+    block_sums<KMAX>(acc, k, partial);
+}
+
+// w -= sum_{j<k} h[j] V_j; then partial <V_j, w> for j < k2, or <w, w> if k2 == -1.
+template <int KMAX>
+__global__ __launch_bounds__(RED_THREADS) void k_update_dot(const double *__restrict__ V, int64_t ld,
+                                                            int k, const double *__restrict__ h,
+                                                            double *__restrict__ w, int64_t n,
+                                                            int k2, double *__restrict__ partial)
+{
+    __shared__ double hs[KMAX];
+    if (threadIdx.x < KMAX && (int)threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double vj[KMAX];
+        double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) {
+                vj[j] = V[j * ld + i];
+                wi -= hs[j] * vj[j];
+            }
+        w[i] = wi;
+        if (k2 == -1) {
+            acc[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < k2) acc[j] += vj[j] * wi;
+        }
+    }
+    if (partial) block_sums<KMAX>(acc, k2 == -1 ? 1 : k2, partial);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial,
+                                                double *__restrict__ out,
+                                                const double *__restrict__ add, int k, int sqrt_last)
+{
+    // one workgroup per output; RED_BLOCKS = 512 partials, 2 per thread, fixed tree
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    const double *p = partial + (int64_t)j * RED_BLOCKS;
+    double s = p[threadIdx.x] + p[threadIdx.x + 256];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = (red[0] + red[1]) + (red[2] + red[3]);
+        if (add) t += add[j];
+        if (sqrt_last && j == k - 1) t = sqrt(t);
+        out[j] = t;
+    }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_norm2_partial(const double *__restrict__ a,
+                                                               int64_t n,
+                                                               double *__restrict__ partial)
+{
+    double acc[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        acc[0] += a[i] * a[i];
+    block_sums<1>(acc, 1, partial);
+}
+
+__global__ void k_node_mask(const uint8_t *__restrict__ dm, uint8_t *__restrict__ nm, int64_t nn)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    uint8_t m = 0;
+    if (dm)
+        for (int f = 0; f < NF; ++f)
+            if (dm[NF * n + f]) m |= (uint8_t)(1u << f);
+    nm[n] = m;
+}
+
+// In-place inverse of each 5x5 block by Gauss-Jordan with partial pivoting.
+__global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32, int64_t nn)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double a[5][5], b[5][5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            a[r][c] = D[n * 25 + r * 5 + c];
+            b[r][c] = (r == c) ? 1.0 : 0.0;
+        }
+#pragma unroll
+    for (int col = 0; col < 5; ++col) {
+        int p = col;
+        double best = fabs(a[col][col]);
+#pragma unroll
+        for (int r = col + 1; r < 5; ++r)
+            if (fabs(a[r][col]) > best) {
+                best = fabs(a[r][col]);
+                p = r;
+            }
+#pragma unroll
+        for (int r = col + 1; r < 5; ++r)
+            if (r == p) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    double t = a[col][c]; a[col][c] = a[r][c]; a[r][c] = t;
+                    t = b[col][c]; b[col][c] = b[r][c]; b[r][c] = t;
+                }
+            }
+        const double inv = 1.0 / a[col][col];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            a[col][c] *= inv;
+            b[col][c] *= inv;
+        }
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            if (r != col) {
+                const double f = a[r][col];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    a[r][c] -= f * a[col][c];
+                    b[r][c] -= f * b[col][c];
+                }
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            D[n * 25 + r * 5 + c] = b[r][c];
+            if (D32) D32[n * 25 + r * 5 + c] = (float)b[r][c];
+        }
+}
+
+template <typename Tm, typename Tin, typename Tout, bool TR>
+__global__ void k_block_apply(const Tm *__restrict__ D, const Tin *__restrict__ v,
+                              Tout *__restrict__ z, int64_t nn, const double *__restrict__ scale)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    using Tc = Tm;
+    Tc vv[5];
+    const Tc sc = scale ? (Tc)(1.0 / scale[0]) : Tc(1);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) vv[f] = (Tc)v[n * 5 + f] * sc;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        Tc acc = 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc += (TR ? D[n * 25 + c * 5 + r] : D[n * 25 + r * 5 + c]) * vv[c];
+        z[n * 5 + r] = (Tout)acc;
+    }
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                        double *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_xpld(int64_t n, const double *__restrict__ x, double lam,
+                       const double *__restrict__ d, double *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] + lam * d[i];
+}
+
+__global__ void k_scale_div(int64_t n, const double *__restrict__ x, const double *__restrict__ s,
+                            double *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double inv = 1.0 / s[0];
+    if (i < n) y[i] = x[i] * inv;
+}
+
+template <typename Tz>
+__global__ void k_combine_vec(const Tz *__restrict__ Z, int64_t ld, int k,
+                              const double *__restrict__ c, double *__restrict__ y, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = y[i];
+    for (int j = 0; j < k; ++j) acc += c[j] * (double)Z[j * ld + i];
+    y[i] = acc;
+}
+
+template <typename Ta, typename Tb>
+__global__ void k_cast(const Ta *__restrict__ a, Tb *__restrict__ b, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (Tb)a[i];
+}
+
+// Thermal compliance: c_n = sum over the node's source elements of s_e h^3/8;
+// partial sums of T_n c_n; dfdx = c on unprescribed T entries.
+__global__ __launch_bounds__(RED_THREADS) void k_compliance(Geo g, const double *__restrict__ x,
+                                                            const double *__restrict__ s,
+                                                            const uint8_t *__restrict__ nmask,
+                                                            double *__restrict__ dfdx,
+                                                            double *__restrict__ partial)
+{
+    const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    const double w8 = 0.125 * g.h * g.h * g.h;
+    double acc[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += stride) {
+        const int I = (int)(n % (g.nx + 1));
+        const int64_t r = n / (g.nx + 1);
+        const int J = (int)(r % (g.ny + 1));
+        const int K = (int)(r / (g.ny + 1));
+        double cn = 0.0;
+        for (int dz = -1; dz <= 0; ++dz)
+            for (int dy = -1; dy <= 0; ++dy)
+                for (int dx = -1; dx <= 0; ++dx) {
+                    int i = I + dx, j = J + dy, k = K + dz;
+                    if (i < 0 || j < 0 || k < 0 || i >= g.nx || j >= g.ny || k >= g.nz) continue;
+                    cn += s[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] * w8;
+                }
+        acc[0] += x[NF * n + 4] * cn;
+        if (dfdx) {
+            for (int f = 0; f < 4; ++f) dfdx[NF * n + f] = 0.0;
+            dfdx[NF * n + 4] = ((nmask[n] >> 4) & 1) ? 0.0 : cn;
+        }
+    }
+    block_sums<1>(acc, 1, partial);
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_node_mask(const uint8_t *dof_mask, uint8_t *nmask, int64_t nn, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_node_mask, dim3(nblk(nn)), dim3(256), 0, st, dof_mask, nmask, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_blocks(double *D, float *D32, int64_t nn, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_invert_blocks, dim3(nblk(nn, 128)), dim3(128), 0, st, D, D32, nn);
+    return hipGetLastError();
+}
+
+template <typename Tm, typename Tin, typename Tout>
+hipError_t launch_block_apply(const Tm *D, const Tin *v, Tout *z, int64_t nn, bool transpose,
+                              const double *scale_dev, hipStream_t st)
+{
+    if (transpose)
+        hipLaunchKernelGGL((k_block_apply<Tm, Tin, Tout, true>), dim3(nblk(nn)), dim3(256), 0, st,
+                           D, v, z, nn, scale_dev);
+    else
+        hipLaunchKernelGGL((k_block_apply<Tm, Tin, Tout, false>), dim3(nblk(nn)), dim3(256), 0, st,
+                           D, v, z, nn, scale_dev);
+    return hipGetLastError();
+}
+template hipError_t launch_block_apply<double, double, double>(const double *, const double *,
+                                                               double *, int64_t, bool,
+                                                               const double *, hipStream_t);
+template hipError_t launch_block_apply<float, double, float>(const float *, const double *, float *,
+                                                             int64_t, bool, const double *,
+                                                             hipStream_t);
+
+hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
+                           double *partial, hipStream_t st)
+{
+    if (k <= 8)
+        hipLaunchKernelGGL(k_multidot<8>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+    else if (k <= 32)
+        hipLaunchKernelGGL(k_multidot<32>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+    else
+        hipLaunchKernelGGL(k_multidot<65>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h, double *w,
+                             int64_t n, int k2, double *partial, hipStream_t st)
+{
+    const int kk = k > k2 ? k : k2;
+    if (kk <= 8)
+        hipLaunchKernelGGL(k_update_dot<8>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+    else if (kk <= 32)
+        hipLaunchKernelGGL(k_update_dot<32>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+    else
+        hipLaunchKernelGGL(k_update_dot<65>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
+                         bool sqrt_last, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, out, add, k, sqrt_last ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm2_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, a, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, st, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpld(int64_t n, const double *x, double lam, const double *d, double *y,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_xpld, dim3(nblk(n)), dim3(256), 0, st, n, x, lam, d, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_div(int64_t n, const double *x, const double *s, double *y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale_div, dim3(nblk(n)), dim3(256), 0, st, n, x, s, y);
+    return hipGetLastError();
+}
+
+template <typename Tz>
+hipError_t launch_combine(const Tz *Z, int64_t ld, int k, const double *c, double *y, int64_t n,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_combine_vec<Tz>, dim3(nblk(n)), dim3(256), 0, st, Z, ld, k, c, y, n);
+    return hipGetLastError();
+}
+template hipError_t launch_combine<double>(const double *, int64_t, int, const double *, double *,
+                                           int64_t, hipStream_t);
+template hipError_t launch_combine<float>(const float *, int64_t, int, const double *, double *,
+                                          int64_t, hipStream_t);
+
+template <typename Ta, typename Tb>
+hipError_t launch_cast(const Ta *a, Tb *b, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cast<Ta, Tb>), dim3(nblk(n)), dim3(256), 0, st, a, b, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cast<double, float>(const double *, float *, int64_t, hipStream_t);
+template hipError_t launch_cast<float, double>(const float *, double *, int64_t, hipStream_t);
+
+hipError_t launch_compliance(const Geo &g, const double *x, const double *s, const uint8_t *nmask,
+                             double *dfdx, double *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_compliance, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, g, x, s, nmask,
+                       dfdx, partial);
+    return hipGetLastError();
+}
+
+}  // namespace fe

@@ -1,0 +1,302 @@
+"""Python binding of the C-ABI in ``include/fe.h`` (argument marshalling only).
+
+Arrays are torch tensors on the GPU; their device pointers and torch's current
+HIP stream are handed to the library, which does all of the work in its own
+kernels.  Nothing here computes any part of the method, and nothing falls back
+to the CPU: if ``libfe_hip.so`` is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # loaded first: the library then shares torch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfe_hip.so")
+
+FE_OK, FE_PENDING, FE_NOT_CONVERGED = 0, 1, 2
+FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_ENAN, FE_ESTATE = -1, -2, -3, -4, -5
+FE_FP64, FE_FP32 = 0, 1
+
+EXPORTS = [
+    "fe_problem_create", "fe_problem_destroy", "fe_problem_set_phys", "fe_problem_ndof",
+    "fe_residual", "fe_jvp", "fe_adjoint_jtvp", "fe_dR_dgamma", "fe_compliance",
+    "fe_solve_opts_default", "newton_solve", "fe_adjoint_solve", "fe_block_diagonal",
+    "fe_line_search_lambda", "fe_solve_footprint_bytes", "serve_create", "serve_submit",
+    "serve_poll", "serve_times", "serve_destroy", "fe_last_error", "fe_version",
+]
+
+
+class FeGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double)]
+
+
+class FePhys(ctypes.Structure):
+    _fields_ = [("Pr", ctypes.c_double), ("Gr", ctypes.c_double), ("Ck", ctypes.c_double),
+                ("qf", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("q_alpha", ctypes.c_double), ("eg", ctypes.c_double * 3)]
+
+
+class FeSolveOpts(ctypes.Structure):
+    _fields_ = [("rtol_newton", ctypes.c_double), ("rtol_lin", ctypes.c_double),
+                ("max_newton", ctypes.c_int), ("restart", ctypes.c_int),
+                ("max_lin", ctypes.c_int), ("n_refine", ctypes.c_int),
+                ("krylov_op_prec", ctypes.c_int), ("ls_lambda_min", ctypes.c_double),
+                ("verbose", ctypes.c_int)]
+
+
+class FeSolveReport(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int), ("lin_its_total", ctypes.c_int),
+                ("status", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("lambda_last", ctypes.c_double),
+                ("t_total_s", ctypes.c_double), ("t_jv_s", ctypes.c_double),
+                ("t_prec_s", ctypes.c_double), ("t_orth_s", ctypes.c_double),
+                ("t_res_s", ctypes.c_double), ("t_setup_s", ctypes.c_double),
+                ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65)]
+
+    def as_dict(self) -> dict:
+        n = min(self.newton_its, 64)
+        return {"newton_its": self.newton_its, "lin_its_total": self.lin_its_total,
+                "status": self.status, "res0": self.res0, "res_final": self.res_final,
+                "lambda_last": self.lambda_last, "t_total_s": self.t_total_s,
+                "t_jv_s": self.t_jv_s, "t_prec_s": self.t_prec_s, "t_orth_s": self.t_orth_s,
+                "t_res_s": self.t_res_s, "t_setup_s": self.t_setup_s,
+                "lin_its": list(self.lin_its[:n]), "res_hist": list(self.res_hist[:n + 1])}
+
+
+class FeError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed with code {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libfe_hip.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with "
+                              "`python -m paper_1508_04596_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        P = ctypes.POINTER
+        L.fe_problem_create.argtypes = [P(FeGrid), P(FePhys), vp, P(vp)]
+        L.fe_problem_destroy.argtypes = [vp]
+        L.fe_problem_set_phys.argtypes = [vp, P(FePhys)]
+        L.fe_problem_ndof.argtypes = [vp]
+        L.fe_problem_ndof.restype = i64
+        L.fe_residual.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fe_jvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fe_adjoint_jtvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fe_dR_dgamma.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fe_compliance.argtypes = [vp, vp, vp, P(dbl), vp, vp]
+        L.fe_block_diagonal.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fe_solve_opts_default.argtypes = [P(FeSolveOpts)]
+        L.fe_solve_opts_default.restype = None
+        L.newton_solve.argtypes = [vp, vp, vp, vp, P(FeSolveOpts), P(FeSolveReport), vp]
+        L.fe_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, vp, P(FeSolveOpts), P(FeSolveReport), vp]
+        L.fe_line_search_lambda.argtypes = [dbl, dbl, dbl, dbl]
+        L.fe_line_search_lambda.restype = dbl
+        L.fe_solve_footprint_bytes.argtypes = [P(FeGrid), P(FeSolveOpts)]
+        L.fe_solve_footprint_bytes.restype = i64
+        L.serve_create.argtypes = [ctypes.c_size_t, i32, P(vp)]
+        L.serve_submit.argtypes = [vp, P(FeGrid), P(FePhys), vp, vp, P(FeSolveOpts),
+                                   P(ctypes.c_uint64)]
+        L.serve_poll.argtypes = [vp, ctypes.c_uint64, vp, P(FeSolveReport)]
+        L.serve_times.argtypes = [vp, ctypes.c_uint64, P(dbl), P(dbl), P(dbl)]
+        L.serve_destroy.argtypes = [vp]
+        L.fe_last_error.restype = ctypes.c_char_p
+        L.fe_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str, ok=(FE_OK,)) -> int:
+    if rc not in ok:
+        raise FeError(rc, what, lib().fe_last_error().decode())
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_phys(Pr=1.0, Gr=1e3, Ck=0.1, qf=0.881, alpha_max=1e4, q_alpha=1.0, eg=(0.0, 0.0, -1.0)):
+    ph = FePhys()
+    ph.Pr, ph.Gr, ph.Ck, ph.qf, ph.alpha_max, ph.q_alpha = Pr, Gr, Ck, qf, alpha_max, q_alpha
+    for d in range(3):
+        ph.eg[d] = eg[d]
+    return ph
+
+
+def solve_opts(**kw) -> FeSolveOpts:
+    o = FeSolveOpts()
+    lib().fe_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "krylov_op_prec" and isinstance(v, str):
+            v = FE_FP32 if v in ("fp32", "mixed") else FE_FP64
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Owns an ``fe_problem`` handle (grid, parameters, Dirichlet mask, workspace)."""
+
+    def __init__(self, nx, ny, nz, h, phys: FePhys, mask: Optional[torch.Tensor] = None):
+        self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
+        self.n_nodes = (nx + 1) * (ny + 1) * (nz + 1)
+        self.n_dof = 5 * self.n_nodes
+        self.n_el = nx * ny * nz
+        g = FeGrid(nx, ny, nz, h)
+        self._grid = g
+        self.phys = phys
+        handle = ctypes.c_void_p()
+        _check(lib().fe_problem_create(ctypes.byref(g), ctypes.byref(phys),
+                                       _ptr(mask, torch.uint8), ctypes.byref(handle)),
+               "fe_problem_create")
+        self.handle = handle
+
+    @classmethod
+    def from_inputs(cls, p, mask="solve", device="cuda"):
+        """Problem for an ``inputs.Problem`` (``mask`` = 'solve', 'walls' or None)."""
+        m = None
+        if mask is not None:
+            arr = p.mask_solve if mask == "solve" else p.mask_walls
+            m = torch.from_numpy(arr).to(device)
+        ph = make_phys(p.Pr, p.Gr, p.Ck, p.qf, p.alpha_max, p.q_alpha, p.eg)
+        return cls(p.nx, p.ny, p.nz, p.h, ph, m)
+
+    def set_phys(self, phys: FePhys):
+        _check(lib().fe_problem_set_phys(self.handle, ctypes.byref(phys)), "fe_problem_set_phys")
+        self.phys = phys
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().fe_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _prec_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return FE_FP64
+    if t.dtype == torch.float32:
+        return FE_FP32
+    raise ValueError("x/v must be float64 or float32")
+
+
+def fe_residual(prob: Problem, x, gamma, s, out=None, stream=None):
+    out = torch.empty_like(x) if out is None else out
+    _check(lib().fe_residual(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
+                             _ptr(s, torch.float64), _ptr(out, torch.float64), _stream(stream)),
+           "fe_residual")
+    return out
+
+
+def fe_jvp(prob: Problem, x, gamma, s, v, out=None, stream=None):
+    prec = _prec_of(x)
+    out = torch.empty_like(v) if out is None else out
+    _check(lib().fe_jvp(prob.handle, prec, _ptr(x, x.dtype), _ptr(gamma, torch.float64),
+                        _ptr(s, torch.float64), _ptr(v, x.dtype), _ptr(out, x.dtype),
+                        _stream(stream)), "fe_jvp")
+    return out
+
+
+def fe_adjoint_jtvp(prob: Problem, x, gamma, s, w, out=None, stream=None):
+    prec = _prec_of(x)
+    out = torch.empty_like(w) if out is None else out
+    _check(lib().fe_adjoint_jtvp(prob.handle, prec, _ptr(x, x.dtype), _ptr(gamma, torch.float64),
+                                 _ptr(s, torch.float64), _ptr(w, x.dtype), _ptr(out, x.dtype),
+                                 _stream(stream)), "fe_adjoint_jtvp")
+    return out
+
+
+def fe_dR_dgamma(prob: Problem, x, gamma, s, lam, out=None, stream=None):
+    out = torch.empty_like(gamma) if out is None else out
+    _check(lib().fe_dR_dgamma(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
+                              _ptr(s, torch.float64), _ptr(lam, torch.float64),
+                              _ptr(out, torch.float64), _stream(stream)), "fe_dR_dgamma")
+    return out
+
+
+def fe_compliance(prob: Problem, x, s, dfdx=None, stream=None):
+    f = ctypes.c_double()
+    _check(lib().fe_compliance(prob.handle, _ptr(x, torch.float64), _ptr(s, torch.float64),
+                               ctypes.byref(f), _ptr(dfdx, torch.float64), _stream(stream)),
+           "fe_compliance")
+    return f.value
+
+
+def fe_block_diagonal(prob: Problem, x, gamma, s, out=None, stream=None):
+    out = torch.empty(25 * prob.n_nodes, dtype=torch.float64, device=x.device) if out is None else out
+    _check(lib().fe_block_diagonal(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
+                                   _ptr(s, torch.float64), _ptr(out, torch.float64),
+                                   _stream(stream)), "fe_block_diagonal")
+    return out
+
+
+def newton_solve(prob: Problem, gamma, s, x, opts: Optional[FeSolveOpts] = None, stream=None,
+                 allow_not_converged=False) -> dict:
+    rep = FeSolveReport()
+    o = solve_opts() if opts is None else opts
+    rc = lib().newton_solve(prob.handle, _ptr(gamma, torch.float64), _ptr(s, torch.float64),
+                            _ptr(x, torch.float64), ctypes.byref(o), ctypes.byref(rep),
+                            _stream(stream))
+    _check(rc, "newton_solve", ok=(FE_OK, FE_NOT_CONVERGED) if allow_not_converged else (FE_OK,))
+    return rep.as_dict()
+
+
+def fe_adjoint_solve(prob: Problem, x, gamma, s, rhs, lam=None, opts: Optional[FeSolveOpts] = None,
+                     stream=None, allow_not_converged=False):
+    lam = torch.empty_like(rhs) if lam is None else lam
+    rep = FeSolveReport()
+    o = solve_opts() if opts is None else opts
+    rc = lib().fe_adjoint_solve(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
+                                _ptr(s, torch.float64), _ptr(rhs, torch.float64),
+                                _ptr(lam, torch.float64), ctypes.byref(o), ctypes.byref(rep),
+                                _stream(stream))
+    _check(rc, "fe_adjoint_solve", ok=(FE_OK, FE_NOT_CONVERGED) if allow_not_converged else (FE_OK,))
+    return lam, rep.as_dict()
+
+
+def fe_line_search_lambda(phi0, phi_half, phi1, lambda_min=0.05) -> float:
+    return float(lib().fe_line_search_lambda(phi0, phi_half, phi1, lambda_min))
+
+
+def fe_solve_footprint_bytes(nx, ny, nz, h=1.0, opts: Optional[FeSolveOpts] = None) -> int:
+    g = FeGrid(nx, ny, nz, h)
+    return int(lib().fe_solve_footprint_bytes(ctypes.byref(g), ctypes.byref(opts) if opts else None))
+
+
+def fe_version() -> str:
+    return lib().fe_version().decode()

@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point ``include/fe.h`` declares, rejects bad arguments before
+touching the device, and its line-search rule matches the scripted cases."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "fe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def fe():
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def test_library_exports_every_declared_entry_point(fe):
+    names = declared_functions()
+    assert "fe_jvp" in names and "newton_solve" in names and "serve_submit" in names
+    L = fe.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+    assert set(fe.EXPORTS) <= set(names)
+
+
+def test_version_and_error_string(fe):
+    assert "gfx950" in fe.fe_version()
+
+
+def test_bad_grid_is_rejected_before_any_device_call(fe):
+    import ctypes
+    L = fe.lib()
+    h = ctypes.c_void_p()
+    ph = fe.make_phys()
+    for g in (fe.FeGrid(0, 4, 4, 0.1), fe.FeGrid(4, -1, 4, 0.1), fe.FeGrid(4, 4, 4, 0.0)):
+        rc = L.fe_problem_create(ctypes.byref(g), ctypes.byref(ph), None, ctypes.byref(h))
+        assert rc == fe.FE_EINVAL
+        assert "grid" in L.fe_last_error().decode()
+    bad = fe.make_phys(Ck=0.0)
+    rc = L.fe_problem_create(ctypes.byref(fe.FeGrid(2, 2, 2, 0.5)), ctypes.byref(bad), None,
+                             ctypes.byref(h))
+    assert rc == fe.FE_EINVAL
+
+
+def test_null_handle_is_rejected(fe):
+    L = fe.lib()
+    assert L.fe_residual(None, None, None, None, None, None) == fe.FE_EINVAL
+    assert L.fe_jvp(None, 0, None, None, None, None, None, None) == fe.FE_EINVAL
+    assert L.newton_solve(None, None, None, None, None, None, None) == fe.FE_EINVAL
+
+
+def test_line_search_rule_on_scripted_norms(fe):
+    ls = fe.fe_line_search_lambda
+    assert ls(4.0, 1.0, 0.0) == 1.0
+    q = lambda l: 2.0 + 5.0 * (l - 0.3) ** 2
+    assert ls(q(0), q(0.5), q(1)) == pytest.approx(0.3, rel=1e-14)
+    q = lambda l: (l - 3.0) ** 2
+    assert ls(q(0), q(0.5), q(1)) == 1.0
+    q = lambda l: (l + 1.0) ** 2
+    assert ls(q(0), q(0.5), q(1)) == 0.05
+    assert ls(1.0, 1.2, 1.3) == 0.5
+    assert ls(1.0, 0.98, 0.9) == 1.0
+
+
+def test_footprint_grows_with_grid_and_restart(fe):
+    a = fe.fe_solve_footprint_bytes(16, 16, 16)
+    b = fe.fe_solve_footprint_bytes(32, 32, 32)
+    assert 0 < a < b
+    o = fe.solve_opts(restart=10)
+    assert fe.fe_solve_footprint_bytes(32, 32, 32, opts=o) < b

@@ -1,0 +1,165 @@
+"""GPU parity of the HIP operators against the CPU oracle, through the C-ABI.
+
+Sizes span several 8x8x4 element tiles with ragged tails in every direction;
+the bench workload (64^3) is compared in full, element by element.  FP64
+operators must match to 1e-11 relative (norm-wise and per entry against the
+vector's largest entry); the FP32 product is compared at its own precision.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solve as osolve
+from paper_1508_04596_amd import inputs
+from tests.helpers import assert_parity, rel_norm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+CASES = [
+    ("C1 8^3", lambda: inputs.config(1)),
+    ("ragged 13x7x9", lambda: inputs.scaled_config(13, 7, 9, 3e3, seed=77)),
+    ("ragged 17x10x5 Gr=1e5", lambda: inputs.scaled_config(17, 10, 5, 1e5, seed=78, extra_passes=1)),
+    ("single element", lambda: inputs.tiny_problem(1, 1, 1, Gr=5e2)),
+    ("thin 2x21x3", lambda: inputs.tiny_problem(2, 21, 3, Gr=2e4)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("mask", ["walls", "solve"])
+def test_residual_jv_jtv_dg_parity(fe, name, make, mask):
+    p = make()
+    print(f"[parity] {name} mask={mask}", flush=True)
+    m = p.mask_walls if mask == "walls" else p.mask_solve
+    x = inputs.random_state(p, 2001, mask=m)
+    prob = fe.Problem.from_inputs(p, mask=mask)
+    g, s, xd = dev(p.gamma), dev(p.s), dev(x)
+    r = host(fe.fe_residual(prob, xd, g, s))
+    assert_parity(r, oracle.residual(p, x, mask=m), what="residual")
+    for seed in (1, 2, 3):
+        v = inputs.random_direction(p, seed, mask=m)
+        # raw direction with nonzero prescribed entries: the output rows there must be v
+        vr = np.random.default_rng(seed).standard_normal(p.n_dof)
+        vr[~m.astype(bool)] = v[~m.astype(bool)]
+        jv = host(fe.fe_jvp(prob, xd, g, s, dev(vr)))
+        ref = oracle.jvp(p, x, vr, mask=m)
+        assert_parity(jv, ref, what="jv")
+        np.testing.assert_array_equal(jv[m.astype(bool)], vr[m.astype(bool)])
+        jt = host(fe.fe_adjoint_jtvp(prob, xd, g, s, dev(vr)))
+        assert_parity(jt, oracle.jtvp(p, x, vr, mask=m), what="jtv")
+        lam = inputs.random_direction(p, seed + 10, mask=m)
+        dg = host(fe.fe_dR_dgamma(prob, xd, g, s, dev(lam)))
+        assert_parity(dg, oracle.dR_dgamma(p, x, lam, mask=m), what="dR/dgamma")
+    prob.close()
+
+
+def test_inner_product_identity_on_gpu(fe):
+    p = inputs.scaled_config(13, 7, 9, 3e3, seed=5)
+    prob = fe.Problem.from_inputs(p, mask="walls")
+    x = dev(inputs.random_state(p, 9))
+    g, s = dev(p.gamma), dev(p.s)
+    v = dev(inputs.random_direction(p, 10))
+    w = dev(inputs.random_direction(p, 11))
+    a = float(torch.dot(fe.fe_jvp(prob, x, g, s, v), w))
+    b = float(torch.dot(v, fe.fe_adjoint_jtvp(prob, x, g, s, w)))
+    assert abs(a - b) <= 1e-12 * abs(a)
+    prob.close()
+
+
+def test_fp32_jv_against_oracle(fe):
+    p = inputs.config(1)
+    prob = fe.Problem.from_inputs(p, mask="walls")
+    x = inputs.random_state(p, 2001)
+    g, s = dev(p.gamma), dev(p.s)
+    for seed in (1, 2):
+        v = inputs.random_direction(p, seed)
+        jv32 = host(fe.fe_jvp(prob, dev(x, torch.float32), g, s, dev(v, torch.float32)))
+        # the oracle at the FP32-rounded inputs isolates the FP32 arithmetic error
+        xr = x.astype(np.float32).astype(np.float64)
+        vr = v.astype(np.float32).astype(np.float64)
+        ref = oracle.jvp(p, xr, vr)
+        err = rel_norm(jv32, ref)
+        print(f"[fp32] C1 jv rel err {err:.3e}")
+        assert err <= 2e-5
+        jt32 = host(fe.fe_adjoint_jtvp(prob, dev(x, torch.float32), g, s, dev(v, torch.float32)))
+        assert rel_norm(jt32, oracle.jtvp(p, xr, vr)) <= 2e-5
+    prob.close()
+
+
+def test_block_diagonal_parity(fe):
+    p = inputs.scaled_config(11, 9, 6, 5e3, seed=21)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = inputs.random_state(p, 31, mask=p.mask_solve)
+    D = host(fe.fe_block_diagonal(prob, dev(x), dev(p.gamma), dev(p.s))).reshape(-1, 5, 5)
+    Ke = oracle.element_jacobians(p, x)
+    dofs = osolve.element_dofs(p)
+    ref = np.zeros((p.n_nodes, 5, 5))
+    for a in range(8):
+        nodes = dofs[:, 5 * a] // 5
+        np.add.at(ref, nodes, Ke[:, 5 * a:5 * a + 5, 5 * a:5 * a + 5])
+    m = p.mask_solve.reshape(-1, 5).astype(bool)
+    for f in range(5):
+        for f2 in range(5):
+            sel = m[:, f] | m[:, f2]
+            ref[sel, f, f2] = 1.0 if f == f2 else 0.0
+    assert_parity(D.reshape(-1), ref.reshape(-1), what="block diagonal")
+    prob.close()
+
+
+def test_compliance_parity(fe):
+    p = inputs.scaled_config(12, 9, 10, 1e3, seed=3)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = inputs.random_state(p, 12, mask=p.mask_solve)
+    dfdx = torch.empty(p.n_dof, dtype=torch.float64, device="cuda")
+    f = fe.fe_compliance(prob, dev(x), dev(p.s), dfdx)
+    assert f == pytest.approx(osolve.compliance(p, x), rel=1e-13)
+    assert_parity(host(dfdx), osolve.compliance_gradient_x(p, mask="solve"), tol=1e-14)
+    prob.close()
+
+
+def test_bench_workload_full_size_parity(fe):
+    """64^3 (the bench workload) in full: residual, J v and J^T w, every entry."""
+    p = inputs.config(2)
+    print("[parity] C2 64^3 full size", flush=True)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = inputs.random_state(p, 2001, mask=p.mask_solve)
+    v = inputs.random_direction(p, 1, mask=p.mask_solve)
+    g, s, xd = dev(p.gamma), dev(p.s), dev(x)
+    assert_parity(host(fe.fe_residual(prob, xd, g, s)), oracle.residual(p, x, mask="solve"), what="R")
+    assert_parity(host(fe.fe_jvp(prob, xd, g, s, dev(v))), oracle.jvp(p, x, v, mask="solve"), what="Jv")
+    prob.close()
+
+
+def test_repeatable_bitwise(fe):
+    p = inputs.scaled_config(24, 16, 12, 1e4, seed=8)
+    prob = fe.Problem.from_inputs(p, mask="walls")
+    x = dev(inputs.random_state(p, 4))
+    v = dev(inputs.random_direction(p, 5))
+    g, s = dev(p.gamma), dev(p.s)
+    a = fe.fe_jvp(prob, x, g, s, v).clone()
+    b = fe.fe_jvp(prob, x, g, s, v).clone()
+    r1 = fe.fe_residual(prob, x, g, s).clone()
+    r2 = fe.fe_residual(prob, x, g, s).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(r1, r2)
+    prob.close()

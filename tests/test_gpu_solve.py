@@ -1,0 +1,89 @@
+"""GPU Newton / adjoint solves against the oracle (backward error and forward difference)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solve as osolve
+from paper_1508_04596_amd import inputs
+from tests.helpers import rel_norm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_c1_backward_error(fe, prec):
+    p = inputs.config(1)
+    print(f"[solve] C1 {prec}", flush=True)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    rep = fe.newton_solve(prob, dev(p.gamma), dev(p.s), x,
+                          fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec))
+    xs = host(x)
+    r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+    r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
+    print(f"[solve] {prec}: newton {rep['newton_its']} lin {rep['lin_its']} rel {r / r0:.3e}")
+    assert r <= 1e-8 * r0 * 1.0001
+    x_or, _, _ = osolve.newton(p, rtol=1e-13)
+    print(f"[solve] forward rel diff {rel_norm(xs, x_or):.3e}")
+    assert rel_norm(xs, x_or) <= 1e-5
+    prob.close()
+
+
+def test_newton_c1_tight_matches_oracle_solution(fe):
+    p = inputs.config(1)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    fe.newton_solve(prob, dev(p.gamma), dev(p.s), x,
+                    fe.solve_opts(rtol_newton=1e-13, rtol_lin=1e-12, max_lin=5000))
+    x_or, _, _ = osolve.newton(p, rtol=1e-13)
+    err = rel_norm(host(x), x_or)
+    print(f"[solve] tight forward rel diff {err:.3e}")
+    assert err <= 1e-10
+    prob.close()
+
+
+def test_adjoint_gradient_against_oracle(fe):
+    p = inputs.scaled_config(10, 10, 10, 2e3, seed=44, extra_passes=1)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    g, s = dev(p.gamma), dev(p.s)
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    fe.newton_solve(prob, g, s, x, fe.solve_opts(rtol_newton=1e-12, rtol_lin=1e-10))
+    xs = host(x)
+    lam_or, grad_or = osolve.adjoint_gradient(p, xs)
+    c = torch.empty_like(x)
+    fe.fe_compliance(prob, x, s, c)
+    lam, rep = fe.fe_adjoint_solve(prob, x, g, s, c, opts=fe.solve_opts(rtol_lin=1e-12, max_lin=5000))
+    dg = fe.fe_dR_dgamma(prob, x, g, s, lam)
+    grad = -host(dg)
+    print(f"[adjoint] its {rep['lin_its_total']} lam err {rel_norm(host(lam), lam_or):.3e} "
+          f"grad err {rel_norm(grad, grad_or):.3e}")
+    # lambda's pressure part is weakly determined (closed cavity, one pinned
+    # pressure): compare it through the oracle's backward error, and the
+    # gradient, which does not see that part, directly
+    lam_h = host(lam)
+    cc = osolve.compliance_gradient_x(p, mask="solve")
+    bwd = np.linalg.norm(oracle.jtvp(p, xs, lam_h, mask="solve") - cc) / np.linalg.norm(cc)
+    print(f"[adjoint] oracle backward error of lambda {bwd:.3e}")
+    assert bwd <= 1e-10
+    assert rel_norm(grad, grad_or) <= 1e-9
+    prob.close()
