@@ -124,7 +124,18 @@ typedef struct {
     fe_prec krylov_op_prec; /* FE_FP64, or FE_FP32 for FP32 J v and preconditioner */
     double ls_lambda_min;   /* lower clamp of the line-search factor (default 0.05) */
     int verbose;            /* 0 silent, 1 one line per Newton step on stderr */
+    int precond;            /* FE_PC_AUTO (default), FE_PC_BJACOBI or FE_PC_MULTIGRID */
+    int mg_nu;              /* multigrid: smoothing sweeps before and after (default 2) */
+    double mg_omega;        /* multigrid: block-Jacobi damping (default 0.6) */
 } fe_solve_opts;
+
+/* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free
+ * geometric multigrid V-cycle (Sec. "Solving the linear systems") whose levels
+ * rediscretise the operator on grids with half the elements per direction,
+ * with damped block-Jacobi smoothing and a direct solve on the coarsest level.
+ * FE_PC_AUTO takes multigrid when every element count halves evenly down to a
+ * coarsest level of at most 2400 DOF, else block-Jacobi. */
+enum { FE_PC_AUTO = 0, FE_PC_BJACOBI = 1, FE_PC_MULTIGRID = 2 };
 
 typedef struct {
     int newton_its, lin_its_total, status;  /* status: FE_OK / FE_NOT_CONVERGED / error */
@@ -133,6 +144,8 @@ typedef struct {
     double t_jv_s, t_prec_s, t_orth_s, t_res_s, t_setup_s; /* stream time per phase */
     int lin_its[64];                        /* Krylov iterations of the first 64 Newton steps */
     double res_hist[65];                    /* |R| after each Newton step, [0] = |R(x0)| */
+    int precond;                            /* preconditioner used (FE_PC_BJACOBI / FE_PC_MULTIGRID) */
+    int mg_levels;                          /* multigrid levels (0 without multigrid) */
 } fe_solve_report;
 
 /* Fill opts with the defaults listed above. */

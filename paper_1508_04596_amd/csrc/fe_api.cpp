@@ -35,6 +35,12 @@ Geo make_geo(const fe_grid &g, const fe_phys &ph)
     o.qf = ph.qf;
     o.amax = ph.alpha_max;
     o.qa = ph.q_alpha;
+    const double h = g.h;
+    o.W = 0.125 * h * h * h;
+    o.gs = 2.0 * 1.7320508075688772935 / h;
+    o.inv16h2 = 1.0 / (16.0 * h * h);
+    o.cvisc = 16.0 * ph.Pr * ph.Pr / (h * h * h * h);
+    o.c16h4 = 16.0 / (h * h * h * h);
     return o;
 }
 

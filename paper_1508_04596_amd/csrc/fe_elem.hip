@@ -29,6 +29,16 @@ namespace {
 
 constexpr double QG = 0.57735026918962576451;  // Gauss abscissa 1/sqrt(3)
 
+// Gauss loop unrolled (compile-time signs) for FP32, rolled for FP64 where the
+// unrolled form runs out of registers.
+#ifndef FE_UNROLL64
+#define FE_UNROLL64 0
+#endif
+template <typename T>
+struct Unroll { static constexpr bool value = true; };
+template <>
+struct Unroll<double> { static constexpr bool value = FE_UNROLL64 != 0; };
+
 template <typename T>
 struct EC {
     T W;        // (h/2)^3, Gauss weight times Jacobian determinant
@@ -44,17 +54,16 @@ template <typename T>
 __device__ __forceinline__ EC<T> make_ec(const Geo &g)
 {
     EC<T> c;
-    double h = g.h;
-    c.W = (T)(0.125 * h * h * h);
-    c.gs = (T)(2.0 / (h * QG));
+    c.W = (T)g.W;
+    c.gs = (T)g.gs;
     c.Pr = (T)g.Pr;
     c.B = (T)g.B;
     c.eg0 = (T)g.eg[0];
     c.eg1 = (T)g.eg[1];
     c.eg2 = (T)g.eg[2];
-    c.inv16h2 = (T)(1.0 / (16.0 * h * h));
-    c.cvisc = (T)(16.0 * g.Pr * g.Pr / (h * h * h * h));
-    c.c16h4 = (T)(16.0 / (h * h * h * h));
+    c.inv16h2 = (T)g.inv16h2;
+    c.cvisc = (T)g.cvisc;
+    c.c16h4 = (T)g.c16h4;
     c.q0 = (T)0.125;
     c.q1 = (T)(0.125 * QG);
     c.q2 = (T)(0.125 / 3.0);
@@ -104,50 +113,86 @@ __device__ __forceinline__ void to_modal(T f[8], const EC<T> &c)
     f[7] *= c.q3;
 }
 
-// Value and physical gradient at Gauss point G (bits = +/- side per direction).
-template <int G, typename T>
-__device__ __forceinline__ void eval_vg(const T m[8], T gs, T &val, T &dx, T &dy, T &dz)
+// Signs of the Gauss point coordinates (+1 / -1 per direction) and their
+// products, either as compile-time constants (fully unrolled Gauss loop) or as
+// run-time values (rolled loop, lower register pressure).
+template <int G>
+struct SgCT {
+    static constexpr double sx = (G & 1) ? 1.0 : -1.0;
+    static constexpr double sy = (G & 2) ? 1.0 : -1.0;
+    static constexpr double sz = (G & 4) ? 1.0 : -1.0;
+    static constexpr double sxy = sx * sy, sxz = sx * sz, syz = sy * sz, sxyz = sx * sy * sz;
+};
+
+template <typename T>
+struct SgRT {
+    T sx, sy, sz, sxy, sxz, syz, sxyz;
+    __device__ __forceinline__ explicit SgRT(int g)
+    {
+        sx = (g & 1) ? T(1) : T(-1);
+        sy = (g & 2) ? T(1) : T(-1);
+        sz = (g & 4) ? T(1) : T(-1);
+        sxy = sx * sy;
+        sxz = sx * sz;
+        syz = sy * sz;
+        sxyz = sxy * sz;
+    }
+};
+
+// Value and physical gradient at the Gauss point with signs SG.
+template <typename T, typename SGT>
+__device__ __forceinline__ void eval_vg(const SGT &SG, const T m[8], T gs, T &val, T &dx, T &dy,
+                                        T &dz)
 {
-    constexpr T sx = (G & 1) ? T(1) : T(-1);
-    constexpr T sy = (G & 2) ? T(1) : T(-1);
-    constexpr T sz = (G & 4) ? T(1) : T(-1);
-    T t1 = sx * m[1], t2 = sy * m[2], t3 = (sx * sy) * m[3], t4 = sz * m[4];
-    T t5 = (sx * sz) * m[5], t6 = (sy * sz) * m[6], t7 = (sx * sy * sz) * m[7];
+    T t1 = T(SG.sx) * m[1], t2 = T(SG.sy) * m[2], t3 = T(SG.sxy) * m[3], t4 = T(SG.sz) * m[4];
+    T t5 = T(SG.sxz) * m[5], t6 = T(SG.syz) * m[6], t7 = T(SG.sxyz) * m[7];
     T ax = (t1 + t3) + (t5 + t7);
     T ay = (t2 + t3) + (t6 + t7);
     T az = (t4 + t5) + (t6 + t7);
     val = ((m[0] + t2) + (t4 + t6)) + ax;
-    dx = (sx * gs) * ax;
-    dy = (sy * gs) * ay;
-    dz = (sz * gs) * az;
+    dx = (T(SG.sx) * gs) * ax;
+    dy = (T(SG.sy) * gs) * ay;
+    dz = (T(SG.sz) * gs) * az;
 }
 
-template <int G, typename T>
-__device__ __forceinline__ void eval_g(const T m[8], T gs, T &dx, T &dy, T &dz)
+template <typename T, typename SGT>
+__device__ __forceinline__ void eval_g(const SGT &SG, const T m[8], T gs, T &dx, T &dy, T &dz)
 {
     T v;
-    eval_vg<G>(m, gs, v, dx, dy, dz);
+    eval_vg(SG, m, gs, v, dx, dy, dz);
 }
 
-// Y[m] += S[G][m] * (c + gs * sum_{d in m} s_d C_d): the modal test-side sum.
-template <int G, typename T>
-__device__ __forceinline__ void accum(T Y[8], T c, T Cx, T Cy, T Cz, T gs)
+// Y[m] += S[g][m] * (c + gs * sum_{d in m} s_d C_d): the modal test-side sum.
+template <typename T, typename SGT>
+__device__ __forceinline__ void accum(const SGT &SG, T Y[8], T c, T Cx, T Cy, T Cz, T gs)
 {
-    constexpr T sx = (G & 1) ? T(1) : T(-1);
-    constexpr T sy = (G & 2) ? T(1) : T(-1);
-    constexpr T sz = (G & 4) ? T(1) : T(-1);
-    T px = (sx * gs) * Cx, py = (sy * gs) * Cy, pz = (sz * gs) * Cz;
+    T px = (T(SG.sx) * gs) * Cx, py = (T(SG.sy) * gs) * Cy, pz = (T(SG.sz) * gs) * Cz;
     T e1 = c + px, e2 = c + py, e4 = c + pz;
     T e3 = e1 + py, e5 = e1 + pz, e6 = e2 + pz, e7 = e3 + pz;
     Y[0] += c;
-    Y[1] += sx * e1;
-    Y[2] += sy * e2;
-    Y[3] += (sx * sy) * e3;
-    Y[4] += sz * e4;
-    Y[5] += (sx * sz) * e5;
-    Y[6] += (sy * sz) * e6;
-    Y[7] += (sx * sy * sz) * e7;
+    Y[1] += T(SG.sx) * e1;
+    Y[2] += T(SG.sy) * e2;
+    Y[3] += T(SG.sxy) * e3;
+    Y[4] += T(SG.sz) * e4;
+    Y[5] += T(SG.sxz) * e5;
+    Y[6] += T(SG.syz) * e6;
+    Y[7] += T(SG.sxyz) * e7;
 }
+
+// Run BODY(sg) over the eight Gauss points: unrolled with compile-time signs
+// when UNR, else as a rolled loop with run-time signs.
+#define FE_GAUSS_LOOP(UNR, T, BODY)                                              \
+    if (UNR) {                                                                   \
+        { SgCT<0> sg; BODY(sg) } { SgCT<1> sg; BODY(sg) }                        \
+        { SgCT<2> sg; BODY(sg) } { SgCT<3> sg; BODY(sg) }                        \
+        { SgCT<4> sg; BODY(sg) } { SgCT<5> sg; BODY(sg) }                        \
+        { SgCT<6> sg; BODY(sg) } { SgCT<7> sg; BODY(sg) }                        \
+    } else {                                                                     \
+        _Pragma("unroll 1") for (int g_ = 0; g_ < 8; ++g_) {                     \
+            SgRT<T> sg(g_);                                                      \
+            BODY(sg)                                                             \
+        }                                                                        \
+    }
 
 // Modal test-side sums -> nodal rows: out_a = W sum_m S[a][m] q^|m|/8 Y[m].
 template <typename T>
@@ -252,7 +297,7 @@ __device__ __forceinline__ bool shared_dir(int l, int I, int n, int T_)
 // ---- element bodies -------------------------------------------------------------
 
 // Residual rows of one element (Galerkin + SUPG + PSPG, see header comment).
-template <typename T>
+template <typename T, bool UNR>
 __device__ __forceinline__ void elem_residual(const EC<T> &c, const T (*sx)[BOXN], const int nb[8],
                                               T alpha, T Kc, T s, T out[NF][8])
 {
@@ -282,14 +327,14 @@ __device__ __forceinline__ void elem_residual(const EC<T> &c, const T (*sx)[BOXN
 #pragma unroll
         for (int m = 0; m < 8; ++m) out[f][m] = T(0);
     const T gs = c.gs;
-#define FE_RES_GP(G)                                                                         \
+#define FE_RES_GP(SG)                                                                         \
     {                                                                                        \
         T u[3], Gd[3][3];                                                                    \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
-            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg(SG, mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
         T pv, gp0, gp1, gp2, Tv, gT0, gT1, gT2;                                              \
-        eval_vg<G>(mp, gs, pv, gp0, gp1, gp2);                                               \
-        eval_vg<G>(mT, gs, Tv, gT0, gT1, gT2);                                               \
+        eval_vg(SG, mp, gs, pv, gp0, gp1, gp2);                                               \
+        eval_vg(SG, mT, gs, Tv, gT0, gT1, gT2);                                               \
         T conv[3], rM[3];                                                                    \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
         const T gpv[3] = {gp0, gp1, gp2};                                                    \
@@ -308,23 +353,22 @@ __device__ __forceinline__ void elem_residual(const EC<T> &c, const T (*sx)[BOXN
             if (i == 0) C0 -= pv;                                                            \
             if (i == 1) C1 -= pv;                                                            \
             if (i == 2) C2 -= pv;                                                            \
-            accum<G>(out[i], conv[i], C0, C1, C2, gs);                                       \
+            accum(SG, out[i], conv[i], C0, C1, C2, gs);                                       \
         }                                                                                    \
-        accum<G>(out[3], Gd[0][0] + Gd[1][1] + Gd[2][2], tau * rM[0], tau * rM[1],           \
+        accum(SG, out[3], Gd[0][0] + Gd[1][1] + Gd[2][2], tau * rM[0], tau * rM[1],           \
                  tau * rM[2], gs);                                                           \
         T trT = tauT * rT;                                                                   \
-        accum<G>(out[4], rT, Kc * gT0 + u[0] * trT, Kc * gT1 + u[1] * trT,                   \
+        accum(SG, out[4], rT, Kc * gT0 + u[0] * trT, Kc * gT1 + u[1] * trT,                   \
                  Kc * gT2 + u[2] * trT, gs);                                                 \
     }
-    FE_RES_GP(0) FE_RES_GP(1) FE_RES_GP(2) FE_RES_GP(3)
-    FE_RES_GP(4) FE_RES_GP(5) FE_RES_GP(6) FE_RES_GP(7)
+    FE_GAUSS_LOOP(UNR, T, FE_RES_GP)
 #undef FE_RES_GP
 #pragma unroll
     for (int f = 0; f < NF; ++f) from_modal(out[f], c);
 }
 
 // Directional derivative J_e v_e (exact linearisation, including d tau).
-template <typename T>
+template <typename T, bool UNR>
 __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
                                         const int nb[8], T alpha, T Kc, T s, T out[NF][8])
 {
@@ -363,18 +407,18 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], con
 #pragma unroll
         for (int m = 0; m < 8; ++m) out[f][m] = T(0);
     const T gs = c.gs;
-#define FE_JV_GP(G)                                                                          \
+#define FE_JV_GP(SG)                                                                          \
     {                                                                                        \
         T u[3], Gd[3][3], du[3], dG[3][3];                                                   \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
-            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
-            eval_vg<G>(md[i], gs, du[i], dG[i][0], dG[i][1], dG[i][2]);                      \
+            eval_vg(SG, mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg(SG, md[i], gs, du[i], dG[i][0], dG[i][1], dG[i][2]);                      \
         }                                                                                    \
         T gp[3], Tv, gT[3], dpv, gdp[3], dTv, gdT[3];                                        \
-        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
-        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
-        eval_vg<G>(mdp, gs, dpv, gdp[0], gdp[1], gdp[2]);                                    \
-        eval_vg<G>(mdT, gs, dTv, gdT[0], gdT[1], gdT[2]);                                    \
+        eval_g(SG, mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg(SG, mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_vg(SG, mdp, gs, dpv, gdp[0], gdp[1], gdp[2]);                                    \
+        eval_vg(SG, mdT, gs, dTv, gdT[0], gdT[1], gdT[2]);                                    \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
         T rM[3], dgal[3], A[3], Bm[3];                                                       \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
@@ -397,16 +441,15 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], con
             if (i == 0) C0 -= dpv;                                                           \
             if (i == 1) C1 -= dpv;                                                           \
             if (i == 2) C2 -= dpv;                                                           \
-            accum<G>(out[i], dgal[i], C0, C1, C2, gs);                                       \
+            accum(SG, out[i], dgal[i], C0, C1, C2, gs);                                       \
         }                                                                                    \
-        accum<G>(out[3], dG[0][0] + dG[1][1] + dG[2][2], A[0], A[1], A[2], gs);              \
+        accum(SG, out[3], dG[0][0] + dG[1][1] + dG[2][2], A[0], A[1], A[2], gs);              \
         T AT = dtauT * rT + tauT * drT, BT = tauT * rT;                                      \
-        accum<G>(out[4], drT, Kc * gdT[0] + u[0] * AT + du[0] * BT,                          \
+        accum(SG, out[4], drT, Kc * gdT[0] + u[0] * AT + du[0] * BT,                          \
                  Kc * gdT[1] + u[1] * AT + du[1] * BT, Kc * gdT[2] + u[2] * AT + du[2] * BT, \
                  gs);                                                                        \
     }
-    FE_JV_GP(0) FE_JV_GP(1) FE_JV_GP(2) FE_JV_GP(3)
-    FE_JV_GP(4) FE_JV_GP(5) FE_JV_GP(6) FE_JV_GP(7)
+    FE_GAUSS_LOOP(UNR, T, FE_JV_GP)
 #undef FE_JV_GP
 #pragma unroll
     for (int f = 0; f < NF; ++f) from_modal(out[f], c);
@@ -417,7 +460,7 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], con
 // (temperature rows) are interpolated from w_e; the multipliers of the varied
 // strong residuals are mu = tau (u.grad Lambda + grad Pi) and muT = tauT u.grad Theta;
 // the element-level tau variation is applied after the Gauss loop.
-template <typename T>
+template <typename T, bool UNR>
 __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
                                          const int nb[8], T alpha, T Kc, T s, T out[NF][8])
 {
@@ -454,18 +497,18 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
 #pragma unroll
         for (int m = 0; m < 8; ++m) out[f][m] = T(0);
     const T gs = c.gs;
-#define FE_JTV_GP(G)                                                                         \
+#define FE_JTV_GP(SG)                                                                         \
     {                                                                                        \
         T u[3], Gd[3][3], L[3], LG[3][3];                                                    \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
-            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
-            eval_vg<G>(mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
+            eval_vg(SG, mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg(SG, mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
         }                                                                                    \
         T gp[3], Tv, gT[3], Pv, gP[3], Th, gTh[3];                                           \
-        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
-        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
-        eval_vg<G>(mP, gs, Pv, gP[0], gP[1], gP[2]);                                         \
-        eval_vg<G>(mTh, gs, Th, gTh[0], gTh[1], gTh[2]);                                     \
+        eval_g(SG, mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg(SG, mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_vg(SG, mP, gs, Pv, gP[0], gP[1], gP[2]);                                         \
+        eval_vg(SG, mTh, gs, Th, gTh[0], gTh[1], gTh[2]);                                     \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
         T rM[3], uL[3], mI[3], LM[3];                                                        \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
@@ -492,15 +535,14 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
             if (j == 0) C0 += Pv;                                                            \
             if (j == 1) C1 += Pv;                                                            \
             if (j == 2) C2 += Pv;                                                            \
-            accum<G>(out[j], cj, C0, C1, C2, gs);                                            \
+            accum(SG, out[j], cj, C0, C1, C2, gs);                                            \
         }                                                                                    \
-        accum<G>(out[3], -(LG[0][0] + LG[1][1] + LG[2][2]), mI[0], mI[1], mI[2], gs);        \
-        accum<G>(out[4], c.B * (egv[0] * LM[0] + egv[1] * LM[1] + egv[2] * LM[2]),           \
+        accum(SG, out[3], -(LG[0][0] + LG[1][1] + LG[2][2]), mI[0], mI[1], mI[2], gs);        \
+        accum(SG, out[4], c.B * (egv[0] * LM[0] + egv[1] * LM[1] + egv[2] * LM[2]),           \
                  Kc * gTh[0] + ThM * u[0], Kc * gTh[1] + ThM * u[1], Kc * gTh[2] + ThM * u[2], \
                  gs);                                                                        \
     }
-    FE_JTV_GP(0) FE_JTV_GP(1) FE_JTV_GP(2) FE_JTV_GP(3)
-    FE_JTV_GP(4) FE_JTV_GP(5) FE_JTV_GP(6) FE_JTV_GP(7)
+    FE_GAUSS_LOOP(UNR, T, FE_JTV_GP)
 #undef FE_JTV_GP
 #pragma unroll
     for (int f = 0; f < NF; ++f) from_modal(out[f], c);
@@ -535,12 +577,13 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
         const int64_t e = (int64_t)t.i + (int64_t)g.nx * ((int64_t)t.j + (int64_t)g.ny * t.k);
         const double y = gamma[e];
         const T alpha = (T)alpha_of(g, y), Kc = (T)K_of(g, y), s = (T)src[e];
+        constexpr bool UNR = Unroll<T>::value;
         if (OP == OP_RES)
-            elem_residual<T>(c, S.x, t.nb, alpha, Kc, s, R);
+            elem_residual<T, UNR>(c, S.x, t.nb, alpha, Kc, s, R);
         else if (OP == OP_JV)
-            elem_jv<T>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
+            elem_jv<T, UNR>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
         else
-            elem_jtv<T>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
+            elem_jtv<T, UNR>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
     }
     // ordered accumulation: in sub-step a every thread adds its corner-a row
     // to a distinct node of the box
@@ -651,6 +694,7 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
                                                    double *__restrict__ gout)
 {
     using T = double;
+    constexpr bool UNR = Unroll<T>::value;
     __shared__ T sx[NF][BOXN];
     __shared__ T sl[NF][BOXN];
     const TileIdx t = tile_index(g);
@@ -693,18 +737,18 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
     const T dtauT_dK = -(tauT * tauT * tauT) * Kc * c.c16h4;      // d tauT / d K
     T ga = 0, gk = 0;
     const T gs = c.gs;
-#define FE_DG_GP(G)                                                                          \
+#define FE_DG_GP(SG)                                                                          \
     {                                                                                        \
         T u[3], Gd[3][3], L[3], LG[3][3];                                                    \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
-            eval_vg<G>(mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
-            eval_vg<G>(mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
+            eval_vg(SG, mu[i], gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                       \
+            eval_vg(SG, mL[i], gs, L[i], LG[i][0], LG[i][1], LG[i][2]);                       \
         }                                                                                    \
         T gp[3], Tv, gT[3], gP[3], gTh[3];                                                   \
-        eval_g<G>(mp, gs, gp[0], gp[1], gp[2]);                                              \
-        eval_vg<G>(mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
-        eval_g<G>(mP, gs, gP[0], gP[1], gP[2]);                                              \
-        eval_g<G>(mTh, gs, gTh[0], gTh[1], gTh[2]);                                          \
+        eval_g(SG, mp, gs, gp[0], gp[1], gp[2]);                                              \
+        eval_vg(SG, mT, gs, Tv, gT[0], gT[1], gT[2]);                                         \
+        eval_g(SG, mP, gs, gP[0], gP[1], gP[2]);                                              \
+        eval_g(SG, mTh, gs, gTh[0], gTh[1], gTh[2]);                                          \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
             T rM = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2] + gp[i]              \
@@ -716,8 +760,7 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
         T uTh = u[0] * gTh[0] + u[1] * gTh[1] + u[2] * gTh[2];                               \
         gk += gTh[0] * gT[0] + gTh[1] * gT[1] + gTh[2] * gT[2] + dtauT_dK * uTh * rT;        \
     }
-    FE_DG_GP(0) FE_DG_GP(1) FE_DG_GP(2) FE_DG_GP(3)
-    FE_DG_GP(4) FE_DG_GP(5) FE_DG_GP(6) FE_DG_GP(7)
+    FE_GAUSS_LOOP(UNR, T, FE_DG_GP)
 #undef FE_DG_GP
     gout[e] = c.W * (da * ga + dK * gk);
 }
@@ -725,14 +768,15 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
 // ---- nodal 5x5 diagonal blocks of J -----------------------------------------------
 
 // Shape function of local node a and its physical gradient at Gauss point G.
-template <int G>
-__device__ __forceinline__ void shape_at(int a, double h, double &N, double dN[3])
+template <typename SGT>
+__device__ __forceinline__ void shape_at(const SGT &SG, int a, double h, double &N, double dN[3])
 {
     const double q = QG;
+    const double sgv[3] = {double(SG.sx), double(SG.sy), double(SG.sz)};
     double f[3], sgn[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double sg = ((G >> d) & 1) ? q : -q;
+        const double sg = sgv[d] * q;
         sgn[d] = ((a >> d) & 1) ? 1.0 : -1.0;
         f[d] = 0.5 * (1.0 + sgn[d] * sg);
     }
@@ -794,15 +838,15 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
             T ua[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) ua[i] = sx[i][t.nb[a]];
-#define FE_BD_GP(G)                                                                          \
+#define FE_BD_GP(SG)                                                                          \
     {                                                                                        \
         T u[3], Gd[3][3], gp[3], Tv, gT[3];                                                  \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
-            eval_vg<G>(mu[i], c.gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                     \
-        eval_g<G>(mp, c.gs, gp[0], gp[1], gp[2]);                                            \
-        eval_vg<G>(mT, c.gs, Tv, gT[0], gT[1], gT[2]);                                       \
+            eval_vg(SG, mu[i], c.gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                     \
+        eval_g(SG, mp, c.gs, gp[0], gp[1], gp[2]);                                            \
+        eval_vg(SG, mT, c.gs, Tv, gT[0], gT[1], gT[2]);                                       \
         T N, dN[3];                                                                          \
-        shape_at<G>(a, h, N, dN);                                                            \
+        shape_at(SG, a, h, N, dN);                                                            \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
         T rM[3];                                                                             \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
@@ -850,8 +894,7 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
                                        + udN * AT + dudN * BT);                              \
         }                                                                                    \
     }
-            FE_BD_GP(0) FE_BD_GP(1) FE_BD_GP(2) FE_BD_GP(3)
-            FE_BD_GP(4) FE_BD_GP(5) FE_BD_GP(6) FE_BD_GP(7)
+            FE_GAUSS_LOOP(false, T, FE_BD_GP)
 #undef FE_BD_GP
 #pragma unroll
             for (int q = 0; q < 25; ++q) so[q * BOXN + t.nb[a]] += blk[q];

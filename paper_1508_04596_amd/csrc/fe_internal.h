@@ -25,6 +25,12 @@ struct Geo {
     double h, Pr, B;    // B = Gr * Pr^2 (buoyancy coefficient)
     double eg[3];
     double Ck, qf, amax, qa;
+    // derived per-launch constants (host-computed)
+    double W;        // (h/2)^3
+    double gs;       // 2/(h/sqrt(3))
+    double inv16h2;  // 1/(16 h^2)
+    double cvisc;    // 16 Pr^2 / h^4
+    double c16h4;    // 16 / h^4
 };
 
 Geo make_geo(const fe_grid &g, const fe_phys &ph);
@@ -52,7 +58,7 @@ hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, 
                             const uint8_t *nmask, double *D, double *slots, hipStream_t st);
 
 // ---- vector kernels (fe_vec.hip) ------------------------------------------
-constexpr int RED_BLOCKS = 512;   // partial sums per reduction (fixed => deterministic)
+constexpr int RED_BLOCKS = 1024;  // partial sums per reduction (fixed => deterministic)
 constexpr int RED_THREADS = 256;
 
 hipError_t launch_node_mask(const uint8_t *dof_mask, uint8_t *nmask, int64_t nn, hipStream_t st);

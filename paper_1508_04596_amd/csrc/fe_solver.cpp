@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "fe_internal.h"
+#include "fe_mg.h"
 
 using namespace fe;
 
@@ -31,6 +32,7 @@ struct SolverWs {
     double *ydev = nullptr;  // device: combination coefficients
     double *hhost = nullptr; // pinned host copy of hbuf / y
     hipEvent_t ev[8] = {};
+    Mg *mg = nullptr;        // multigrid hierarchy (created on first use)
 };
 
 static void free_ws(SolverWs *w)
@@ -43,6 +45,7 @@ static void free_ws(SolverWs *w)
     (void)hipFree(w->D32);
     (void)hipFree(w->x32);
     if (w->hhost) (void)hipHostFree(w->hhost);
+    mg_free(w->mg);
     for (auto &e : w->ev)
         if (e) (void)hipEventDestroy(e);
     delete w;
@@ -300,6 +303,35 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->krylov_op_prec = FE_FP64;
     o->ls_lambda_min = 0.05;
     o->verbose = 0;
+    o->precond = FE_PC_AUTO;
+    o->mg_nu = 2;
+    o->mg_omega = 0.6;
+}
+
+// Resolve the preconditioner choice and make the multigrid hierarchy ready.
+static int choose_precond(fe_problem *p, const fe_solve_opts &o, bool mixed, int *pc)
+{
+    int want = o.precond;
+    if (want == FE_PC_AUTO) want = mg_num_levels(p->grid) >= 2 ? FE_PC_MULTIGRID : FE_PC_BJACOBI;
+    if (want != FE_PC_MULTIGRID && want != FE_PC_BJACOBI) {
+        set_error("unknown preconditioner");
+        return FE_EINVAL;
+    }
+    *pc = want;
+    if (want == FE_PC_MULTIGRID) {
+        SolverWs *w = p->ws;
+        if (w->mg && mixed && !w->mg->mixed) {
+            mg_free(w->mg);
+            w->mg = nullptr;
+        }
+        if (!w->mg) {
+            int rc = mg_create(p, mixed, &w->mg);
+            if (rc) return rc;
+        }
+        w->mg->nu1 = w->mg->nu2 = o.mg_nu < 1 ? 1 : o.mg_nu;
+        w->mg->omega = o.mg_omega;
+    }
+    return FE_OK;
 }
 
 int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
@@ -343,6 +375,13 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     int rc = ensure_ws(p, opts.restart, mixed);
     if (rc) return rc;
     SolverWs *w = p->ws;
+    int pc = FE_PC_BJACOBI;
+    rc = choose_precond(p, opts, mixed, &pc);
+    if (rc) return rc;
+    if (pc == FE_PC_MULTIGRID) {
+        rc = mg_set_design(w->mg, p, gamma, s_elem, st);
+        if (rc) return rc;
+    }
     const int64_t n = p->ndof;
     fe_solve_report rep;
     std::memset(&rep, 0, sizeof(rep));
@@ -365,6 +404,11 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     LinSys L;
     L.z32 = mixed;
     L.prec = [&](const double *v, void *z) -> hipError_t {
+        if (pc == FE_PC_MULTIGRID) {
+            int r = mixed ? mg_apply32(w->mg, v, (float *)z, false, st)
+                          : mg_apply64(w->mg, v, (double *)z, false, st);
+            return r == FE_OK ? hipSuccess : hipErrorUnknown;
+        }
         if (mixed)
             return launch_block_apply<float, double, float>(w->D32, v, (float *)z, p->nn, false,
                                                             nullptr, st);
@@ -395,6 +439,14 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
         FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
         FE_CHECK_HIP(launch_invert_blocks(w->D, mixed ? w->D32 : nullptr, p->nn, st));
         if (mixed) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+        if (pc == FE_PC_MULTIGRID) {
+            rc = mg_setup(w->mg, p, x, w->D, w->D32, w->x32, st);
+            if (rc) {
+                rep.status = rc;
+                fill_report(report, rep);
+                return rc;
+            }
+        }
         FE_CHECK_HIP(launch_axpby(n, -1.0, R, 0.0, w->rhs, st));
         FE_CHECK_HIP(hipEventRecord(e1, st));
         LinStats ls;
@@ -476,6 +528,8 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     FE_CHECK_HIP(hipStreamSynchronize(st));
     rep.res_final = rn;
     rep.status = status;
+    rep.precond = pc;
+    rep.mg_levels = pc == FE_PC_MULTIGRID ? (int)w->mg->lev.size() : 0;
     rep.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_report(report, rep);
     if (status != FE_OK) set_error("newton_solve: not converged within max_newton");
@@ -503,11 +557,22 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
     SolverWs *w = p->ws;
     fe_solve_report rep;
     std::memset(&rep, 0, sizeof(rep));
+    int pc = FE_PC_BJACOBI;
+    rc = choose_precond(p, opts, false, &pc);
+    if (rc) return rc;
     FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
     FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
+    if (pc == FE_PC_MULTIGRID) {
+        rc = mg_set_design(w->mg, p, gamma, s_elem, st);
+        if (rc == FE_OK) rc = mg_setup(w->mg, p, x, w->D, nullptr, nullptr, st);
+        if (rc) return rc;
+    }
     LinSys L;
     L.z32 = false;
     L.prec = [&](const double *v, void *z) -> hipError_t {
+        if (pc == FE_PC_MULTIGRID)
+            return mg_apply64(w->mg, v, (double *)z, true, st) == FE_OK ? hipSuccess
+                                                                         : hipErrorUnknown;
         return launch_block_apply<double, double, double>(w->D, v, (double *)z, p->nn, true,
                                                           nullptr, st);
     };
@@ -532,6 +597,8 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
     rep.t_prec_s = ls.t_prec;
     rep.t_orth_s = ls.t_orth;
     rep.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep.precond = pc;
+    rep.mg_levels = pc == FE_PC_MULTIGRID ? (int)w->mg->lev.size() : 0;
     fill_report(report, rep);
     if (!ls.converged) set_error("fe_adjoint_solve: FGMRES not converged");
     return rep.status;

@@ -96,11 +96,14 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ parti
                                                 double *__restrict__ out,
                                                 const double *__restrict__ add, int k, int sqrt_last)
 {
-    // one workgroup per output; RED_BLOCKS = 512 partials, 2 per thread, fixed tree
+    // one workgroup per output; RED_BLOCKS partials, summed in a fixed tree
+    static_assert(RED_BLOCKS % 256 == 0, "RED_BLOCKS must be a multiple of 256");
     __shared__ double red[4];
     const int j = blockIdx.x;
     const double *p = partial + (int64_t)j * RED_BLOCKS;
-    double s = p[threadIdx.x] + p[threadIdx.x + 256];
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < RED_BLOCKS / 256; ++q) s += p[threadIdx.x + 256 * q];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();

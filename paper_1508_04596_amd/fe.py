@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfe_hip.so")
 FE_OK, FE_PENDING, FE_NOT_CONVERGED = 0, 1, 2
 FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_ENAN, FE_ESTATE = -1, -2, -3, -4, -5
 FE_FP64, FE_FP32 = 0, 1
+FE_PC_AUTO, FE_PC_BJACOBI, FE_PC_MULTIGRID = 0, 1, 2
 
 EXPORTS = [
     "fe_problem_create", "fe_problem_destroy", "fe_problem_set_phys", "fe_problem_ndof",
@@ -45,7 +46,8 @@ class FeSolveOpts(ctypes.Structure):
                 ("max_newton", ctypes.c_int), ("restart", ctypes.c_int),
                 ("max_lin", ctypes.c_int), ("n_refine", ctypes.c_int),
                 ("krylov_op_prec", ctypes.c_int), ("ls_lambda_min", ctypes.c_double),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
+                ("mg_omega", ctypes.c_double)]
 
 
 class FeSolveReport(ctypes.Structure):
@@ -55,7 +57,8 @@ class FeSolveReport(ctypes.Structure):
                 ("t_total_s", ctypes.c_double), ("t_jv_s", ctypes.c_double),
                 ("t_prec_s", ctypes.c_double), ("t_orth_s", ctypes.c_double),
                 ("t_res_s", ctypes.c_double), ("t_setup_s", ctypes.c_double),
-                ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65)]
+                ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65),
+                ("precond", ctypes.c_int), ("mg_levels", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         n = min(self.newton_its, 64)
@@ -64,7 +67,9 @@ class FeSolveReport(ctypes.Structure):
                 "lambda_last": self.lambda_last, "t_total_s": self.t_total_s,
                 "t_jv_s": self.t_jv_s, "t_prec_s": self.t_prec_s, "t_orth_s": self.t_orth_s,
                 "t_res_s": self.t_res_s, "t_setup_s": self.t_setup_s,
-                "lin_its": list(self.lin_its[:n]), "res_hist": list(self.res_hist[:n + 1])}
+                "lin_its": list(self.lin_its[:n]), "res_hist": list(self.res_hist[:n + 1]),
+                "precond": {1: "bjacobi", 2: "multigrid"}.get(self.precond, "none"),
+                "mg_levels": self.mg_levels}
 
 
 class FeError(RuntimeError):
@@ -154,6 +159,9 @@ def solve_opts(**kw) -> FeSolveOpts:
     for k, v in kw.items():
         if k == "krylov_op_prec" and isinstance(v, str):
             v = FE_FP32 if v in ("fp32", "mixed") else FE_FP64
+        if k == "precond" and isinstance(v, str):
+            v = {"auto": FE_PC_AUTO, "bjacobi": FE_PC_BJACOBI, "multigrid": FE_PC_MULTIGRID,
+                 "mg": FE_PC_MULTIGRID}[v]
         setattr(o, k, v)
     return o
 

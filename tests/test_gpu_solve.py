@@ -30,18 +30,21 @@ def host(t):
     return t.double().cpu().numpy()
 
 
+@pytest.mark.parametrize("pc", ["bjacobi", "multigrid"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_newton_c1_backward_error(fe, prec):
+def test_newton_c1_backward_error(fe, prec, pc):
     p = inputs.config(1)
-    print(f"[solve] C1 {prec}", flush=True)
+    print(f"[solve] C1 {prec} {pc}", flush=True)
     prob = fe.Problem.from_inputs(p, mask="solve")
     x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
     rep = fe.newton_solve(prob, dev(p.gamma), dev(p.s), x,
-                          fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec))
+                          fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, precond=pc))
+    assert rep["precond"] == pc
     xs = host(x)
     r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
     r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
-    print(f"[solve] {prec}: newton {rep['newton_its']} lin {rep['lin_its']} rel {r / r0:.3e}")
+    print(f"[solve] {prec} {pc}: newton {rep['newton_its']} lin {rep['lin_its']} rel {r / r0:.3e} "
+          f"levels {rep['mg_levels']}")
     assert r <= 1e-8 * r0 * 1.0001
     x_or, _, _ = osolve.newton(p, rtol=1e-13)
     print(f"[solve] forward rel diff {rel_norm(xs, x_or):.3e}")
@@ -86,4 +89,22 @@ def test_adjoint_gradient_against_oracle(fe):
     print(f"[adjoint] oracle backward error of lambda {bwd:.3e}")
     assert bwd <= 1e-10
     assert rel_norm(grad, grad_or) <= 1e-9
+    prob.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multigrid_newton_on_32_cubed(fe, prec):
+    """Multigrid-preconditioned solve on a 32^3 C2-style problem (3 levels)."""
+    p = inputs.scaled_config(32, 32, 32, 1e4, seed=1032)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    rep = fe.newton_solve(prob, dev(p.gamma), dev(p.s), x,
+                          fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, precond="multigrid"))
+    xs = host(x)
+    r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+    r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
+    print(f"[mg32] {prec}: newton {rep['newton_its']} lin {rep['lin_its']} levels {rep['mg_levels']} "
+          f"t {rep['t_total_s']:.3f}s rel {r / r0:.3e}")
+    assert rep["mg_levels"] >= 3
+    assert r <= 1e-8 * r0 * 1.0001
     prob.close()
