@@ -205,6 +205,9 @@ int serve_submit(fe_server *s, const fe_grid *grid, const fe_phys *phys, const d
 int serve_poll(fe_server *s, uint64_t ticket, double *x_host_out, fe_solve_report *report);
 /* Timestamps (seconds, server clock) of submit, admit and completion. */
 int serve_times(fe_server *s, uint64_t ticket, double *t_submit, double *t_admit, double *t_done);
+/* Error message of a finished request that failed ("" otherwise); the string
+ * stays valid until serve_destroy. */
+const char *serve_error(fe_server *s, uint64_t ticket);
 int serve_destroy(fe_server *s);
 
 const char *fe_last_error(void);

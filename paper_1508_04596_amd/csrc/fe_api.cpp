@@ -76,17 +76,23 @@ static int check_phys(const fe_phys *ph)
     return FE_OK;
 }
 
-}  // namespace fe
+namespace {
+struct HipAllocator final : Allocator {
+    hipError_t dev_alloc(void **p, size_t n) override { return hipMalloc(p, n); }
+    void dev_free(void *p) override { (void)hipFree(p); }
+    hipError_t host_alloc(void **p, size_t n) override { return hipHostMalloc(p, n); }
+    void host_free(void *p) override { (void)hipHostFree(p); }
+};
+}  // namespace
 
-using namespace fe;
+Allocator *default_allocator()
+{
+    static HipAllocator a;
+    return &a;
+}
 
-extern "C" {
-
-const char *fe_last_error(void) { return g_last_error.c_str(); }
-const char *fe_version(void) { return "fe-hip 1.0 (gfx950)"; }
-
-int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
-                      fe_problem **out)
+int problem_create_ex(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
+                      MaskKind kind, Allocator *alloc, hipStream_t stream, fe_problem **out)
 {
     if (!out) {
         set_error("out is NULL");
@@ -99,6 +105,7 @@ int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *d
     if (rc) return rc;
     fe_problem *p = new (std::nothrow) fe_problem();
     if (!p) return FE_ENOMEM;
+    p->alloc = alloc ? alloc : default_allocator();
     p->grid = *grid;
     p->phys = *phys;
     p->geo = make_geo(*grid, *phys);
@@ -111,20 +118,24 @@ int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *d
         return hip_fail(e, "hipGetDevice");
     }
     const size_t slot_bytes = (size_t)n_tiles(p->geo) * BOXN * NF * sizeof(double);
-    if ((e = hipMalloc(&p->nmask, p->nn)) != hipSuccess ||
-        (e = hipMalloc(&p->dof_mask, p->ndof)) != hipSuccess ||
-        (e = hipMalloc(&p->slots, slot_bytes)) != hipSuccess ||
-        (e = hipMalloc(&p->partial, sizeof(double) * 66 * RED_BLOCKS)) != hipSuccess ||
-        (e = hipMalloc(&p->scal, sizeof(double) * 256)) != hipSuccess) {
+    if ((e = dalloc(p, &p->nmask, p->nn)) != hipSuccess ||
+        (e = dalloc(p, &p->dof_mask, p->ndof)) != hipSuccess ||
+        (e = dalloc(p, &p->slots, slot_bytes)) != hipSuccess ||
+        (e = dalloc(p, &p->partial, sizeof(double) * 66 * RED_BLOCKS)) != hipSuccess ||
+        (e = dalloc(p, &p->scal, sizeof(double) * 256)) != hipSuccess) {
         fe_problem_destroy(p);
-        return hip_fail(e, "hipMalloc (problem)");
+        return hip_fail(e, "device allocation (problem)");
     }
-    if (dof_mask)
-        e = hipMemcpy(p->dof_mask, dof_mask, p->ndof, hipMemcpyDeviceToDevice);
-    else
-        e = hipMemset(p->dof_mask, 0, p->ndof);
-    if (e == hipSuccess) e = launch_node_mask(p->dof_mask, p->nmask, p->nn, 0);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (kind == MASK_WALLS_PIN) {
+        e = launch_wall_mask(grid->nx, grid->ny, grid->nz, p->nmask, p->dof_mask, stream);
+    } else {
+        if (dof_mask)
+            e = hipMemcpyAsync(p->dof_mask, dof_mask, p->ndof, hipMemcpyDeviceToDevice, stream);
+        else
+            e = hipMemsetAsync(p->dof_mask, 0, p->ndof, stream);
+        if (e == hipSuccess) e = launch_node_mask(p->dof_mask, p->nmask, p->nn, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         fe_problem_destroy(p);
         return hip_fail(e, "fe_problem_create mask setup");
@@ -133,18 +144,33 @@ int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *d
     return FE_OK;
 }
 
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+const char *fe_version(void) { return "fe-hip 1.0 (gfx950)"; }
+
+int fe_problem_create(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
+                      fe_problem **out)
+{
+    return problem_create_ex(grid, phys, dof_mask, MASK_GIVEN, nullptr, 0, out);
+}
+
 void fe_free_solver_ws(fe_problem *p);  // fe_solver.cpp
 
 int fe_problem_destroy(fe_problem *p)
 {
     if (!p) return FE_OK;
     fe_free_solver_ws(p);
-    (void)hipFree(p->nmask);
-    (void)hipFree(p->dof_mask);
-    (void)hipFree(p->slots);
-    (void)hipFree(p->slots25);
-    (void)hipFree(p->partial);
-    (void)hipFree(p->scal);
+    dfree(p, p->nmask);
+    dfree(p, p->dof_mask);
+    dfree(p, p->slots);
+    dfree(p, p->slots25);
+    dfree(p, p->partial);
+    dfree(p, p->scal);
     delete p;
     return FE_OK;
 }
@@ -240,7 +266,7 @@ int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const
     }
     if (!p->slots25) {
         const size_t b = (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double);
-        FE_CHECK_HIP(hipMalloc(&p->slots25, b));
+        FE_CHECK_HIP(dalloc(p, &p->slots25, b));
     }
     FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, D, p->slots25, stream));
     return FE_OK;

@@ -81,7 +81,7 @@ hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
                          bool sqrt_last, hipStream_t st);
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st);
-// y = a*x + b*y with scalars from device pointers (NULL pointer = constant given)
+// y = a*x + b*y (y is not read when b == 0)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
 // y = x + lam*d
 hipError_t launch_xpld(int64_t n, const double *x, double lam, const double *d, double *y,
@@ -105,6 +105,26 @@ int hip_fail(hipError_t e, const char *what);
 
 struct SolverWs;
 
+// Device / host memory source of a problem: hipMalloc by default, or a
+// sub-allocator over a pre-allocated HBM arena (the solve server).
+struct Allocator {
+    virtual ~Allocator() = default;
+    virtual hipError_t dev_alloc(void **p, size_t n) = 0;
+    virtual void dev_free(void *p) = 0;
+    virtual hipError_t host_alloc(void **p, size_t n) = 0;  // host staging memory
+    virtual void host_free(void *p) = 0;
+};
+Allocator *default_allocator();
+
+enum MaskKind { MASK_GIVEN = 0, MASK_WALLS_PIN = 1 };
+// Internal constructor: mask from a device array (MASK_GIVEN, may be NULL) or
+// generated on the device (walls u,v,w,T plus the pressure of node 0);
+// allocations through alloc, set-up work ordered on stream.
+int problem_create_ex(const fe_grid *grid, const fe_phys *phys, const uint8_t *dof_mask,
+                      MaskKind kind, Allocator *alloc, hipStream_t stream, fe_problem **out);
+hipError_t launch_wall_mask(int nx, int ny, int nz, uint8_t *nmask, uint8_t *dof_mask,
+                            hipStream_t st);
+
 }  // namespace fe
 
 struct fe_problem {
@@ -120,7 +140,29 @@ struct fe_problem {
     double *partial = nullptr;    // reduction partials, 66 * RED_BLOCKS
     double *scal = nullptr;       // device scalars
     fe::SolverWs *ws = nullptr;    // Newton/FGMRES workspace (allocated on first solve)
+    fe::Allocator *alloc = nullptr; // memory source of this problem's buffers
 };
+
+namespace fe {
+template <typename T>
+inline hipError_t dalloc(fe_problem *p, T **ptr, size_t bytes)
+{
+    return p->alloc->dev_alloc(reinterpret_cast<void **>(ptr), bytes);
+}
+inline void dfree(fe_problem *p, void *ptr)
+{
+    if (ptr) p->alloc->dev_free(ptr);
+}
+template <typename T>
+inline hipError_t halloc(fe_problem *p, T **ptr, size_t bytes)
+{
+    return p->alloc->host_alloc(reinterpret_cast<void **>(ptr), bytes);
+}
+inline void hfree(fe_problem *p, void *ptr)
+{
+    if (ptr) p->alloc->host_free(ptr);
+}
+}  // namespace fe
 
 #define FE_CHECK_HIP(call)                                        \
     do {                                                          \

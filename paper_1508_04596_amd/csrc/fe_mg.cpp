@@ -38,34 +38,35 @@ hipError_t mg_probes(int nx, int ny, int nz, double *probe, int64_t ndof, hipStr
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
 
-static void free_level(MgLevel &L, bool owned)
+static void free_level(fe_problem *p, MgLevel &L, bool owned)
 {
     if (owned) {
-        (void)hipFree(L.nmask);
-        (void)hipFree(L.gamma);
-        (void)hipFree(L.s);
-        (void)hipFree(L.x);
-        (void)hipFree(L.x32);
-        (void)hipFree(L.D);
-        (void)hipFree(L.D32);
-        (void)hipFree(L.slots);
-        (void)hipFree(L.slots25);
+        dfree(p, L.nmask);
+        dfree(p, L.gamma);
+        dfree(p, L.s);
+        dfree(p, L.x);
+        dfree(p, L.x32);
+        dfree(p, L.D);
+        dfree(p, L.D32);
+        dfree(p, L.slots);
+        dfree(p, L.slots25);
     }
-    (void)hipFree(L.b);
-    (void)hipFree(L.xs);
-    (void)hipFree(L.t);
-    (void)hipFree(L.b32);
-    (void)hipFree(L.xs32);
-    (void)hipFree(L.t32);
+    dfree(p, L.b);
+    dfree(p, L.xs);
+    dfree(p, L.t);
+    dfree(p, L.b32);
+    dfree(p, L.xs32);
+    dfree(p, L.t32);
 }
 
 void mg_free(Mg *mg)
 {
     if (!mg) return;
-    for (size_t l = 0; l < mg->lev.size(); ++l) free_level(mg->lev[l], l > 0);
-    (void)hipFree(mg->probe);
-    (void)hipFree(mg->probe_out);
-    if (mg->hbuf) (void)hipHostFree(mg->hbuf);
+    fe_problem *p = mg->owner;
+    for (size_t l = 0; l < mg->lev.size(); ++l) free_level(p, mg->lev[l], l > 0);
+    dfree(p, mg->probe);
+    dfree(p, mg->probe_out);
+    hfree(p, mg->hbuf);
     delete mg;
 }
 
@@ -86,6 +87,40 @@ int mg_num_levels(const fe_grid &g)
     return n;
 }
 
+static int64_t r256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// Device bytes mg_create allocates for grid g (each allocation rounded up to 256 B).
+int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed)
+{
+    const int nl = mg_num_levels(g0);
+    if (nl < 2) return 0;
+    fe_grid g = g0;
+    int64_t b = 0, ndof_c = 0;
+    for (int l = 0; l < nl; ++l) {
+        if (l > 0) {
+            g.nx /= 2;
+            g.ny /= 2;
+            g.nz /= 2;
+        }
+        const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1), ndof = NF * nn;
+        const int64_t ne = (int64_t)g.nx * g.ny * g.nz;
+        const int64_t nt = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+        if (l > 0) {
+            b += r256(nn) + 2 * r256(8 * ne) + r256(8 * ndof) + r256(8 * 25 * nn);
+            b += r256(nt * BOXN * NF * 8) + r256(nt * BOXN * 25 * 8);
+            b += 2 * r256(8 * ndof);
+            if (mixed) b += r256(4 * ndof) + r256(4 * 25 * nn) + 2 * r256(4 * ndof);
+        } else if (mixed) {
+            b += r256(4 * ndof);
+        }
+        b += r256(8 * ndof);
+        if (mixed) b += r256(4 * ndof);
+        ndof_c = ndof;
+    }
+    b += 2 * r256(8 * 135 * ndof_c);
+    return b;
+}
+
 // Allocate the hierarchy for problem p (levels >= 1 own their data).
 int mg_create(fe_problem *p, bool mixed, Mg **out)
 {
@@ -97,6 +132,7 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
         return FE_EINVAL;
     }
     Mg *mg = new Mg();
+    mg->owner = p;
     mg->mixed = mixed;
     mg->lev.resize(nl);
     hipError_t e = hipSuccess;
@@ -116,30 +152,30 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
         L.ndof = NF * L.nn;
         const size_t nb = sizeof(double) * L.ndof;
         if (l > 0) {
-            if (e == hipSuccess) e = hipMalloc(&L.nmask, L.nn);
-            if (e == hipSuccess) e = hipMalloc(&L.gamma, sizeof(double) * L.ne);
-            if (e == hipSuccess) e = hipMalloc(&L.s, sizeof(double) * L.ne);
-            if (e == hipSuccess) e = hipMalloc(&L.x, nb);
-            if (e == hipSuccess) e = hipMalloc(&L.D, sizeof(double) * 25 * L.nn);
-            if (e == hipSuccess) e = hipMalloc(&L.slots, (size_t)n_tiles(L.geo) * BOXN * NF * sizeof(double));
-            if (e == hipSuccess) e = hipMalloc(&L.slots25, (size_t)n_tiles(L.geo) * BOXN * 25 * sizeof(double));
-            if (e == hipSuccess && mixed) e = hipMalloc(&L.x32, sizeof(float) * L.ndof);
-            if (e == hipSuccess && mixed) e = hipMalloc(&L.D32, sizeof(float) * 25 * L.nn);
-            if (e == hipSuccess) e = hipMalloc(&L.b, nb);
-            if (e == hipSuccess) e = hipMalloc(&L.xs, nb);
-            if (e == hipSuccess && mixed) e = hipMalloc(&L.b32, sizeof(float) * L.ndof);
-            if (e == hipSuccess && mixed) e = hipMalloc(&L.xs32, sizeof(float) * L.ndof);
+            if (e == hipSuccess) e = dalloc(p, &L.nmask, L.nn);
+            if (e == hipSuccess) e = dalloc(p, &L.gamma, sizeof(double) * L.ne);
+            if (e == hipSuccess) e = dalloc(p, &L.s, sizeof(double) * L.ne);
+            if (e == hipSuccess) e = dalloc(p, &L.x, nb);
+            if (e == hipSuccess) e = dalloc(p, &L.D, sizeof(double) * 25 * L.nn);
+            if (e == hipSuccess) e = dalloc(p, &L.slots, (size_t)n_tiles(L.geo) * BOXN * NF * sizeof(double));
+            if (e == hipSuccess) e = dalloc(p, &L.slots25, (size_t)n_tiles(L.geo) * BOXN * 25 * sizeof(double));
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.x32, sizeof(float) * L.ndof);
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.D32, sizeof(float) * 25 * L.nn);
+            if (e == hipSuccess) e = dalloc(p, &L.b, nb);
+            if (e == hipSuccess) e = dalloc(p, &L.xs, nb);
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.b32, sizeof(float) * L.ndof);
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.xs32, sizeof(float) * L.ndof);
         } else if (mixed) {
-            if (e == hipSuccess) e = hipMalloc(&L.b32, sizeof(float) * L.ndof);  // cast of the Krylov vector
+            if (e == hipSuccess) e = dalloc(p, &L.b32, sizeof(float) * L.ndof);  // cast of the Krylov vector
         }
-        if (e == hipSuccess) e = hipMalloc(&L.t, nb);
-        if (e == hipSuccess && mixed) e = hipMalloc(&L.t32, sizeof(float) * L.ndof);
+        if (e == hipSuccess) e = dalloc(p, &L.t, nb);
+        if (e == hipSuccess && mixed) e = dalloc(p, &L.t32, sizeof(float) * L.ndof);
     }
     const MgLevel &C = mg->lev.back();
     mg->nc = C.ndof;
-    if (e == hipSuccess) e = hipMalloc(&mg->probe, sizeof(double) * 135 * C.ndof);
-    if (e == hipSuccess) e = hipMalloc(&mg->probe_out, sizeof(double) * 135 * C.ndof);
-    if (e == hipSuccess) e = hipHostMalloc(&mg->hbuf, sizeof(double) * 135 * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 135 * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->probe_out, sizeof(double) * 135 * C.ndof);
+    if (e == hipSuccess) e = halloc(p, &mg->hbuf, sizeof(double) * 135 * C.ndof);
     if (e != hipSuccess) {
         mg_free(mg);
         return hip_fail(e, "hipMalloc (multigrid)");

@@ -23,6 +23,7 @@ struct MgLevel {
 };
 
 struct Mg {
+    fe_problem *owner = nullptr;  // allocations go through owner->alloc
     std::vector<MgLevel> lev;
     bool mixed = false;
     int nu1 = 2, nu2 = 2;
@@ -36,6 +37,7 @@ struct Mg {
 };
 
 int mg_num_levels(const fe_grid &g);
+int64_t mg_footprint_bytes(const fe_grid &g, bool mixed);
 int mg_create(fe_problem *p, bool mixed, Mg **out);
 void mg_free(Mg *mg);
 int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, hipStream_t st);

@@ -1,40 +1,360 @@
-// Continuous-batching solve server (scheduler, admission, batched launches).
+// Continuous-batching solve server.
+//
+// One device arena of hbm_budget_bytes is allocated at creation; every admitted
+// request takes its whole working set (problem handle, solver workspace,
+// multigrid hierarchy, design, source and state) from it through a first-fit
+// sub-allocator, so admission is decided by memory footprint and no device
+// allocation or free (and no implicit device synchronisation) happens while
+// requests run.  max_active worker threads, each with its own HIP stream, take
+// requests from the queue in arrival order as soon as the head request's
+// footprint fits in the unreserved part of the arena; a request therefore
+// starts while others are still on the GPU, and the kernels of all running
+// requests overlap on the device.  A finished request releases its memory and
+// wakes the admission of the next.  Each request runs the same deterministic
+// kernels as a standalone newton_solve, so its result does not depend on what
+// else is running.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "fe_internal.h"
 
 using namespace fe;
 
-struct fe_server {
-    int dummy;
+namespace {
+
+class Arena final : public Allocator {
+  public:
+    hipError_t init(size_t bytes)
+    {
+        size_ = bytes / 256 * 256;
+        const char *pz = std::getenv("FE_ARENA_POISON");
+        poison_ = pz && pz[0] == '1';
+        hipError_t e = hipMalloc(&base_, size_);
+        if (e == hipSuccess) free_[0] = size_;
+        return e;
+    }
+    ~Arena() override
+    {
+        if (base_) (void)hipFree(base_);
+    }
+    hipError_t dev_alloc(void **p, size_t n) override
+    {
+        n = std::max<size_t>(256, (n + 255) / 256 * 256);
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > n) free_[off + n] = sz - n;
+            used_[off] = n;
+            *p = static_cast<char *>(base_) + off;
+            // debugging aid: fill fresh blocks with NaN bytes so that a read
+            // before the first write shows up as a non-finite result
+            if (poison_) return hipMemset(*p, 0xFF, n);
+            return hipSuccess;
+        }
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    void dev_free(void *p) override
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        const size_t off = static_cast<char *>(p) - static_cast<char *>(base_);
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t start = off, n = u->second;
+        used_.erase(u);
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && next->first == start + n) {
+            n += next->second;
+            free_.erase(next);
+        }
+        auto it = free_.lower_bound(start);
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                n += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = n;
+    }
+    // host staging memory: plain pageable memory (freeing it never synchronises)
+    hipError_t host_alloc(void **p, size_t n) override
+    {
+        *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void host_free(void *p) override { std::free(p); }
+    size_t size() const { return size_; }
+
+  private:
+    void *base_ = nullptr;
+    size_t size_ = 0;
+    bool poison_ = false;
+    std::mutex mu_;
+    std::map<size_t, size_t> free_;            // offset -> size of free blocks
+    std::unordered_map<size_t, size_t> used_;  // offset -> size of live blocks
 };
+
+enum ReqState { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2 };
+
+struct Request {
+    uint64_t ticket = 0;
+    fe_grid grid;
+    fe_phys phys;
+    fe_solve_opts opts;
+    std::vector<double> gamma, s, x;
+    size_t footprint = 0;
+    ReqState state = Q_WAITING;
+    int status = FE_PENDING;
+    fe_solve_report rep;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::string error;
+};
+
+}  // namespace
+
+struct fe_server {
+    Arena arena;
+    size_t budget = 0;
+    int max_active = 1;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    size_t reserved = 0;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::vector<std::thread> workers;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+size_t request_footprint(const fe_grid &g, const fe_solve_opts &o)
+{
+    const int64_t ws = fe_solve_footprint_bytes(&g, &o);
+    const int64_t ne = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t ndof = (int64_t)NF * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
+    return (size_t)(ws + 2 * r(8 * ne) + r(8 * ndof) + 64 * 256);
+}
+
+int run_request(fe_server *S, Request *r, hipStream_t st)
+{
+    fe_problem *p = nullptr;
+    int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &S->arena, st, &p);
+    if (rc) return rc;
+    const int64_t ne = p->ne, ndof = p->ndof;
+    double *g = nullptr, *s = nullptr, *x = nullptr;
+    hipError_t e = dalloc(p, &g, sizeof(double) * ne);
+    if (e == hipSuccess) e = dalloc(p, &s, sizeof(double) * ne);
+    if (e == hipSuccess) e = dalloc(p, &x, sizeof(double) * ndof);
+    if (e == hipSuccess) e = hipMemcpyAsync(g, r->gamma.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s, r->s.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(x, 0, sizeof(double) * ndof, st);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "serve: request set-up");
+    } else {
+        rc = newton_solve(p, g, s, x, &r->opts, &r->rep, st);
+        r->x.resize(ndof);
+        e = hipMemcpyAsync(r->x.data(), x, sizeof(double) * ndof, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess && rc >= 0) rc = hip_fail(e, "serve: result copy");
+    }
+    dfree(p, g);
+    dfree(p, s);
+    dfree(p, x);
+    fe_problem_destroy(p);
+    return rc;
+}
+
+void worker_main(fe_server *S)
+{
+    (void)hipSetDevice(S->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    while (true) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] {
+                return S->stop ||
+                       (!S->queue.empty() && S->reserved + S->queue.front()->footprint <= S->budget);
+            });
+            if (S->stop) break;
+            r = S->queue.front();
+            S->queue.pop_front();
+            S->reserved += r->footprint;
+            r->state = Q_RUNNING;
+            r->t_admit = S->now();
+        }
+        int rc = run_request(S, r, st);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->reserved -= r->footprint;
+            r->status = rc;
+            if (rc < 0) r->rep.status = rc;
+            if (rc != FE_OK) r->error = fe_last_error();
+            r->state = Q_DONE;
+            r->t_done = S->now();
+        }
+        S->cv.notify_all();
+    }
+    if (st) (void)hipStreamDestroy(st);
+}
+
+}  // namespace
 
 extern "C" {
 
-int serve_create(size_t, int, fe_server **out)
+int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out)
 {
-    if (out) *out = nullptr;
-    set_error("serve_create: server not built yet");
-    return FE_ESTATE;
+    if (!out || max_active < 1 || max_active > 64 || hbm_budget_bytes < ((size_t)1 << 20)) {
+        set_error("serve_create: need out != NULL, 1 <= max_active <= 64, budget >= 1 MiB");
+        return FE_EINVAL;
+    }
+    *out = nullptr;
+    auto *S = new (std::nothrow) fe_server();
+    if (!S) return FE_ENOMEM;
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        set_error("serve_create: no device");
+        return FE_EHIP;
+    }
+    hipError_t e = S->arena.init(hbm_budget_bytes);
+    if (e != hipSuccess) {
+        delete S;
+        return hip_fail(e, "serve_create: arena allocation");
+    }
+    S->budget = S->arena.size();
+    S->max_active = max_active;
+    S->t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < max_active; ++i) S->workers.emplace_back(worker_main, S);
+    *out = S;
+    return FE_OK;
 }
 
-int serve_submit(fe_server *, const fe_grid *, const fe_phys *, const double *, const double *,
-                 const fe_solve_opts *, uint64_t *)
+int serve_submit(fe_server *S, const fe_grid *grid, const fe_phys *phys, const double *gamma_host,
+                 const double *s_host, const fe_solve_opts *opts, uint64_t *ticket)
 {
-    set_error("serve_submit: server not built yet");
-    return FE_ESTATE;
+    if (!S || !grid || !phys || !gamma_host || !s_host || !ticket) {
+        set_error("serve_submit: NULL argument");
+        return FE_EINVAL;
+    }
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->h > 0)) {
+        set_error("serve_submit: bad grid");
+        return FE_EINVAL;
+    }
+    auto r = std::make_unique<Request>();
+    r->grid = *grid;
+    r->phys = *phys;
+    fe_solve_opts_default(&r->opts);
+    if (opts) r->opts = *opts;
+    r->opts.verbose = 0;
+    const int64_t ne = (int64_t)grid->nx * grid->ny * grid->nz;
+    r->gamma.assign(gamma_host, gamma_host + ne);
+    r->s.assign(s_host, s_host + ne);
+    std::memset(&r->rep, 0, sizeof(r->rep));
+    r->footprint = request_footprint(r->grid, r->opts);
+    std::lock_guard<std::mutex> lk(S->mu);
+    r->ticket = S->next_ticket++;
+    r->t_submit = S->now();
+    *ticket = r->ticket;
+    Request *raw = r.get();
+    if (r->footprint > S->budget) {
+        r->state = Q_DONE;
+        r->status = FE_ENOMEM;
+        r->rep.status = FE_ENOMEM;
+        r->t_admit = r->t_done = r->t_submit;
+        S->reqs[raw->ticket] = std::move(r);
+        set_error("serve_submit: request footprint exceeds the server's memory budget");
+        return FE_ENOMEM;
+    }
+    S->reqs[raw->ticket] = std::move(r);
+    S->queue.push_back(raw);
+    S->cv.notify_all();
+    return FE_OK;
 }
 
-int serve_poll(fe_server *, uint64_t, double *, fe_solve_report *)
+int serve_poll(fe_server *S, uint64_t ticket, double *x_host_out, fe_solve_report *report)
 {
-    set_error("serve_poll: server not built yet");
-    return FE_ESTATE;
+    if (!S) {
+        set_error("serve_poll: NULL server");
+        return FE_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("serve_poll: unknown ticket");
+        return FE_EINVAL;
+    }
+    Request *r = it->second.get();
+    if (r->state != Q_DONE) return FE_PENDING;
+    if (x_host_out && !r->x.empty()) std::memcpy(x_host_out, r->x.data(), sizeof(double) * r->x.size());
+    if (report) *report = r->rep;
+    return r->status;
 }
 
-int serve_times(fe_server *, uint64_t, double *, double *, double *)
+int serve_times(fe_server *S, uint64_t ticket, double *t_submit, double *t_admit, double *t_done)
 {
-    set_error("serve_times: server not built yet");
-    return FE_ESTATE;
+    if (!S) {
+        set_error("serve_times: NULL server");
+        return FE_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("serve_times: unknown ticket");
+        return FE_EINVAL;
+    }
+    const Request *r = it->second.get();
+    if (t_submit) *t_submit = r->t_submit;
+    if (t_admit) *t_admit = r->t_admit;
+    if (t_done) *t_done = r->t_done;
+    return r->state == Q_DONE ? FE_OK : FE_PENDING;
 }
 
-int serve_destroy(fe_server *) { return FE_OK; }
+const char *serve_error(fe_server *S, uint64_t ticket)
+{
+    if (!S) return "";
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || it->second->state != Q_DONE) return "";
+    return it->second->error.c_str();
+}
+
+int serve_destroy(fe_server *S)
+{
+    if (!S) return FE_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto &t : S->workers) t.join();
+    delete S;
+    return FE_OK;
+}
 
 }  // extern "C"

@@ -33,18 +33,20 @@ struct SolverWs {
     double *hhost = nullptr; // pinned host copy of hbuf / y
     hipEvent_t ev[8] = {};
     Mg *mg = nullptr;        // multigrid hierarchy (created on first use)
+    fe_problem *owner = nullptr;  // allocations go through owner->alloc
 };
 
 static void free_ws(SolverWs *w)
 {
     if (!w) return;
+    fe_problem *p = w->owner;
     double *d[] = {w->R, w->Rh, w->R1, w->xt, w->delta, w->rhs, w->V, w->Z, w->D, w->tmp,
                    w->hbuf, w->ydev};
-    for (double *q : d) (void)hipFree(q);
-    (void)hipFree(w->Z32);
-    (void)hipFree(w->D32);
-    (void)hipFree(w->x32);
-    if (w->hhost) (void)hipHostFree(w->hhost);
+    for (double *q : d) dfree(p, q);
+    dfree(p, w->Z32);
+    dfree(p, w->D32);
+    dfree(p, w->x32);
+    hfree(p, w->hhost);
     mg_free(w->mg);
     for (auto &e : w->ev)
         if (e) (void)hipEventDestroy(e);
@@ -71,6 +73,7 @@ static int ensure_ws(fe_problem *p, int m, bool mixed)
     free_ws(w);
     p->ws = nullptr;
     w = new SolverWs();
+    w->owner = p;
     w->m = m;
     w->mixed = mixed;
     w->ndof = p->ndof;
@@ -79,20 +82,20 @@ static int ensure_ws(fe_problem *p, int m, bool mixed)
     hipError_t e = hipSuccess;
     double **vecs[] = {&w->R, &w->Rh, &w->R1, &w->xt, &w->delta, &w->rhs, &w->tmp};
     for (double **q : vecs)
-        if (e == hipSuccess) e = hipMalloc(q, nb);
-    if (e == hipSuccess) e = hipMalloc(&w->V, nb * (m + 1));
-    if (e == hipSuccess) e = hipMalloc(&w->Z, nb * m);
-    if (e == hipSuccess && mixed) e = hipMalloc(&w->Z32, sizeof(float) * p->ndof * m);
-    if (e == hipSuccess) e = hipMalloc(&w->D, sizeof(double) * 25 * p->nn);
-    if (e == hipSuccess && mixed) e = hipMalloc(&w->D32, sizeof(float) * 25 * p->nn);
-    if (e == hipSuccess && mixed) e = hipMalloc(&w->x32, sizeof(float) * p->ndof);
-    if (e == hipSuccess) e = hipMalloc(&w->hbuf, sizeof(double) * 256);
-    if (e == hipSuccess) e = hipMalloc(&w->ydev, sizeof(double) * 256);
-    if (e == hipSuccess) e = hipHostMalloc(&w->hhost, sizeof(double) * 256);
+        if (e == hipSuccess) e = dalloc(p, q, nb);
+    if (e == hipSuccess) e = dalloc(p, &w->V, nb * (m + 1));
+    if (e == hipSuccess) e = dalloc(p, &w->Z, nb * m);
+    if (e == hipSuccess && mixed) e = dalloc(p, &w->Z32, sizeof(float) * p->ndof * m);
+    if (e == hipSuccess) e = dalloc(p, &w->D, sizeof(double) * 25 * p->nn);
+    if (e == hipSuccess && mixed) e = dalloc(p, &w->D32, sizeof(float) * 25 * p->nn);
+    if (e == hipSuccess && mixed) e = dalloc(p, &w->x32, sizeof(float) * p->ndof);
+    if (e == hipSuccess) e = dalloc(p, &w->hbuf, sizeof(double) * 256);
+    if (e == hipSuccess) e = dalloc(p, &w->ydev, sizeof(double) * 256);
+    if (e == hipSuccess) e = halloc(p, &w->hhost, sizeof(double) * 256);
     for (auto &ev : w->ev)
         if (e == hipSuccess) e = hipEventCreate(&ev);
     if (e == hipSuccess && !p->slots25)
-        e = hipMalloc(&p->slots25, (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double));
+        e = dalloc(p, &p->slots25, (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double));
     if (e != hipSuccess) {
         free_ws(w);
         return hip_fail(e, "hipMalloc (solver workspace)");
@@ -340,13 +343,23 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
     fe_solve_opts d;
     fe_solve_opts_default(&d);
     if (!opts) opts = &d;
+    const bool mixed = opts->krylov_op_prec == FE_FP32;
     const int64_t nn = (int64_t)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
     const int64_t ndof = NF * nn;
     const int64_t ntile = (int64_t)((grid->nx + TX - 1) / TX) * ((grid->ny + TY - 1) / TY) *
                           ((grid->nz + TZ - 1) / TZ);
-    int64_t b = ws_bytes(ndof, nn, opts->restart, opts->krylov_op_prec == FE_FP32);
-    b += ntile * BOXN * (NF + 25) * 8;  // slots
-    b += nn + ndof + 66 * RED_BLOCKS * 8 + 256 * 8;
+    auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
+    int64_t b = 0;
+    // problem handle
+    b += r(nn) + r(ndof) + r(ntile * BOXN * NF * 8) + r(66 * RED_BLOCKS * 8) + r(256 * 8);
+    // solver workspace
+    b += 7 * r(8 * ndof) + r(8 * ndof * (opts->restart + 1)) + r(8 * ndof * opts->restart);
+    if (mixed) b += r(4 * ndof * opts->restart) + r(4 * 25 * nn) + r(4 * ndof);
+    b += r(8 * 25 * nn) + 2 * r(256 * 8) + r(ntile * BOXN * 25 * 8);
+    // multigrid hierarchy
+    const bool mg = opts->precond == FE_PC_MULTIGRID ||
+                    (opts->precond == FE_PC_AUTO && mg_num_levels(*grid) >= 2);
+    if (mg) b += mg_footprint_bytes(*grid, mixed);
     return b;
 }
 

@@ -219,7 +219,9 @@ __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, doubl
                         double *__restrict__ y)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a * x[i] + b * y[i];
+    if (i >= n) return;
+    // b == 0 overwrites y without reading it (y may hold anything, even NaN)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
 
 __global__ void k_xpld(int64_t n, const double *__restrict__ x, double lam,
@@ -410,4 +412,33 @@ hipError_t launch_compliance(const Geo &g, const double *x, const double *s, con
     return hipGetLastError();
 }
 
+}  // namespace fe
+
+namespace fe {
+namespace {
+// Walls (u, v, w, T on every boundary node) plus the pressure of node 0.
+__global__ void k_wall_mask(int nx, int ny, int nz, uint8_t *__restrict__ nmask,
+                            uint8_t *__restrict__ dof_mask)
+{
+    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int I = (int)(n % (nx + 1));
+    const int64_t r = n / (nx + 1);
+    const int J = (int)(r % (ny + 1)), K = (int)(r / (ny + 1));
+    const bool wall = I == 0 || J == 0 || K == 0 || I == nx || J == ny || K == nz;
+    uint8_t m = wall ? (uint8_t)(1 | 2 | 4 | 16) : (uint8_t)0;
+    if (n == 0) m |= 8;
+    nmask[n] = m;
+    for (int f = 0; f < NF; ++f) dof_mask[NF * n + f] = (m >> f) & 1;
+}
+}  // namespace
+
+hipError_t launch_wall_mask(int nx, int ny, int nz, uint8_t *nmask, uint8_t *dof_mask, hipStream_t st)
+{
+    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    hipLaunchKernelGGL(k_wall_mask, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, nx, ny, nz,
+                       nmask, dof_mask);
+    return hipGetLastError();
+}
 }  // namespace fe

@@ -26,7 +26,7 @@ EXPORTS = [
     "fe_residual", "fe_jvp", "fe_adjoint_jtvp", "fe_dR_dgamma", "fe_compliance",
     "fe_solve_opts_default", "newton_solve", "fe_adjoint_solve", "fe_block_diagonal",
     "fe_line_search_lambda", "fe_solve_footprint_bytes", "serve_create", "serve_submit",
-    "serve_poll", "serve_times", "serve_destroy", "fe_last_error", "fe_version",
+    "serve_poll", "serve_times", "serve_error", "serve_destroy", "fe_last_error", "fe_version",
 ]
 
 
@@ -116,6 +116,8 @@ def lib() -> ctypes.CDLL:
         L.serve_poll.argtypes = [vp, ctypes.c_uint64, vp, P(FeSolveReport)]
         L.serve_times.argtypes = [vp, ctypes.c_uint64, P(dbl), P(dbl), P(dbl)]
         L.serve_destroy.argtypes = [vp]
+        L.serve_error.argtypes = [vp, ctypes.c_uint64]
+        L.serve_error.restype = ctypes.c_char_p
         L.fe_last_error.restype = ctypes.c_char_p
         L.fe_version.restype = ctypes.c_char_p
         _lib = L
@@ -308,3 +310,82 @@ def fe_solve_footprint_bytes(nx, ny, nz, h=1.0, opts: Optional[FeSolveOpts] = No
 
 def fe_version() -> str:
     return lib().fe_version().decode()
+
+
+class Server:
+    """Continuous-batching solve server (``serve_*`` entry points).
+
+    Requests carry their own grid, parameters, design and source (host numpy
+    arrays, copied at submit); walls and the pressure pin are applied by the
+    library and every solve starts from x = 0."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().serve_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_active),
+                                  ctypes.byref(h)), "serve_create")
+        self.handle = h
+        self.n_dof = {}
+
+    def submit(self, nx, ny, nz, h, phys: FePhys, gamma, s, opts: Optional[FeSolveOpts] = None,
+               allow_enomem=False) -> int:
+        import numpy as np
+        g = np.ascontiguousarray(gamma, dtype=np.float64)
+        ss = np.ascontiguousarray(s, dtype=np.float64)
+        assert g.size == nx * ny * nz and ss.size == nx * ny * nz
+        t = ctypes.c_uint64()
+        grid = FeGrid(nx, ny, nz, h)
+        rc = lib().serve_submit(self.handle, ctypes.byref(grid), ctypes.byref(phys),
+                                g.ctypes.data_as(ctypes.c_void_p), ss.ctypes.data_as(ctypes.c_void_p),
+                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(t))
+        _check(rc, "serve_submit", ok=(FE_OK, FE_ENOMEM) if allow_enomem else (FE_OK,))
+        self.n_dof[t.value] = 5 * (nx + 1) * (ny + 1) * (nz + 1)
+        return t.value
+
+    def poll(self, ticket: int, want_x=True):
+        """(status, x or None, report dict); status FE_PENDING while not finished."""
+        import numpy as np
+        x = np.empty(self.n_dof[ticket]) if want_x else None
+        rep = FeSolveReport()
+        rc = lib().serve_poll(self.handle, ctypes.c_uint64(ticket),
+                              x.ctypes.data_as(ctypes.c_void_p) if want_x else None,
+                              ctypes.byref(rep))
+        if rc == FE_PENDING:
+            return rc, None, None
+        return rc, x, rep.as_dict()
+
+    def error(self, ticket: int) -> str:
+        return lib().serve_error(self.handle, ctypes.c_uint64(ticket)).decode()
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().serve_times(self.handle, ctypes.c_uint64(ticket), ctypes.byref(a), ctypes.byref(b),
+                          ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def wait(self, ticket: int, poll_s=0.0005, timeout_s=600.0):
+        import time
+        t0 = time.time()
+        while True:
+            rc, x, rep = self.poll(ticket)
+            if rc != FE_PENDING:
+                return rc, x, rep
+            if time.time() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} not finished after {timeout_s} s")
+            time.sleep(poll_s)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

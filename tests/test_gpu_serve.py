@@ -1,0 +1,116 @@
+"""Continuous-batching server: results alone vs in a mix, memory admission,
+failure isolation, correctness against the oracle's residual."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_04596_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def submit(fe, srv, p, opts):
+    ph = fe.make_phys(p.Pr, p.Gr, p.Ck, p.qf, p.alpha_max, p.q_alpha, p.eg)
+    return srv.submit(p.nx, p.ny, p.nz, p.h, ph, p.gamma, p.s, opts)
+
+
+def test_same_result_alone_and_in_the_mix(fe):
+    reqs = inputs.serving_trace(n_requests=12, seed=4000)
+    probs = [inputs.request_problem(r) for r in reqs]
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    alone = {}
+    with fe.Server(4 << 30, max_active=1) as srv:
+        for i in (0, 5):
+            t = submit(fe, srv, probs[i], opts)
+            rc, x, rep = srv.wait(t)
+            assert rc == fe.FE_OK, rep
+            alone[i] = x
+    with fe.Server(4 << 30, max_active=6) as srv:
+        tickets = [submit(fe, srv, p, opts) for p in probs]
+        res = [srv.wait(t) for t in tickets]
+        times = [srv.times(t) for t in tickets]
+    for i, (rc, x, rep) in enumerate(res):
+        p = probs[i]
+        assert rc == fe.FE_OK, (i, rep)
+        r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+        r = np.linalg.norm(oracle.residual(p, x, mask="solve"))
+        assert r <= 1e-8 * r0 * 1.0001, (i, r / r0)
+    for i, x in alone.items():
+        assert np.array_equal(res[i][1], x), f"request {i} differs alone vs in the mix"
+    # several requests were on the GPU at the same time
+    overlaps = sum(1 for a in range(len(times)) for b in range(a + 1, len(times))
+                   if times[a][1] < times[b][2] and times[b][1] < times[a][2])
+    print(f"[serve] overlapping request pairs: {overlaps}")
+    assert overlaps > 0
+
+
+def test_admission_by_memory_budget(fe):
+    p = inputs.scaled_config(32, 32, 32, 1e4, seed=5)
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    fp = fe.fe_solve_footprint_bytes(32, 32, 32, p.h, opts)
+    # room for one 32^3 request at a time, even with 4 worker slots
+    with fe.Server(int(fp * 1.6), max_active=4) as srv:
+        tickets = [submit(fe, srv, p, opts) for _ in range(3)]
+        res = [srv.wait(t) for t in tickets]
+        times = [srv.times(t) for t in tickets]
+    assert all(r[0] == fe.FE_OK for r in res)
+    for k in range(1, 3):
+        assert times[k][1] >= times[k - 1][2] - 1e-6, "admitted before memory was released"
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[1][1], res[2][1])
+
+
+def test_failing_request_is_isolated(fe):
+    good = inputs.scaled_config(16, 16, 16, 1e4, seed=9)
+    bad = inputs.scaled_config(16, 16, 16, 1e4, seed=10)
+    bad.gamma[123] = np.nan
+    opts = fe.solve_opts(rtol_newton=1e-8)
+    with fe.Server(2 << 30, max_active=3) as srv:
+        t1 = submit(fe, srv, good, opts)
+        t2 = submit(fe, srv, bad, opts)
+        t3 = submit(fe, srv, good, opts)
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+        errs = [srv.error(t) for t in (t1, t2, t3)]
+    print(f"[serve] statuses {r1[0]} {r2[0]} {r3[0]} errors {errs}")
+    assert r1[0] == fe.FE_OK and r3[0] == fe.FE_OK
+    assert r2[0] == fe.FE_ENAN
+    assert np.array_equal(r1[1], r3[1])
+
+
+def test_oversized_request_is_refused(fe):
+    p = inputs.scaled_config(48, 48, 48, 1e4, seed=11)
+    with fe.Server(64 << 20, max_active=2) as srv:
+        t = submit_enomem = srv.submit(p.nx, p.ny, p.nz, p.h, fe.make_phys(Gr=p.Gr), p.gamma, p.s,
+                                       fe.solve_opts(), allow_enomem=True)
+        rc, _, _ = srv.poll(t)
+        assert rc == fe.FE_ENOMEM and submit_enomem == t
+
+
+@pytest.mark.parametrize("prec,pc", [("fp64", "multigrid"), ("mixed", "multigrid"),
+                                     ("fp64", "bjacobi")])
+def test_no_read_before_write_with_poisoned_memory(fe, monkeypatch, prec, pc):
+    """Every buffer a solve uses is filled with NaN bytes when allocated; the
+    solve must still succeed and give the result of a clean run."""
+    p = inputs.scaled_config(16, 16, 16, 1e4, seed=12)
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, precond=pc, max_lin=400)
+    with fe.Server(1 << 30, max_active=1) as srv:
+        clean = srv.wait(submit(fe, srv, p, opts))
+    monkeypatch.setenv("FE_ARENA_POISON", "1")
+    with fe.Server(1 << 30, max_active=1) as srv:
+        t = submit(fe, srv, p, opts)
+        poisoned = srv.wait(t)
+        err = srv.error(t)
+    assert clean[0] == fe.FE_OK and poisoned[0] == fe.FE_OK, err
+    assert np.array_equal(clean[1], poisoned[1])
