@@ -51,6 +51,10 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--max-newton", type=int, default=50)
     ap.add_argument("--max-lin", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving trace (Poisson arrivals, 20/s); 0 = skip")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--serve-max-active", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -82,6 +86,7 @@ def main():
     def step(rec):
         x64 = torch.zeros(n_dof, dtype=torch.float64, device=dev)
         fe.fe_residual(prob, x64, g, s, r)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         rep64 = fe.newton_solve(prob, g, s, x64, opts64, allow_not_converged=True)
         t_solve64 = time.perf_counter() - t0
@@ -97,6 +102,7 @@ def main():
             fe.fe_jvp(prob, x32, g, s, v32, out32)
         e2.record(stream)
         xm = torch.zeros(n_dof, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()  # the J v loops above were queued asynchronously
         t0 = time.perf_counter()
         repmx = fe.newton_solve(prob, g, s, xm, optsmx, allow_not_converged=True)
         t_solvemx = time.perf_counter() - t0
@@ -144,6 +150,11 @@ def main():
                 "unit": "GB/s", "frac": bytes_alg / t_jv64 / PEAK_HBM, "traffic": None,
                 "kernel": "fe_jvp FP64 (element pass + shared-node pass)"}
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
+                            args.serve_max_active)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_seconds)
@@ -170,10 +181,39 @@ def main():
         "solve_mixed_phase_s": {k: last["repmx"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
         "mixed_vs_fp64_rel": last["mixed_vs_fp64"], "mixed_res_rel": last["mixed_res_rel"],
         "jv32_vs_jv64_rel": last["jv32_vs_jv64"],
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "serving": serve,
     }
     prob.close()
     print(json.dumps(line), flush=True)
+
+
+def serve_trace(fe, inputs, n, budget_gb, max_active):
+    """Serving workload: n requests with Poisson arrivals at 20/s, grids uniform
+    over {16,24,32,48}^3, log10 Gr uniform in [3,5], 40 %-solid smoothed random
+    designs, mixed precision to 1e-8; latency = completion - arrival."""
+    import time as _t
+    reqs = inputs.serving_trace(n_requests=n, rate_per_s=20.0, seed=4000)
+    probs = [inputs.request_problem(r) for r in reqs]
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    lat, tickets, statuses = [], [], []
+    with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+        t0 = _t.perf_counter()
+        for r, pr in zip(reqs, probs):
+            wait = t0 + r.arrival_s - _t.perf_counter()
+            if wait > 0:
+                _t.sleep(wait)
+            ph = fe.make_phys(pr.Pr, pr.Gr, pr.Ck, pr.qf, pr.alpha_max, pr.q_alpha, pr.eg)
+            tickets.append(srv.submit(pr.nx, pr.ny, pr.nz, pr.h, ph, pr.gamma, pr.s, opts))
+        for t in tickets:
+            rc, _, _ = srv.wait(t)
+            statuses.append(rc)
+        times = [srv.times(t) for t in tickets]
+    lat = np.array([d - a for a, _, d in times])
+    makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
+    return {"requests": n, "rate_per_s": 20.0, "budget_gb": budget_gb, "max_active": max_active,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "solves_per_s": n / makespan, "all_converged": all(s == 0 for s in statuses),
+            "queue_wait_p50_s": float(np.percentile([b - a for a, b, _ in times], 50))}
 
 
 def cpu_baseline(p, seconds):

@@ -127,6 +127,7 @@ typedef struct {
     int precond;            /* FE_PC_AUTO (default), FE_PC_BJACOBI or FE_PC_MULTIGRID */
     int mg_nu;              /* multigrid: smoothing sweeps before and after (default 2) */
     double mg_omega;        /* multigrid: block-Jacobi damping (default 0.6) */
+    double atol_newton;     /* also stop when |R|_2 <= atol_newton (default 0; for warm starts) */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

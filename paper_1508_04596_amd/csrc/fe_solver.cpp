@@ -309,6 +309,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->precond = FE_PC_AUTO;
     o->mg_nu = 2;
     o->mg_omega = 0.6;
+    o->atol_newton = 0.0;
 }
 
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
@@ -442,7 +443,7 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     int status = FE_NOT_CONVERGED;
     double lam = 1.0;
     while (true) {
-        if (rn <= opts.rtol_newton * r0) {
+        if (rn <= opts.rtol_newton * r0 || rn <= opts.atol_newton) {
             status = FE_OK;
             break;
         }

@@ -47,7 +47,7 @@ class FeSolveOpts(ctypes.Structure):
                 ("max_lin", ctypes.c_int), ("n_refine", ctypes.c_int),
                 ("krylov_op_prec", ctypes.c_int), ("ls_lambda_min", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
-                ("mg_omega", ctypes.c_double)]
+                ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double)]
 
 
 class FeSolveReport(ctypes.Structure):
