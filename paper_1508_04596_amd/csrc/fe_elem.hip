@@ -29,13 +29,17 @@ namespace {
 
 constexpr double QG = 0.57735026918962576451;  // Gauss abscissa 1/sqrt(3)
 
-// Gauss loop unrolled (compile-time signs) for FP32, rolled for FP64 where the
-// unrolled form runs out of registers.
+// Gauss loop rolled (run-time signs) by default: the unrolled form (compile-time
+// signs, fewer instructions) needs more registers than a wave64 can hold
+// without spilling in FP64, and runs at lower occupancy in FP32.
 #ifndef FE_UNROLL64
 #define FE_UNROLL64 0
 #endif
+#ifndef FE_UNROLL32
+#define FE_UNROLL32 0
+#endif
 template <typename T>
-struct Unroll { static constexpr bool value = true; };
+struct Unroll { static constexpr bool value = FE_UNROLL32 != 0; };
 template <>
 struct Unroll<double> { static constexpr bool value = FE_UNROLL64 != 0; };
 

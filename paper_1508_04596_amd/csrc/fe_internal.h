@@ -13,7 +13,16 @@ namespace fe {
 constexpr int NF = 5;  // unknowns per node: u, v, w, p, T
 
 // Element tile processed by one workgroup: TX*TY*TZ elements, one per thread.
-constexpr int TX = 8, TY = 8, TZ = 4;
+#ifndef FE_TILE_X
+#define FE_TILE_X 8
+#endif
+#ifndef FE_TILE_Y
+#define FE_TILE_Y 8
+#endif
+#ifndef FE_TILE_Z
+#define FE_TILE_Z 4
+#endif
+constexpr int TX = FE_TILE_X, TY = FE_TILE_Y, TZ = FE_TILE_Z;
 constexpr int NTHR = TX * TY * TZ;  // 256 threads = 4 wave64
 constexpr int BX = TX + 1, BY = TY + 1, BZ = TZ + 1;
 constexpr int BOXN = BX * BY * BZ;  // nodes of the tile's node box (405)
@@ -81,6 +90,12 @@ hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
                          bool sqrt_last, hipStream_t st);
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st);
+// Orthogonalise w against V_0..V_{k-1} by classical Gram-Schmidt with one
+// conditional second pass (taken when the first pass removes more than 1 -
+// 1/sqrt(2) of the norm): hbuf[0..k) = first-pass coefficients, hbuf[65..65+k)
+// = second-pass coefficients (0 when skipped), hbuf[130] = |w| after.
+hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, double *hbuf,
+                      double *partial, hipStream_t st);
 // y = a*x + b*y (y is not read when b == 0)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
 // y = x + lam*d

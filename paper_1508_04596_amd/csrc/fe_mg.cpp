@@ -184,6 +184,7 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
     mg->kl = mg->ku = bw;
     mg->A.assign((size_t)C.ndof * C.ndof, 0.0);
     mg->piv.assign(C.ndof, 0);
+    mg->Lc.assign((size_t)C.ndof * bw, 0.0);
     mg->hb.assign(C.ndof, 0.0);
     *out = mg;
     return FE_OK;
@@ -233,9 +234,11 @@ static int band_lu(Mg *mg)
         for (int64_t i = k + 1; i <= iend; ++i) {
             const double l = A[i * n + k] * inv;
             A[i * n + k] = l;
+            mg->Lc[k * kl + (i - k - 1)] = l;
             if (l != 0.0)
                 for (int64_t j = k + 1; j <= jend; ++j) A[i * n + j] -= l * A[k * n + j];
         }
+        for (int64_t i = iend + 1; i <= k + kl; ++i) mg->Lc[k * kl + (i - k - 1)] = 0.0;
     }
     return FE_OK;
 }
@@ -246,11 +249,13 @@ static void band_solve(const Mg *mg, double *b, bool transpose)
     const int kl = mg->kl, ku = mg->ku;
     const double *A = mg->A.data();
     if (!transpose) {
+        const double *Lc = mg->Lc.data();  // multipliers of column k, contiguous
         for (int64_t k = 0; k < n; ++k) {
             const int64_t p = mg->piv[k];
             if (p != k) std::swap(b[k], b[p]);
-            const int64_t iend = std::min<int64_t>(n - 1, k + kl);
-            for (int64_t i = k + 1; i <= iend; ++i) b[i] -= A[i * n + k] * b[k];
+            const int64_t cnt = std::min<int64_t>(n - 1, k + kl) - k;
+            const double bk = b[k];
+            for (int64_t q = 0; q < cnt; ++q) b[k + 1 + q] -= Lc[k * kl + q] * bk;
         }
         for (int64_t k = n - 1; k >= 0; --k) {
             const int64_t jend = std::min<int64_t>(n - 1, k + kl + ku);
@@ -266,10 +271,11 @@ static void band_solve(const Mg *mg, double *b, bool transpose)
             for (int64_t j = j0; j < k; ++j) s -= A[j * n + k] * b[j];
             b[k] = s / A[k * n + k];
         }
+        const double *Lc = mg->Lc.data();
         for (int64_t k = n - 1; k >= 0; --k) {
-            const int64_t iend = std::min<int64_t>(n - 1, k + kl);
+            const int64_t cnt = std::min<int64_t>(n - 1, k + kl) - k;
             double s = b[k];
-            for (int64_t i = k + 1; i <= iend; ++i) s -= A[i * n + k] * b[i];
+            for (int64_t q = 0; q < cnt; ++q) s -= Lc[k * kl + q] * b[k + 1 + q];
             b[k] = s;
             const int64_t p = mg->piv[k];
             if (p != k) std::swap(b[k], b[p]);

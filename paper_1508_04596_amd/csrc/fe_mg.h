@@ -31,7 +31,7 @@ struct Mg {
     // coarsest level: dense-stored band LU
     int64_t nc = 0;
     int kl = 0, ku = 0;
-    std::vector<double> A, hb;
+    std::vector<double> A, hb, Lc;  // dense band LU, work vector, L multipliers by column
     std::vector<int> piv;
     double *probe = nullptr, *probe_out = nullptr, *hbuf = nullptr;
 };

@@ -1,5 +1,6 @@
 // Host-driven solvers over the device kernels: flexible GMRES with classical
-// Gram-Schmidt (two passes) in FP64, damped Newton with the quadratic L2 line
+// Gram-Schmidt (a second pass where the first loses more than 1 - 1/sqrt(2) of
+// the norm) in FP64, damped Newton with the quadratic L2 line
 // search (Sec. "Solving the non-linear system"), the adjoint solve, and the
 // FP32-operator / FP64-residual refinement used in mixed mode.
 //
@@ -184,12 +185,7 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
             FE_CHECK_HIP(L.op_z(zj, vn));
             FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
             const int k = j + 1;
-            FE_CHECK_HIP(launch_multidot(w->V, ld, k, vn, n, p->partial, st));
-            FE_CHECK_HIP(launch_reduce(p->partial, k, w->hbuf, nullptr, false, st));
-            FE_CHECK_HIP(launch_update_dot(w->V, ld, k, w->hbuf, vn, n, k, p->partial, st));
-            FE_CHECK_HIP(launch_reduce(p->partial, k, w->hbuf + 65, nullptr, false, st));
-            FE_CHECK_HIP(launch_update_dot(w->V, ld, k, w->hbuf + 65, vn, n, -1, p->partial, st));
-            FE_CHECK_HIP(launch_reduce(p->partial, 1, w->hbuf + 130, nullptr, true, st));
+            FE_CHECK_HIP(launch_cgs(w->V, ld, k, vn, n, w->hbuf, p->partial, st));
             FE_CHECK_HIP(launch_scale_div(n, vn, w->hbuf + 130, vn, st));
             FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
             FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * 131,

@@ -92,10 +92,78 @@ __global__ __launch_bounds__(RED_THREADS) void k_update_dot(const double *__rest
     if (partial) block_sums<KMAX>(acc, k2 == -1 ? 1 : k2, partial);
 }
 
+// Exact-count variants (K known at compile time, every load of an element
+// issued together).  flag: optional device flag; the kernel does nothing
+// when it is 0 (conditional second Gram-Schmidt pass).
+template <int K, bool NORM>
+__global__ __launch_bounds__(RED_THREADS) void k_mdot(const double *__restrict__ V, int64_t ld,
+                                                      const double *__restrict__ w, int64_t n,
+                                                      double *__restrict__ partial,
+                                                      const double *__restrict__ flag)
+{
+    if (flag && flag[0] == 0.0) return;
+    constexpr int KA = K + (NORM ? 1 : 0);
+    double acc[KA];
+#pragma unroll
+    for (int j = 0; j < KA; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+        double vj[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] += vj[j] * wi;
+        if (NORM) acc[KA - 1] += wi * wi;
+    }
+    block_sums<KA>(acc, KA, partial);
+}
+
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void k_upd(const double *__restrict__ V, int64_t ld,
+                                                     const double *__restrict__ h,
+                                                     double *__restrict__ w, int64_t n,
+                                                     double *__restrict__ partial,
+                                                     const double *__restrict__ flag)
+{
+    if (flag && flag[0] == 0.0) return;
+    __shared__ double hs[K];
+    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[1] = {0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double vj[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
+        double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) wi -= hs[j] * vj[j];
+        w[i] = wi;
+        acc[0] += wi * wi;
+    }
+    block_sums<1>(acc, 1, partial);
+}
+
+// flag = 1 when the projected norm fell below 1/sqrt(2) of the original norm
+// (a second Gram-Schmidt pass is needed), else 0.
+__global__ void k_reorth_flag(const double *__restrict__ w2_before, const double *__restrict__ beta,
+                              double *__restrict__ flag)
+{
+    const double nb = sqrt(w2_before[0]);
+    flag[0] = (beta[0] < 0.70710678118654752 * nb) ? 1.0 : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial,
                                                 double *__restrict__ out,
-                                                const double *__restrict__ add, int k, int sqrt_last)
+                                                const double *__restrict__ add, int k, int sqrt_last,
+                                                const double *__restrict__ flag, int flag_mode)
 {
+    // flag_mode 1: write zeros when *flag == 0; 2: leave out untouched when *flag == 0
+    if (flag && flag[0] == 0.0) {
+        if (flag_mode == 1 && threadIdx.x == 0) out[blockIdx.x] = 0.0;
+        return;
+    }
     // one workgroup per output; RED_BLOCKS partials, summed in a fixed tree
     static_assert(RED_BLOCKS % 256 == 0, "RED_BLOCKS must be a multiple of 256");
     __shared__ double red[4];
@@ -354,7 +422,81 @@ hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
                          bool sqrt_last, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, out, add, k, sqrt_last ? 1 : 0);
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, out, add, k, sqrt_last ? 1 : 0,
+                       (const double *)nullptr, 0);
+    return hipGetLastError();
+}
+
+// Exact-count dispatch for 1 <= k <= 32.
+#define FE_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) \
+    X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) \
+    X(29) X(30) X(31) X(32)
+
+static hipError_t mdot_exact(int k, bool norm, const double *V, int64_t ld, const double *w,
+                             int64_t n, double *partial, const double *flag, hipStream_t st)
+{
+    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    switch (k) {
+#define FE_MD(K)                                                                               \
+    case K:                                                                                    \
+        if (norm)                                                                              \
+            hipLaunchKernelGGL((k_mdot<K, true>), g, b, 0, st, V, ld, w, n, partial, flag);    \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_mdot<K, false>), g, b, 0, st, V, ld, w, n, partial, flag);   \
+        break;
+        FE_K_CASES(FE_MD)
+#undef FE_MD
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t upd_exact(int k, const double *V, int64_t ld, const double *h, double *w,
+                            int64_t n, double *partial, const double *flag, hipStream_t st)
+{
+    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    switch (k) {
+#define FE_UP(K)                                                                               \
+    case K:                                                                                    \
+        hipLaunchKernelGGL((k_upd<K>), g, b, 0, st, V, ld, h, w, n, partial, flag);            \
+        break;
+        FE_K_CASES(FE_UP)
+#undef FE_UP
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, double *hbuf,
+                      double *partial, hipStream_t st)
+{
+    hipError_t e;
+    if (k > 32) {  // long bases: unconditional two passes with the generic kernels
+        if ((e = launch_multidot(V, ld, k, w, n, partial, st)) != hipSuccess) return e;
+        if ((e = launch_reduce(partial, k, hbuf, nullptr, false, st)) != hipSuccess) return e;
+        if ((e = launch_update_dot(V, ld, k, hbuf, w, n, k, partial, st)) != hipSuccess) return e;
+        if ((e = launch_reduce(partial, k, hbuf + 65, nullptr, false, st)) != hipSuccess) return e;
+        if ((e = launch_update_dot(V, ld, k, hbuf + 65, w, n, -1, partial, st)) != hipSuccess) return e;
+        return launch_reduce(partial, 1, hbuf + 130, nullptr, true, st);
+    }
+    double *flag = hbuf + 131;
+    // pass 1: h1 = V^T w and |w|^2 (stored at hbuf[k]), w -= V h1, beta = |w|
+    if ((e = mdot_exact(k, true, V, ld, w, n, partial, nullptr, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf, (const double *)nullptr,
+                       k + 1, 0, (const double *)nullptr, 0);
+    if ((e = upd_exact(k, V, ld, hbuf, w, n, partial, nullptr, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
+                       (const double *)nullptr, 1, 1, (const double *)nullptr, 0);
+    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(1), 0, st, hbuf + k, hbuf + 130, flag);
+    // pass 2 only where the flag asks for it: h2 (zeros otherwise), w -= V h2, beta
+    if ((e = mdot_exact(k, false, V, ld, w, n, partial, flag, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, hbuf + 65, (const double *)nullptr,
+                       k, 0, flag, 1);
+    if ((e = upd_exact(k, V, ld, hbuf + 65, w, n, partial, flag, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
+                       (const double *)nullptr, 1, 1, flag, 2);
     return hipGetLastError();
 }
 
