@@ -12,8 +12,8 @@ One step = the whole hot path on that input:
 
 Prints one JSON line.  ``value`` is the FP64 J v throughput in GDOF/s; the solve
 times, the FP32 rate and the mixed-vs-FP64 error ride along.  ``roofline``
-describes the FP64 element kernel of J v, timed with HIP events on the stream
-it runs on; ``cpu_baseline`` times the CPU oracle's J v on the host cores.
+describes the FP64 element-pass kernel of J v, timed with HIP events that the
+library records around each of its launches on the stream it runs on; ``cpu_baseline`` times the CPU oracle's J v on the host cores.
 """
 from __future__ import annotations
 
@@ -34,6 +34,15 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_ELEM_JV = 4212.0
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
+# HBM bytes per launch of the FP64 J v element-pass kernel on the 64^3 workload
+# (1024 tiles), from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
+# torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
+# 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
+# whenever the element kernel changes.
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = 21124.0, 17298.375
+FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
+ELEM_TRAFFIC_BYTES = 1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
 # Algorithmic HBM bytes of one FP64 J v: x, v read and J v written (5 values per
 # node each), gamma and s read (one value per element each).
 def jv_bytes(n_nodes, n_el, word=8):
@@ -46,6 +55,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--jv-reps", type=int, default=1000)
+    ap.add_argument("--kernel-reps", type=int, default=200,
+                    help="J v launches timed per precision with per-launch events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", action="store_true")
@@ -101,13 +112,24 @@ def main():
         for _ in range(args.jv_reps):
             fe.fe_jvp(prob, x32, g, s, v32, out32)
         e2.record(stream)
+        # element-pass kernel alone: HIP events recorded by the library around
+        # each launch, on the stream the kernel runs on
+        fe.fe_kernel_timer(prob, True)
+        for _ in range(args.kernel_reps):
+            fe.fe_jvp(prob, x64, g, s, vdir, out64)
+        ms64, n64 = fe.fe_kernel_timer_read(prob)
+        for _ in range(args.kernel_reps):
+            fe.fe_jvp(prob, x32, g, s, v32, out32)
+        ms32, n32 = fe.fe_kernel_timer_read(prob)
+        fe.fe_kernel_timer(prob, False)
         xm = torch.zeros(n_dof, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()  # the J v loops above were queued asynchronously
         t0 = time.perf_counter()
         repmx = fe.newton_solve(prob, g, s, xm, optsmx, allow_not_converged=True)
         t_solvemx = time.perf_counter() - t0
         torch.cuda.synchronize()
-        rec.update(t_jv64=e0.elapsed_time(e1) * 1e-3 / args.jv_reps,
+        rec.update(t_elem64=ms64 * 1e-3 / max(n64, 1), t_elem32=ms32 * 1e-3 / max(n32, 1),
+                   t_jv64=e0.elapsed_time(e1) * 1e-3 / args.jv_reps,
                    t_jv32=e1.elapsed_time(e2) * 1e-3 / args.jv_reps,
                    t_solve64=t_solve64, t_solvemx=t_solvemx, rep64=rep64, repmx=repmx,
                    mixed_vs_fp64=float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)),
@@ -135,20 +157,18 @@ def main():
     last = recs[-1]
     value = n_dof / t_jv64 / 1e9
 
-    roof = None
+    t_elem64 = float(np.median([q["t_elem64"] for q in recs]))
+    t_elem32 = float(np.median([q["t_elem32"] for q in recs]))
     bytes_alg = jv_bytes(n_nodes, n_el)
-    if FLOPS_PER_ELEM_JV:
-        achieved = FLOPS_PER_ELEM_JV * n_el / t_jv64
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                "kernel": "fe_jvp FP64 (element pass + shared-node pass)",
-                "flops_per_elem": FLOPS_PER_ELEM_JV,
-                "hbm_alg_GBps": bytes_alg / t_jv64 / 1e9,
-                "hbm_alg_frac": bytes_alg / t_jv64 / PEAK_HBM}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_alg / t_jv64 / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": bytes_alg / t_jv64 / PEAK_HBM, "traffic": None,
-                "kernel": "fe_jvp FP64 (element pass + shared-node pass)"}
+    achieved = FLOPS_PER_ELEM_JV * n_el / t_elem64
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+            "traffic": ELEM_TRAFFIC_BYTES,
+            "kernel": "k_elem<double,double,JV> (FP64 J v element pass, 1024 tiles of 8x8x4)",
+            "kernel_avg_us": t_elem64 * 1e6, "flops_per_elem": FLOPS_PER_ELEM_JV,
+            "traffic_GBps": ELEM_TRAFFIC_BYTES / t_elem64 / 1e9,
+            "jv_alg_bytes": bytes_alg,
+            "jv_op_alg_GBps": bytes_alg / t_jv64 / 1e9}
 
     serve = None
     if args.serve_requests > 0:
@@ -169,6 +189,7 @@ def main():
                                "Newton to 1e-8 FP64 and mixed",
                    "jv_reps": args.jv_reps},
         "jv_fp64_ms": t_jv64 * 1e3, "jv_fp32_ms": t_jv32 * 1e3,
+        "elem_fp64_us": t_elem64 * 1e6, "elem_fp32_us": t_elem32 * 1e6,
         "jv_fp32_gdofs": n_dof / t_jv32 / 1e9,
         "solve_fp64_s": last["t_solve64"], "solve_mixed_s": last["t_solvemx"],
         "solve_fp64_converged": last["rep64"]["status"] == 0,

@@ -96,6 +96,18 @@ int fe_residual(fe_problem *p, const double *x, const double *gamma, const doubl
 int fe_jvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma, const double *s_elem,
            const void *v, void *jv, hipStream_t stream);
 
+/* Element-pass timer of fe_jvp (instrumentation; it changes no result).
+ * fe_kernel_timer(p, 1) clears the record and starts timing: every later
+ * fe_jvp on p records a pair of HIP events on its stream, right before and
+ * right after its element-pass kernel (the tile kernel; the shared-node pass
+ * that follows is not inside the pair).  fe_kernel_timer(p, 0) stops timing.
+ * fe_kernel_timer_read waits for the last recorded pair, writes the summed
+ * element-pass time in milliseconds and the number of timed launches, and
+ * clears the record.  Events are created on first use and kept by the handle
+ * (one pair per launch between reads).  FE_EINVAL for NULL arguments. */
+int fe_kernel_timer(fe_problem *p, int enable);
+int fe_kernel_timer_read(fe_problem *p, double *elem_ms, int64_t *launches);
+
 /* jtw = J(x)^T w, the exact transpose of fe_jvp's operator, evaluated element by
  * element in reverse mode with every element quantity recomputed from x. */
 int fe_adjoint_jtvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma,

@@ -164,6 +164,7 @@ void fe_free_solver_ws(fe_problem *p);  // fe_solver.cpp
 int fe_problem_destroy(fe_problem *p)
 {
     if (!p) return FE_OK;
+    for (hipEvent_t e : p->timer_ev) (void)hipEventDestroy(e);
     fe_free_solver_ws(p);
     dfree(p, p->nmask);
     dfree(p, p->dof_mask);
@@ -209,18 +210,59 @@ int fe_jvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma, cons
         set_error("fe_jvp: NULL argument");
         return FE_EINVAL;
     }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (p->timer_on) {
+        while (p->timer_ev.size() < 2 * (p->timer_n + 1)) {
+            hipEvent_t e;
+            FE_CHECK_HIP(hipEventCreate(&e));
+            p->timer_ev.push_back(e);
+        }
+        ev0 = p->timer_ev[2 * p->timer_n];
+        ev1 = p->timer_ev[2 * p->timer_n + 1];
+    }
     if (prec == FE_FP64) {
         FE_CHECK_HIP((launch_elem<double, double>(OP_JV, p->geo, (const double *)x,
                                                   (const double *)v, gamma, s_elem, p->nmask,
-                                                  (double *)jv, p->slots, stream)));
+                                                  (double *)jv, p->slots, stream, ev0, ev1)));
     } else if (prec == FE_FP32) {
         FE_CHECK_HIP((launch_elem<float, float>(OP_JV, p->geo, (const float *)x, (const float *)v,
                                                 gamma, s_elem, p->nmask, (float *)jv,
-                                                (float *)p->slots, stream)));
+                                                (float *)p->slots, stream, ev0, ev1)));
     } else {
         set_error("fe_jvp: unknown precision");
         return FE_EINVAL;
     }
+    if (p->timer_on) ++p->timer_n;
+    return FE_OK;
+}
+
+int fe_kernel_timer(fe_problem *p, int enable)
+{
+    if (!p) {
+        set_error("fe_kernel_timer: NULL problem");
+        return FE_EINVAL;
+    }
+    p->timer_on = enable != 0;
+    p->timer_n = 0;
+    return FE_OK;
+}
+
+int fe_kernel_timer_read(fe_problem *p, double *elem_ms, int64_t *launches)
+{
+    if (!p || !elem_ms || !launches) {
+        set_error("fe_kernel_timer_read: NULL argument");
+        return FE_EINVAL;
+    }
+    double total = 0.0;
+    for (size_t i = 0; i < p->timer_n; ++i) {
+        float ms = 0.f;
+        FE_CHECK_HIP(hipEventSynchronize(p->timer_ev[2 * i + 1]));
+        FE_CHECK_HIP(hipEventElapsedTime(&ms, p->timer_ev[2 * i], p->timer_ev[2 * i + 1]));
+        total += ms;
+    }
+    *elem_ms = total;
+    *launches = (int64_t)p->timer_n;
+    p->timer_n = 0;
     return FE_OK;
 }
 

@@ -935,7 +935,7 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
 template <typename Tin, typename Tout>
 hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, const double *gamma,
                        const double *s, const uint8_t *nmask, Tout *out, Tout *slots,
-                       hipStream_t st)
+                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 grid((unsigned)n_tiles(g)), block(NTHR);
     const int64_t nn = n_nodes(g);
@@ -948,8 +948,16 @@ hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, cons
                            (const Tout *)slots, nmask, v, out);
         break;
     case OP_JV:
+        if (ev0) {
+            const hipError_t e = hipEventRecord(ev0, st);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL((k_elem<Tin, Tout, OP_JV>), grid, block, 0, st, g, x, v, gamma, s,
                            nmask, out, slots);
+        if (ev1) {
+            const hipError_t e = hipEventRecord(ev1, st);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL((k_combine<Tin, Tout, NF, OP_JV>), cgrid, cblock, 0, st, g,
                            (const Tout *)slots, nmask, v, out);
         break;
@@ -965,13 +973,13 @@ hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, cons
 
 template hipError_t launch_elem<double, double>(ElemOp, const Geo &, const double *, const double *,
                                                 const double *, const double *, const uint8_t *,
-                                                double *, double *, hipStream_t);
+                                                double *, double *, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_elem<float, float>(ElemOp, const Geo &, const float *, const float *,
                                               const double *, const double *, const uint8_t *,
-                                              float *, float *, hipStream_t);
+                                              float *, float *, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_elem<float, double>(ElemOp, const Geo &, const float *, const float *,
                                                const double *, const double *, const uint8_t *,
-                                               double *, double *, hipStream_t);
+                                               double *, double *, hipStream_t, hipEvent_t, hipEvent_t);
 
 hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st)

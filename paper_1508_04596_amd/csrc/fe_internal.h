@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "fe.h"
 
@@ -55,10 +56,12 @@ enum ElemOp { OP_RES = 0, OP_JV = 1, OP_JTV = 2 };
 // x, v: node vectors of type Tin; out: node vector of type Tout; nmask: per
 // node bit mask (bit f set = DOF f prescribed); slots: tile-face partial sums,
 // n_tiles * BOXN * 5 values of Tout.
+// ev0/ev1 (optional): recorded on st right before and right after the J v
+// element-pass kernel.
 template <typename Tin, typename Tout>
 hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, const double *gamma,
                        const double *s, const uint8_t *nmask, Tout *out, Tout *slots,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
 // Raw nodal 5x5 diagonal blocks of J (row-major [n][25]), masked rows/cols set
@@ -156,6 +159,11 @@ struct fe_problem {
     double *scal = nullptr;       // device scalars
     fe::SolverWs *ws = nullptr;    // Newton/FGMRES workspace (allocated on first solve)
     fe::Allocator *alloc = nullptr; // memory source of this problem's buffers
+    // Element-pass timer of fe_jvp (instrumentation, off by default): start/stop
+    // event pairs, timer_n of them recorded since the last read.
+    bool timer_on = false;
+    std::vector<hipEvent_t> timer_ev;
+    size_t timer_n = 0;
 };
 
 namespace fe {

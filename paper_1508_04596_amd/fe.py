@@ -99,6 +99,8 @@ def lib() -> ctypes.CDLL:
         L.fe_residual.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fe_jvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.fe_adjoint_jtvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fe_kernel_timer.argtypes = [vp, i32]
+        L.fe_kernel_timer_read.argtypes = [vp, P(dbl), P(ctypes.c_int64)]
         L.fe_dR_dgamma.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fe_compliance.argtypes = [vp, vp, vp, P(dbl), vp, vp]
         L.fe_block_diagonal.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -240,6 +242,19 @@ def fe_jvp(prob: Problem, x, gamma, s, v, out=None, stream=None):
                         _ptr(s, torch.float64), _ptr(v, x.dtype), _ptr(out, x.dtype),
                         _stream(stream)), "fe_jvp")
     return out
+
+
+def fe_kernel_timer(prob: Problem, enable: bool = True):
+    """Start (clearing the record) or stop timing fe_jvp's element-pass kernel."""
+    _check(lib().fe_kernel_timer(prob.handle, 1 if enable else 0), "fe_kernel_timer")
+
+
+def fe_kernel_timer_read(prob: Problem):
+    """(summed element-pass milliseconds, launches) since the last read; clears the record."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().fe_kernel_timer_read(prob.handle, ctypes.byref(ms), ctypes.byref(n)),
+           "fe_kernel_timer_read")
+    return ms.value, n.value
 
 
 def fe_adjoint_jtvp(prob: Problem, x, gamma, s, w, out=None, stream=None):

@@ -163,3 +163,27 @@ def test_repeatable_bitwise(fe):
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(r1, r2)
     prob.close()
+
+
+def test_kernel_timer_changes_no_result(fe):
+    """The element-pass timer counts every timed J v launch, reports a positive
+    time, and leaves the product bitwise unchanged."""
+    p = inputs.scaled_config(24, 16, 12, 1e4, seed=8)
+    prob = fe.Problem.from_inputs(p, mask="walls")
+    x = dev(inputs.random_state(p, 4))
+    v = dev(inputs.random_direction(p, 5))
+    g, s = dev(p.gamma), dev(p.s)
+    ref = fe.fe_jvp(prob, x, g, s, v).clone()
+    fe.fe_kernel_timer(prob, True)
+    outs = [fe.fe_jvp(prob, x, g, s, v).clone() for _ in range(5)]
+    ms, n = fe.fe_kernel_timer_read(prob)
+    out32 = fe.fe_jvp(prob, x.float(), g, s, v.float())
+    ms32, n32 = fe.fe_kernel_timer_read(prob)
+    fe.fe_kernel_timer(prob, False)
+    fe.fe_jvp(prob, x, g, s, v)
+    assert fe.fe_kernel_timer_read(prob) == (0.0, 0)
+    torch.cuda.synchronize()
+    assert n == 5 and ms > 0.0 and n32 == 1 and ms32 > 0.0
+    assert all(torch.equal(o, ref) for o in outs)
+    assert rel_norm(host(out32), host(ref)) < 1e-5
+    prob.close()
