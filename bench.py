@@ -40,9 +40,10 @@ PEAK_HBM = 8.0e12
 # torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
 # 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
 # whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 21124.0, 17298.375
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = None, None  # not yet taken for the current kernel
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
-ELEM_TRAFFIC_BYTES = 1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
+ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
+                      if ELEM_FETCH_KIB is not None else None)
 # Algorithmic HBM bytes of one FP64 J v: x, v read and J v written (5 values per
 # node each), gamma and s read (one value per element each).
 def jv_bytes(n_nodes, n_el, word=8):
@@ -166,7 +167,7 @@ def main():
             "traffic": ELEM_TRAFFIC_BYTES,
             "kernel": "k_elem<double,double,JV> (FP64 J v element pass, 1024 tiles of 8x8x4)",
             "kernel_avg_us": t_elem64 * 1e6, "flops_per_elem": FLOPS_PER_ELEM_JV,
-            "traffic_GBps": ELEM_TRAFFIC_BYTES / t_elem64 / 1e9,
+            "traffic_GBps": ELEM_TRAFFIC_BYTES / t_elem64 / 1e9 if ELEM_TRAFFIC_BYTES else None,
             "jv_alg_bytes": bytes_alg,
             "jv_op_alg_GBps": bytes_alg / t_jv64 / 1e9}
 

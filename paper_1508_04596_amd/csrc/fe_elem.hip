@@ -237,10 +237,28 @@ struct TileIdx {
     int nb[8];           // node-box index of the element's corners
 };
 
+#ifndef FE_XCD_REMAP
+#define FE_XCD_REMAP 1
+#endif
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Map workgroup b to a tile so that every XCD works through a contiguous range
+// of tiles: neighbouring tiles, which re-read each other's face nodes, then
+// share an L2.  A bijection on [0, n): the last n mod 8 tiles map to themselves.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3;
+    if (b >= (q << 3)) return b;
+    return (b & 7) * q + (b >> 3);
+}
+
 __device__ __forceinline__ TileIdx tile_index(const Geo &g)
 {
     TileIdx t;
+#if FE_XCD_REMAP
+    t.tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+#else
     t.tile = blockIdx.x;
+#endif
     t.btx = t.tile % g.ntx;
     int r = t.tile / g.ntx;
     t.bty = r % g.nty;
@@ -266,27 +284,44 @@ __device__ __forceinline__ int64_t gnode(const Geo &g, int I, int J, int K)
 
 // Stage the node box of x (and of the masked direction v) in LDS; zero the
 // output accumulator.
-template <typename T, int NVO>
+template <typename T, int NVO, bool HASV>
 __device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
                                       const T *__restrict__ v, const uint8_t *__restrict__ nmask,
                                       T (*sx)[BOXN], T (*sv)[BOXN], T *so)
 {
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
-    for (int idx = threadIdx.x; idx < BOXN * NF; idx += NTHR) {
-        int nb = idx / NF, f = idx - nb * NF;
-        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
-        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
-        T xv = T(0), vv = T(0);
-        if (I <= g.nx && J <= g.ny && K <= g.nz) {
-            int64_t gn = gnode(g, I, J, K);
-            xv = x[NF * gn + f];
-            if (v) {
-                vv = v[NF * gn + f];
-                if ((nmask[gn] >> f) & 1) vv = T(0);
-            }
+    // fixed trip count, unrolled: every thread issues all of its global loads
+    // before the first one is waited for
+    constexpr int NIT = (BOXN * NF + NTHR - 1) / NTHR;
+    T xv[NIT], vv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * NTHR;
+        // branch-free: entries outside the box or the grid load node 0 and
+        // are replaced by 0, so no load waits on a branch
+        const int nb = idx / NF, f = idx - nb * NF;
+        const int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        const int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        const bool in = idx < BOXN * NF && I <= g.nx && J <= g.ny && K <= g.nz;
+        const int64_t gn = in ? gnode(g, I, J, K) : 0;
+        const T xl = x[NF * gn + f];
+        xv[it] = in ? xl : T(0);
+        vv[it] = T(0);
+        if (HASV) {
+            const T vl = v[NF * gn + f];
+            const int m = nmask[gn];
+            const bool keep = in & (((m >> f) & 1) == 0);
+            vv[it] = keep ? vl : T(0);
         }
-        sx[f][nb] = xv;
-        if (sv) sv[f][nb] = vv;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * NTHR;
+        if (idx < BOXN * NF) {
+            int nb = idx / NF, f = idx - nb * NF;
+            sx[f][nb] = xv[it];
+            if (HASV) sv[f][nb] = vv[it];
+        }
     }
     if (NVO > 0)
         for (int idx = threadIdx.x; idx < BOXN * NVO; idx += NTHR) so[idx] = T(0);
@@ -571,7 +606,7 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
     using T = Tin;
     __shared__ TileSmem<T> S;
     const TileIdx t = tile_index(g);
-    stage<T, NF>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
+    stage<T, NF, OP != OP_RES>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
                  (OP == OP_RES) ? nullptr : S.v, &S.o[0][0]);
     __syncthreads();
 
@@ -601,23 +636,38 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
     }
     // write-out: complete nodes to out, shared ones to the tile's slots
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
-    for (int nb = threadIdx.x; nb < BOXN; nb += NTHR) {
-        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
-        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
-        if (I > g.nx || J > g.ny || K > g.nz) continue;
-        bool sh = shared_dir(lx, I, g.nx, TX) || shared_dir(ly, J, g.ny, TY) ||
-                  shared_dir(lz, K, g.nz, TZ);
-        if (sh) {
+    // fixed trip count: the node-mask loads of all of this thread's nodes are
+    // issued before the first is waited for
+    constexpr int NWO = (BOXN + NTHR - 1) / NTHR;
+    int64_t gnw[NWO];
+    int mw[NWO];
+    bool own[NWO], shw[NWO];
+#pragma unroll
+    for (int it = 0; it < NWO; ++it) {
+        const int nb = threadIdx.x + it * NTHR;
+        const int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        const int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        const bool in = nb < BOXN && I <= g.nx && J <= g.ny && K <= g.nz;
+        const bool sh = shared_dir(lx, I, g.nx, TX) | shared_dir(ly, J, g.ny, TY) |
+                        shared_dir(lz, K, g.nz, TZ);
+        shw[it] = in & sh;
+        own[it] = in & !sh;
+        gnw[it] = own[it] ? gnode(g, I, J, K) : 0;
+        mw[it] = nmask[gnw[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < NWO; ++it) {
+        const int nb = threadIdx.x + it * NTHR;
+        if (shw[it]) {
             Tout *sl = slots + ((int64_t)t.tile * BOXN + nb) * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) sl[f] = (Tout)S.o[f][nb];
-        } else {
-            int64_t gn = gnode(g, I, J, K);
-            uint8_t m = nmask[gn];
+        } else if (own[it]) {
+            const int64_t gn = gnw[it];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 Tout val = (Tout)S.o[f][nb];
-                if ((m >> f) & 1) val = (OP == OP_RES) ? Tout(0) : (Tout)v[NF * gn + f];
+                if ((mw[it] >> f) & 1) val = (OP == OP_RES) ? Tout(0) : (Tout)v[NF * gn + f];
                 out[NF * gn + f] = val;
             }
         }
@@ -702,7 +752,7 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
     __shared__ T sx[NF][BOXN];
     __shared__ T sl[NF][BOXN];
     const TileIdx t = tile_index(g);
-    stage<T, 0>(g, t, x, lam, nmask, sx, sl, nullptr);
+    stage<T, 0, true>(g, t, x, lam, nmask, sx, sl, nullptr);
     __syncthreads();
     if (!t.valid) return;
     const EC<T> c = make_ec<T>(g);
@@ -801,7 +851,7 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
     __shared__ T sx[NF][BOXN];
     __shared__ T so[25 * BOXN];
     const TileIdx t = tile_index(g);
-    stage<T, 25>(g, t, x, (const double *)nullptr, nmask, sx, nullptr, so);
+    stage<T, 25, false>(g, t, x, (const double *)nullptr, nmask, sx, nullptr, so);
     __syncthreads();
     const EC<T> c = make_ec<T>(g);
     T alpha = 0, Kc = 1, s = 0, tau = 0, tauT = 0;
