@@ -29,9 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Floating-point work of one FP64 element J v evaluation: the modal 2x2x2
-# Gauss pass with compile-time Gauss-point signs, counted from the FP64
-# instructions of that element body (FMA = 2 flops, add/mul = 1).
-FLOPS_PER_ELEM_JV = 4212.0
+# Gauss pass (points in pairs that share their y/z sums), counted from the
+# FP64 instructions of that element body built with compile-time Gauss-point
+# signs (FMA = 2 flops, add/mul = 1).  The kernel runs the same arithmetic with
+# run-time signs: multiplications by +-1 are not counted.
+FLOPS_PER_ELEM_JV = 3855.0
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP64 J v element-pass kernel on the 64^3 workload
