@@ -190,6 +190,19 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
 int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
                       double *D, hipStream_t stream);
 
+/* The assembled Jacobian J(x) of a small problem, dense and row-major:
+ * J_host[i * n_dof + j] = dR_i/dx_j (host FP64[n_dof * n_dof], written in
+ * full), with the identity in place of prescribed rows and columns: the matrix
+ * whose product with a vector fe_jvp evaluates (Sec. "Finite element
+ * formulation", consistent Jacobian).  Built on the device from the element
+ * Jacobians by 135 colour-by-field probing products, then expanded on the
+ * host; this is how the multigrid preconditioner obtains its coarsest-level
+ * matrix.  FE_EINVAL for NULL arguments or n_dof > FE_DENSE_MAX_DOF; synchronises
+ * the stream. */
+#define FE_DENSE_MAX_DOF 20000
+int fe_jacobian_dense(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                      double *J_host, hipStream_t stream);
+
 /* Damping factor of the quadratic line search for scripted residual norms
  * phi(l) = |R(x + l delta)|^2 at l = 0, 1/2, 1 (host-only helper). */
 double fe_line_search_lambda(double phi0, double phi_half, double phi1, double lambda_min);

@@ -5,6 +5,7 @@
 #include <string>
 
 #include "fe_internal.h"
+#include "fe_mg.h"
 
 namespace fe {
 
@@ -311,6 +312,35 @@ int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const
         FE_CHECK_HIP(dalloc(p, &p->slots25, b));
     }
     FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, D, p->slots25, stream));
+    return FE_OK;
+}
+
+int fe_jacobian_dense(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
+                      double *J_host, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !J_host) {
+        set_error("fe_jacobian_dense: NULL argument");
+        return FE_EINVAL;
+    }
+    if (p->ndof > FE_DENSE_MAX_DOF) {
+        set_error("fe_jacobian_dense: more than FE_DENSE_MAX_DOF unknowns");
+        return FE_EINVAL;
+    }
+    double *Je = nullptr, *probe = nullptr;
+    double *h = nullptr;
+    hipError_t e = dalloc(p, &Je, sizeof(double) * 1600 * p->ne);
+    if (e == hipSuccess) e = dalloc(p, &probe, sizeof(double) * 135 * p->ndof);
+    if (e == hipSuccess) e = halloc(p, &h, sizeof(double) * 135 * p->ndof);
+    if (e == hipSuccess)
+        e = launch_probe_products(p->geo, x, gamma, s_elem, p->nmask, Je, probe, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, probe, sizeof(double) * 135 * p->ndof, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) assemble_from_probes(p->grid, h, J_host);
+    dfree(p, Je);
+    dfree(p, probe);
+    hfree(p, h);
+    if (e != hipSuccess) return hip_fail(e, "fe_jacobian_dense");
     return FE_OK;
 }
 

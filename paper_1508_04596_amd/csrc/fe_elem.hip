@@ -477,9 +477,10 @@ __device__ __forceinline__ void elem_residual(const EC<T> &c, const T (*sx)[BOXN
 }
 
 // Directional derivative J_e v_e (exact linearisation, including d tau).
-template <typename T, bool UNR>
-__device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
-                                        const int nb[8], T alpha, T Kc, T s, T out[NF][8])
+// xs(f, a), vs(f, a): the state and the direction at corner a, field f.
+template <typename T, bool UNR, typename XS, typename VS>
+__device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T Kc, T s,
+                                        T out[NF][8])
 {
     T mu[3][8], md[3][8], mp[8], mT[8], mdp[8], mdT[8];
     T U2 = T(0), udu = T(0);
@@ -487,7 +488,7 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], con
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-            T xa = sx[i][nb[a]], va = sv[i][nb[a]];
+            T xa = xs(i, a), va = vs(i, a);
             U2 += xa * xa;
             udu += xa * va;
             mu[i][a] = xa;
@@ -498,10 +499,10 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, const T (*sx)[BOXN], con
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-        mp[a] = sx[3][nb[a]];
-        mT[a] = sx[4][nb[a]];
-        mdp[a] = sv[3][nb[a]];
-        mdT[a] = sv[4][nb[a]];
+        mp[a] = xs(3, a);
+        mT[a] = xs(4, a);
+        mdp[a] = vs(3, a);
+        mdT[a] = vs(4, a);
     }
     to_modal(mp, c);
     to_modal(mT, c);
@@ -755,7 +756,9 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
         if (OP == OP_RES)
             elem_residual<T, UNR>(c, S.x, t.nb, alpha, Kc, s, R);
         else if (OP == OP_JV)
-            elem_jv<T, UNR>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
+            elem_jv<T, UNR>(
+                c, [&](int f, int a) { return S.x[f][t.nb[a]]; },
+                [&](int f, int a) { return S.v[f][t.nb[a]]; }, alpha, Kc, s, R);
         else
             elem_jtv<T, UNR>(c, S.x, S.v, t.nb, alpha, Kc, s, R);
     }
@@ -1115,6 +1118,83 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
 
 }  // namespace
 
+// ---- assembled operator of a small grid (coarsest multigrid level) -----------------
+
+// Element Jacobians: thread (e, c) evaluates J_e e_c, the 40 element rows for the
+// unit direction on local DOF c = 8 f + a (corner a, field f); a prescribed DOF
+// gives a zero direction, as in fe_jvp.  Je is [element][row][column], 40 x 40.
+__global__ __launch_bounds__(64) void k_elem_jac(Geo g, const double *__restrict__ x,
+                                                 const double *__restrict__ gamma,
+                                                 const double *__restrict__ src,
+                                                 const uint8_t *__restrict__ nmask,
+                                                 double *__restrict__ Je)
+{
+    const int64_t ne = n_elem(g);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= ne * 40) return;
+    const int64_t e = tid / 40;
+    const int col = (int)(tid - e * 40);
+    const int i = (int)(e % g.nx), j = (int)((e / g.nx) % g.ny), k = (int)(e / ((int64_t)g.nx * g.ny));
+    int64_t nd[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) nd[a] = gnode(g, i + (a & 1), j + ((a >> 1) & 1), k + (a >> 2));
+    const int fc = col >> 3, ac = col & 7;
+    const double one = ((nmask[nd[ac]] >> fc) & 1) ? 0.0 : 1.0;
+    const EC<double> c = make_ec<double>(g);
+    const double y = gamma[e];
+    const double alpha = alpha_of(g, y), Kc = K_of(g, y), s = src[e];
+    double R[NF][8];
+    elem_jv<double, false>(
+        c, [&](int f, int a) { return x[NF * nd[a] + f]; },
+        [&](int f, int a) { return (8 * f + a == col) ? one : 0.0; }, alpha, Kc, s, R);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Je[(e * 40 + 8 * f + a) * 40 + col] = R[f][a];
+}
+
+// The 135 probing products J p_q of a small grid from its element Jacobians:
+// p_q is the sum of the unit vectors of field f (q = 5 col + f) on the nodes of
+// colour col = (I mod 3) + 3 (J mod 3) + 9 (K mod 3).  Every element has at most
+// one corner of a colour, so row (N, g) of J p_q sums one element entry per
+// element around N, in increasing element order.  Prescribed rows are identity rows.
+__global__ __launch_bounds__(256) void k_probe_from_jac(Geo g, const double *__restrict__ Je,
+                                                        const uint8_t *__restrict__ nmask,
+                                                        double *__restrict__ probe_out)
+{
+    const int64_t nn = n_nodes(g), ndof = NF * nn;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= 135 * ndof) return;
+    const int q = (int)(tid / ndof);
+    const int64_t row = tid - (int64_t)q * ndof;
+    const int64_t N = row / NF;
+    const int gr = (int)(row - N * NF);
+    const int colr = q / NF, f = q - colr * NF;
+    const int I = (int)(N % (g.nx + 1)), J = (int)((N / (g.nx + 1)) % (g.ny + 1)),
+              K = (int)(N / ((int64_t)(g.nx + 1) * (g.ny + 1)));
+    const int colN = (I % 3) + 3 * (J % 3) + 9 * (K % 3);
+    if ((nmask[N] >> gr) & 1) {
+        probe_out[tid] = (colN == colr && f == gr) ? 1.0 : 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int dz = -1; dz <= 0; ++dz)
+        for (int dy = -1; dy <= 0; ++dy)
+            for (int dx = -1; dx <= 0; ++dx) {
+                const int ei = I + dx, ej = J + dy, ek = K + dz;
+                if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx || ej >= g.ny || ek >= g.nz) continue;
+                const int64_t e = ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek);
+                const int aN = (-dx) | ((-dy) << 1) | ((-dz) << 2);
+                for (int b = 0; b < 8; ++b) {
+                    const int mi = ei + (b & 1), mj = ej + ((b >> 1) & 1), mk = ek + (b >> 2);
+                    if ((mi % 3) + 3 * (mj % 3) + 9 * (mk % 3) != colr) continue;
+                    acc += Je[(e * 40 + 8 * gr + aN) * 40 + 8 * f + b];
+                    break;
+                }
+            }
+    probe_out[tid] = acc;
+}
+
 // ---- launchers ----------------------------------------------------------------------
 
 template <typename Tin, typename Tout>
@@ -1183,6 +1263,18 @@ hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, 
     hipLaunchKernelGGL((k_combine<double, double, 25, OP_RES>), dim3((unsigned)((nn + 255) / 256)),
                        dim3(256), 0, st, g, (const double *)slots, nmask, (const double *)nullptr,
                        D);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_products(const Geo &g, const double *x, const double *gamma,
+                                 const double *s, const uint8_t *nmask, double *Je,
+                                 double *probe_out, hipStream_t st)
+{
+    const int64_t ne = n_elem(g), ndof = NF * n_nodes(g);
+    hipLaunchKernelGGL(k_elem_jac, dim3((unsigned)((ne * 40 + 63) / 64)), dim3(64), 0, st, g, x,
+                       gamma, s, nmask, Je);
+    hipLaunchKernelGGL(k_probe_from_jac, dim3((unsigned)((135 * ndof + 255) / 256)), dim3(256), 0,
+                       st, g, (const double *)Je, nmask, probe_out);
     return hipGetLastError();
 }
 

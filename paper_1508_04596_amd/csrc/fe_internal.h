@@ -45,8 +45,11 @@ struct Geo {
 
 Geo make_geo(const fe_grid &g, const fe_phys &ph);
 
-inline int64_t n_nodes(const Geo &g) { return (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1); }
-inline int64_t n_elem(const Geo &g) { return (int64_t)g.nx * g.ny * g.nz; }
+__host__ __device__ inline int64_t n_nodes(const Geo &g)
+{
+    return (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+}
+__host__ __device__ inline int64_t n_elem(const Geo &g) { return (int64_t)g.nx * g.ny * g.nz; }
 inline int64_t n_tiles(const Geo &g) { return (int64_t)g.ntx * g.nty * g.ntz; }
 
 // Which element operator a tile kernel evaluates.
@@ -66,6 +69,12 @@ hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, con
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
 // Raw nodal 5x5 diagonal blocks of J (row-major [n][25]), masked rows/cols set
 // to the identity; slots must hold n_tiles * BOXN * 25 doubles.
+// The 135 colour-by-field probing products J p_q of a small grid, from element
+// Jacobians (Je: n_elem * 1600 doubles of work space; probe_out: 135 * n_dof,
+// product q at offset q * n_dof).
+hipError_t launch_probe_products(const Geo &g, const double *x, const double *gamma,
+                                 const double *s, const uint8_t *nmask, double *Je,
+                                 double *probe_out, hipStream_t st);
 hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, const double *s,
                             const uint8_t *nmask, double *D, double *slots, hipStream_t st);
 

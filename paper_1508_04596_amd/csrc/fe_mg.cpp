@@ -33,7 +33,6 @@ hipError_t mg_prolong_add(int nfx, int nfy, int nfz, const T *xc, const uint8_t 
 template <typename T>
 hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T omega, bool transpose,
                      bool accumulate, hipStream_t st);
-hipError_t mg_probes(int nx, int ny, int nz, double *probe, int64_t ndof, hipStream_t st);
 
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
@@ -95,7 +94,7 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed)
     const int nl = mg_num_levels(g0);
     if (nl < 2) return 0;
     fe_grid g = g0;
-    int64_t b = 0, ndof_c = 0;
+    int64_t b = 0, ndof_c = 0, ne_c = 0;
     for (int l = 0; l < nl; ++l) {
         if (l > 0) {
             g.nx /= 2;
@@ -116,8 +115,9 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed)
         b += r256(8 * ndof);
         if (mixed) b += r256(4 * ndof);
         ndof_c = ndof;
+        ne_c = ne;
     }
-    b += 2 * r256(8 * 135 * ndof_c);
+    b += r256(8 * 1600 * ne_c) + r256(8 * 135 * ndof_c);
     return b;
 }
 
@@ -173,7 +173,7 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
     }
     const MgLevel &C = mg->lev.back();
     mg->nc = C.ndof;
-    if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 135 * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 1600 * C.ne);  // element Jacobians
     if (e == hipSuccess) e = dalloc(p, &mg->probe_out, sizeof(double) * 135 * C.ndof);
     if (e == hipSuccess) e = halloc(p, &mg->hbuf, sizeof(double) * 135 * C.ndof);
     if (e != hipSuccess) {
@@ -185,7 +185,8 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
     mg->A.assign((size_t)C.ndof * C.ndof, 0.0);
     mg->piv.assign(C.ndof, 0);
     mg->Lc.assign((size_t)C.ndof * bw, 0.0);
-    mg->hb.assign(C.ndof, 0.0);
+    mg->Uc.assign((size_t)C.ndof * 2 * bw, 0.0);
+    mg->hb.assign(C.ndof + 2 * bw, 0.0);  // 2 bw entries of scratch, then the vector
     *out = mg;
     return FE_OK;
 }
@@ -240,28 +241,44 @@ static int band_lu(Mg *mg)
         }
         for (int64_t i = iend + 1; i <= k + kl; ++i) mg->Lc[k * kl + (i - k - 1)] = 0.0;
     }
+    // U by columns for the back substitution: Uc[k w + t] = U(k - w + t, k), w = kl + ku
+    const int64_t w = kl + ku;
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t t = 0; t < w; ++t) {
+            const int64_t r = k - w + t;
+            mg->Uc[k * w + t] = r >= 0 ? A[r * n + k] : 0.0;
+        }
     return FE_OK;
 }
 
+// b: the right-hand side on entry, the solution on exit; it is preceded by
+// kl + ku entries of scratch (the back substitution's column updates run into
+// them instead of being clipped).  Both sweeps of the forward solve are
+// contiguous multiply-subtract loops over a column of L or U.
 static void band_solve(const Mg *mg, double *b, bool transpose)
 {
     const int64_t n = mg->nc;
     const int kl = mg->kl, ku = mg->ku;
     const double *A = mg->A.data();
     if (!transpose) {
-        const double *Lc = mg->Lc.data();  // multipliers of column k, contiguous
+        const double *__restrict__ Lc = mg->Lc.data();  // multipliers of column k, contiguous
         for (int64_t k = 0; k < n; ++k) {
             const int64_t p = mg->piv[k];
             if (p != k) std::swap(b[k], b[p]);
             const int64_t cnt = std::min<int64_t>(n - 1, k + kl) - k;
             const double bk = b[k];
-            for (int64_t q = 0; q < cnt; ++q) b[k + 1 + q] -= Lc[k * kl + q] * bk;
+            const double *__restrict__ l = Lc + k * kl;
+            double *__restrict__ y = b + k + 1;
+            for (int64_t q = 0; q < cnt; ++q) y[q] -= l[q] * bk;
         }
+        const int64_t w = kl + ku;
+        for (int64_t t = 1; t <= w; ++t) b[-t] = 0.0;
         for (int64_t k = n - 1; k >= 0; --k) {
-            const int64_t jend = std::min<int64_t>(n - 1, k + kl + ku);
-            double s = b[k];
-            for (int64_t j = k + 1; j <= jend; ++j) s -= A[k * n + j] * b[j];
-            b[k] = s / A[k * n + k];
+            const double xk = b[k] / A[k * n + k];
+            b[k] = xk;
+            const double *__restrict__ u = mg->Uc.data() + k * w;
+            double *__restrict__ y = b + k - w;
+            for (int64_t t = 0; t < w; ++t) y[t] -= u[t] * xk;
         }
     } else {
         // A^T x = b with A = P^T L U: U^T y = b, then L^T and the swaps in reverse
@@ -303,19 +320,25 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
             if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(C.x, C.x32, C.ndof, st)));
         }
     }
-    // coarsest level: 135 probing products J e_(colour,field) in FP64
+    // coarsest level: the 135 probing products J p_(colour,field) in FP64, from
+    // its element Jacobians (two launches)
     MgLevel &C = mg->lev.back();
-    FE_CHECK_HIP(mg_probes(C.grid.nx, C.grid.ny, C.grid.nz, mg->probe, C.ndof, st));
-    for (int q = 0; q < 135; ++q)
-        FE_CHECK_HIP((launch_elem<double, double>(OP_JV, C.geo, C.x, mg->probe + (int64_t)q * C.ndof,
-                                                  C.gamma, C.s, C.nmask,
-                                                  mg->probe_out + (int64_t)q * C.ndof, C.slots, st)));
+    FE_CHECK_HIP(launch_probe_products(C.geo, C.x, C.gamma, C.s, C.nmask, mg->probe,
+                                       mg->probe_out, st));
     FE_CHECK_HIP(hipMemcpyAsync(mg->hbuf, mg->probe_out, sizeof(double) * 135 * C.ndof,
                                 hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipStreamSynchronize(st));
-    const int nx = C.grid.nx, ny = C.grid.ny, nz = C.grid.nz;
-    const int64_t n = C.ndof;
-    std::fill(mg->A.begin(), mg->A.end(), 0.0);
+    assemble_from_probes(C.grid, mg->hbuf, mg->A.data());
+    return band_lu(mg);
+}
+
+// Dense row-major J from the 135 colour-by-field probing products: entry
+// (N g, M f) is row N g of product (colour(M), f), M within one node of N.
+void assemble_from_probes(const fe_grid &grid, const double *probe, double *A)
+{
+    const int nx = grid.nx, ny = grid.ny, nz = grid.nz;
+    const int64_t n = NF * (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    std::fill(A, A + n * n, 0.0);
     for (int K = 0; K <= nz; ++K)
         for (int J = 0; J <= ny; ++J)
             for (int I = 0; I <= nx; ++I) {
@@ -329,11 +352,10 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
                             const int col = (i % 3) + 3 * (j % 3) + 9 * (k % 3);
                             for (int g = 0; g < NF; ++g)
                                 for (int f = 0; f < NF; ++f)
-                                    mg->A[(NF * N + g) * n + NF * M + f] =
-                                        mg->hbuf[(int64_t)(NF * col + f) * n + NF * N + g];
+                                    A[(NF * N + g) * n + NF * M + f] =
+                                        probe[(int64_t)(NF * col + f) * n + NF * N + g];
                         }
             }
-    return band_lu(mg);
 }
 
 template <typename T>
@@ -369,9 +391,10 @@ static int coarse_solve(Mg *mg, MgLevel &C, const T *b, T *x, bool tr, hipStream
     T *h = reinterpret_cast<T *>(mg->hbuf);
     FE_CHECK_HIP(hipMemcpyAsync(h, b, sizeof(T) * n, hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < n; ++i) mg->hb[i] = (double)h[i];
-    band_solve(mg, mg->hb.data(), tr);
-    for (int64_t i = 0; i < n; ++i) h[i] = (T)mg->hb[i];
+    double *hb = mg->hb.data() + (mg->kl + mg->ku);
+    for (int64_t i = 0; i < n; ++i) hb[i] = (double)h[i];
+    band_solve(mg, hb, tr);
+    for (int64_t i = 0; i < n; ++i) h[i] = (T)hb[i];
     FE_CHECK_HIP(hipMemcpyAsync(x, h, sizeof(T) * n, hipMemcpyHostToDevice, st));
     return FE_OK;
 }

@@ -32,9 +32,16 @@ struct Mg {
     int64_t nc = 0;
     int kl = 0, ku = 0;
     std::vector<double> A, hb, Lc;  // dense band LU, work vector, L multipliers by column
+    std::vector<double> Uc;         // U by columns, kl + ku entries above the diagonal each
     std::vector<int> piv;
-    double *probe = nullptr, *probe_out = nullptr, *hbuf = nullptr;
+    double *probe = nullptr;      // element Jacobians of the coarsest level, 1600 per element
+    double *probe_out = nullptr;  // 135 probing products, [q][n_dof]
+    double *hbuf = nullptr;
 };
+
+// Dense row-major n_dof x n_dof J of a grid from its 135 probing products
+// (probe: [q][n_dof] on the host).
+void assemble_from_probes(const fe_grid &grid, const double *probe, double *A);
 
 int mg_num_levels(const fe_grid &g);
 int64_t mg_footprint_bytes(const fe_grid &g, bool mixed);

@@ -139,25 +139,6 @@ __global__ void k_smooth(const T *__restrict__ D, const T *__restrict__ b, const
     }
 }
 
-// Probe vectors for the coarsest-level assembly: column set (colour, field),
-// colour = (I mod 3) + 3 (J mod 3) + 9 (K mod 3); probe[q][dof] for q = 5*colour + field.
-template <typename T>
-__global__ void k_probes(int nx, int ny, int nz, T *__restrict__ probe, int64_t ndof)
-{
-    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 135 * nn) return;
-    const int q = (int)(idx / nn);
-    const int64_t n = idx - (int64_t)q * nn;
-    const int I = (int)(n % (nx + 1));
-    const int64_t r = n / (nx + 1);
-    const int J = (int)(r % (ny + 1)), K = (int)(r / (ny + 1));
-    const int col = (I % 3) + 3 * (J % 3) + 9 * (K % 3);
-    const int fq = q % NF, cq = q / NF;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) probe[(int64_t)q * ndof + NF * n + f] = (cq == col && f == fq) ? T(1) : T(0);
-}
-
 }  // namespace
 
 hipError_t mg_coarsen_elem(int ncx, int ncy, int ncz, const double *f, double *c, hipStream_t st)
@@ -217,13 +198,6 @@ hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T ome
         else
             hipLaunchKernelGGL((k_smooth<T, false, false>), g, bl, 0, st, D, b, t, x, nn, omega);
     }
-    return hipGetLastError();
-}
-
-hipError_t mg_probes(int nx, int ny, int nz, double *probe, int64_t ndof, hipStream_t st)
-{
-    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-    hipLaunchKernelGGL(k_probes<double>, dim3(nblk(135 * nn)), dim3(256), 0, st, nx, ny, nz, probe, ndof);
     return hipGetLastError();
 }
 

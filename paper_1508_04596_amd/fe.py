@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         L.fe_residual.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fe_jvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.fe_adjoint_jtvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fe_jacobian_dense.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fe_kernel_timer.argtypes = [vp, i32]
         L.fe_kernel_timer_read.argtypes = [vp, P(dbl), P(ctypes.c_int64)]
         L.fe_dR_dgamma.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -242,6 +243,17 @@ def fe_jvp(prob: Problem, x, gamma, s, v, out=None, stream=None):
                         _ptr(s, torch.float64), _ptr(v, x.dtype), _ptr(out, x.dtype),
                         _stream(stream)), "fe_jvp")
     return out
+
+
+def fe_jacobian_dense(prob: Problem, x, gamma, s, stream=None):
+    """Assembled J(x) of a small problem as a dense row-major numpy array."""
+    import numpy as np
+    n = int(lib().fe_problem_ndof(prob.handle))
+    J = np.empty((n, n), dtype=np.float64)
+    _check(lib().fe_jacobian_dense(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
+                                   _ptr(s, torch.float64), J.ctypes.data_as(ctypes.c_void_p),
+                                   _stream(stream)), "fe_jacobian_dense")
+    return J
 
 
 def fe_kernel_timer(prob: Problem, enable: bool = True):

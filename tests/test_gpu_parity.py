@@ -187,3 +187,22 @@ def test_kernel_timer_changes_no_result(fe):
     assert all(torch.equal(o, ref) for o in outs)
     assert rel_norm(host(out32), host(ref)) < 1e-5
     prob.close()
+
+
+@pytest.mark.parametrize("dims,mask", [((4, 4, 4), "solve"), ((3, 4, 5), "walls"), ((5, 5, 10), "solve")])
+def test_dense_jacobian_parity(fe, dims, mask):
+    """Assembled J from element Jacobians and colour probing (the multigrid's
+    coarsest-level matrix) against the oracle's assembled sparse J, every entry;
+    ragged sizes that are not multiples of the 3-colouring period."""
+    p = inputs.scaled_config(*dims, 1e5, seed=41)
+    prob = fe.Problem.from_inputs(p, mask=mask)
+    m = p.mask_solve if mask == "solve" else p.mask_walls
+    x = inputs.random_state(p, 43, mask=m)
+    J = fe.fe_jacobian_dense(prob, dev(x), dev(p.gamma), dev(p.s))
+    ref = osolve.assemble(p, x, mask=mask).toarray()
+    assert_parity(J.reshape(-1), ref.reshape(-1), what=f"dense J {dims}")
+    # and J applied to a vector equals the matrix-free product
+    v = inputs.random_direction(p, 3, mask=m)
+    jv = host(fe.fe_jvp(prob, dev(x), dev(p.gamma), dev(p.s), dev(v)))
+    assert rel_norm(J @ v, jv) <= 1e-12
+    prob.close()
