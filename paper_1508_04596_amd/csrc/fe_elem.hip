@@ -876,6 +876,64 @@ __global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__
     }
 }
 
+// The shared-node pass fused with one damped block-Jacobi sweep of the
+// multigrid smoother: t = J x is completed per node exactly as k_combine does
+// (rows of a node inside one tile were written to t by the element pass), and
+// x += omega D^{-1} (b - t) (D^{-T} for the transposed operator) is applied at
+// once, so t is never written for shared nodes nor read back.  Each thread
+// reads and writes only its own node of x.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restrict__ slots,
+                                                        const uint8_t *__restrict__ nmask,
+                                                        const T *__restrict__ t,
+                                                        const T *__restrict__ D,
+                                                        const T *__restrict__ b, T *x, T omega)
+{
+    const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    const int64_t gn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gn >= nn) return;
+    const int I = (int)(gn % (g.nx + 1));
+    const int64_t r = gn / (g.nx + 1);
+    const int J = (int)(r % (g.ny + 1));
+    const int K = (int)(r / (g.ny + 1));
+    int tx[2], lx[2], ty[2], ly[2], tz[2], lz[2];
+    const int cx = tiles_of(I, g.nx, TX, g.ntx, tx, lx);
+    const int cy = tiles_of(J, g.ny, TY, g.nty, ty, ly);
+    const int cz = tiles_of(K, g.nz, TZ, g.ntz, tz, lz);
+    T tv[NF];
+    if (cx == 1 && cy == 1 && cz == 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tv[f] = t[NF * gn + f];
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tv[f] = T(0);
+        for (int a = 0; a < cz; ++a)
+            for (int bb = 0; bb < cy; ++bb)
+                for (int cc = 0; cc < cx; ++cc) {
+                    int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[bb] + (int64_t)g.nty * tz[a]);
+                    int nb = lx[cc] + BX * (ly[bb] + BY * lz[a]);
+                    const T *sl = slots + (tile * BOXN + nb) * NF;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) tv[f] += sl[f];
+                }
+        const uint8_t m = nmask[gn];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if ((m >> f) & 1) tv[f] = x[NF * gn + f];
+    }
+    T rr[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rr[f] = b[NF * gn + f] - tv[f];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < NF; ++c)
+            acc += (OP == OP_JTV ? D[gn * 25 + c * NF + a] : D[gn * 25 + a * NF + c]) * rr[c];
+        x[NF * gn + a] += omega * acc;
+    }
+}
+
 // ---- design derivative: one output per element, no scatter ---------------------
 
 __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restrict__ x,
@@ -1265,6 +1323,36 @@ hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, 
                        D);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_elem_smooth(bool tr, const Geo &g, const T *xs, T *x, const double *gamma,
+                              const double *s, const uint8_t *nmask, T *t, T *slots, const T *D,
+                              const T *b, T omega, hipStream_t st)
+{
+    const dim3 grid((unsigned)n_tiles(g)), block(NTHR);
+    const int64_t nn = n_nodes(g);
+    const dim3 cgrid((unsigned)((nn + 255) / 256)), cblock(256);
+    if (tr) {
+        hipLaunchKernelGGL((k_elem<T, T, OP_JTV>), grid, block, 0, st, g, xs, (const T *)x, gamma,
+                           s, nmask, t, slots);
+        hipLaunchKernelGGL((k_combine_smooth<T, OP_JTV>), cgrid, cblock, 0, st, g,
+                           (const T *)slots, nmask, (const T *)t, D, b, x, omega);
+    } else {
+        hipLaunchKernelGGL((k_elem<T, T, OP_JV>), grid, block, 0, st, g, xs, (const T *)x, gamma, s,
+                           nmask, t, slots);
+        hipLaunchKernelGGL((k_combine_smooth<T, OP_JV>), cgrid, cblock, 0, st, g,
+                           (const T *)slots, nmask, (const T *)t, D, b, x, omega);
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_elem_smooth<double>(bool, const Geo &, const double *, double *,
+                                               const double *, const double *, const uint8_t *,
+                                               double *, double *, const double *, const double *,
+                                               double, hipStream_t);
+template hipError_t launch_elem_smooth<float>(bool, const Geo &, const float *, float *,
+                                              const double *, const double *, const uint8_t *,
+                                              float *, float *, const float *, const float *, float,
+                                              hipStream_t);
 
 hipError_t launch_probe_products(const Geo &g, const double *x, const double *gamma,
                                  const double *s, const uint8_t *nmask, double *Je,

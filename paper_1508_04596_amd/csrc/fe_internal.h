@@ -69,6 +69,12 @@ hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, con
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
 // Raw nodal 5x5 diagonal blocks of J (row-major [n][25]), masked rows/cols set
 // to the identity; slots must hold n_tiles * BOXN * 25 doubles.
+// One smoother sweep with the operator fused: x += omega D^{-1} (b - J x) (J^T
+// and D^{-T} when tr), J at state xs; t (node vector) and slots are work space.
+template <typename T>
+hipError_t launch_elem_smooth(bool tr, const Geo &g, const T *xs, T *x, const double *gamma,
+                              const double *s, const uint8_t *nmask, T *t, T *slots, const T *D,
+                              const T *b, T omega, hipStream_t st);
 // The 135 colour-by-field probing products J p_q of a small grid, from element
 // Jacobians (Je: n_elem * 1600 doubles of work space; probe_out: 135 * n_dof,
 // product q at offset q * n_dof).

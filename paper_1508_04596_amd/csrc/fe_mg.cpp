@@ -409,10 +409,9 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
     const T *D = blocksT<T>(L);
     T *t = vecT<T>(L, 2);
     FE_CHECK_HIP(mg_smooth<T>(D, b, nullptr, x, L.nn, om, tr, false, st));
-    for (int it = 1; it < mg->nu1; ++it) {
-        FE_CHECK_HIP(op<T>(L, x, t, tr, st));
-        FE_CHECK_HIP(mg_smooth<T>(D, b, t, x, L.nn, om, tr, true, st));
-    }
+    for (int it = 1; it < mg->nu1; ++it)
+        FE_CHECK_HIP(launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t,
+                                           (T *)L.slots, D, b, om, st));
     MgLevel &C = mg->lev[l + 1];
     FE_CHECK_HIP(op<T>(L, x, t, tr, st));
     T *bc = vecT<T>(C, 0), *xc = vecT<T>(C, 1);
@@ -420,10 +419,9 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
     int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st);
     if (rc) return rc;
     FE_CHECK_HIP(mg_prolong_add<T>(L.grid.nx, L.grid.ny, L.grid.nz, xc, L.nmask, x, st));
-    for (int it = 0; it < mg->nu2; ++it) {
-        FE_CHECK_HIP(op<T>(L, x, t, tr, st));
-        FE_CHECK_HIP(mg_smooth<T>(D, b, t, x, L.nn, om, tr, true, st));
-    }
+    for (int it = 0; it < mg->nu2; ++it)
+        FE_CHECK_HIP(launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t,
+                                           (T *)L.slots, D, b, om, st));
     return FE_OK;
 }
 
