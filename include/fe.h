@@ -130,7 +130,7 @@ typedef struct {
     double rtol_newton;     /* stop when |R|_2 <= rtol_newton |R(x0)|_2 (default 1e-8) */
     double rtol_lin;        /* FGMRES relative tolerance per Newton step (default 1e-5) */
     int max_newton;         /* default 50 */
-    int restart;            /* FGMRES restart length m, 1..64 (default 30) */
+    int restart;            /* FGMRES restart length m, 1..64 (default 60) */
     int max_lin;            /* Krylov iterations per linear solve (default 3000) */
     int n_refine;           /* mixed mode: iterative-refinement sweeps (default 3) */
     fe_prec krylov_op_prec; /* FE_FP64, or FE_FP32 for FP32 J v and preconditioner */
@@ -140,6 +140,11 @@ typedef struct {
     int mg_nu;              /* multigrid: smoothing sweeps before and after (default 2) */
     double mg_omega;        /* multigrid: block-Jacobi damping (default 0.6) */
     double atol_newton;     /* also stop when |R|_2 <= atol_newton (default 0; for warm starts) */
+    int ramp_steps;         /* recovery when Newton fails from the given vector (Sec. "Solving the
+                               non-linear system"): restart from it and solve ramp_steps problems
+                               with the heat source scaled by k/ramp_steps, k = 1..ramp_steps, each
+                               warm-started from the previous one; the last one is held to the
+                               original tolerance.  0 (default) = off */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free
@@ -159,6 +164,7 @@ typedef struct {
     double res_hist[65];                    /* |R| after each Newton step, [0] = |R(x0)| */
     int precond;                            /* preconditioner used (FE_PC_BJACOBI / FE_PC_MULTIGRID) */
     int mg_levels;                          /* multigrid levels (0 without multigrid) */
+    int ramp_stages;                        /* heat-source ramping stages run (0: none needed) */
 } fe_solve_report;
 
 /* Fill opts with the defaults listed above. */

@@ -8,6 +8,7 @@
 // norm are FP64.  One Arnoldi step runs entirely on the device; the host reads
 // back one Hessenberg column (j+2 numbers) per step to update the Givens
 // rotations and test convergence.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -296,7 +297,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->rtol_newton = 1e-8;
     o->rtol_lin = 1e-5;
     o->max_newton = 50;
-    o->restart = 30;
+    o->restart = 60;
     o->max_lin = 3000;
     o->n_refine = 3;
     o->krylov_op_prec = FE_FP64;
@@ -306,6 +307,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->mg_nu = 2;
     o->mg_omega = 0.6;
     o->atol_newton = 0.0;
+    o->ramp_steps = 0;
 }
 
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
@@ -365,22 +367,11 @@ static void fill_report(fe_solve_report *rep, const fe_solve_report &r)
     if (rep) *rep = r;
 }
 
-int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, double *x,
-                 const fe_solve_opts *opts_in, fe_solve_report *report, hipStream_t st)
+// One damped Newton solve from x (the body of newton_solve without recovery).
+static int newton_core(fe_problem *p, const double *gamma, const double *s_elem, double *x,
+                       const fe_solve_opts &opts, fe_solve_report *report, hipStream_t st)
 {
     auto t0 = std::chrono::steady_clock::now();
-    if (!p || !gamma || !s_elem || !x) {
-        set_error("newton_solve: NULL argument");
-        return FE_EINVAL;
-    }
-    fe_solve_opts opts;
-    fe_solve_opts_default(&opts);
-    if (opts_in) opts = *opts_in;
-    if (opts.restart < 1 || opts.restart > 64 || opts.max_newton < 0 || opts.max_lin < 1 ||
-        !(opts.rtol_newton >= 0) || !(opts.rtol_lin > 0)) {
-        set_error("newton_solve: invalid options (restart 1..64, max_lin >= 1, rtol_lin > 0)");
-        return FE_EINVAL;
-    }
     const bool mixed = opts.krylov_op_prec == FE_FP32;
     int rc = ensure_ws(p, opts.restart, mixed);
     if (rc) return rc;
@@ -544,6 +535,91 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     fill_report(report, rep);
     if (status != FE_OK) set_error("newton_solve: not converged within max_newton");
     return status;
+}
+
+int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, double *x,
+                 const fe_solve_opts *opts_in, fe_solve_report *report, hipStream_t st)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !gamma || !s_elem || !x) {
+        set_error("newton_solve: NULL argument");
+        return FE_EINVAL;
+    }
+    fe_solve_opts opts;
+    fe_solve_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if (opts.restart < 1 || opts.restart > 64 || opts.max_newton < 0 || opts.max_lin < 1 ||
+        !(opts.rtol_newton >= 0) || !(opts.rtol_lin > 0) || opts.ramp_steps < 0 ||
+        opts.ramp_steps > 64) {
+        set_error("newton_solve: invalid options (restart 1..64, max_lin >= 1, rtol_lin > 0, "
+                  "ramp_steps 0..64)");
+        return FE_EINVAL;
+    }
+    if (opts.ramp_steps == 0) return newton_core(p, gamma, s_elem, x, opts, report, st);
+
+    // keep the initial vector: the ramp restarts from it
+    const int64_t n = p->ndof;
+    double *x0 = nullptr, *sk = nullptr;
+    hipError_t e = dalloc(p, &x0, sizeof(double) * n);
+    if (e == hipSuccess) e = dalloc(p, &sk, sizeof(double) * p->ne);
+    if (e == hipSuccess) e = hipMemcpyAsync(x0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        dfree(p, x0);
+        dfree(p, sk);
+        return hip_fail(e, "newton_solve (ramp buffers)");
+    }
+    fe_solve_report r1;
+    std::memset(&r1, 0, sizeof(r1));
+    int rc = newton_core(p, gamma, s_elem, x, opts, &r1, st);
+    if ((rc != FE_NOT_CONVERGED && rc != FE_ENAN) || !std::isfinite(r1.res0)) {
+        dfree(p, x0);
+        dfree(p, sk);
+        r1.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        fill_report(report, r1);
+        return rc;
+    }
+    // ramping: stage k solves with s * k / K from the previous stage's result;
+    // the last stage is held to the original target rtol_newton * |R(x0)|
+    fe_solve_report tot = r1;
+    const double target = opts.rtol_newton * r1.res0;
+    e = hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    const int K = opts.ramp_steps;
+    for (int k = 1; k <= K && e == hipSuccess; ++k) {
+        const double *sk_use = s_elem;
+        if (k < K) {
+            e = launch_axpby(p->ne, (double)k / K, s_elem, 0.0, sk, st);
+            if (e != hipSuccess) break;
+            sk_use = sk;
+        }
+        fe_solve_opts ok = opts;
+        if (k == K) ok.atol_newton = std::max(opts.atol_newton, target);
+        fe_solve_report rk;
+        std::memset(&rk, 0, sizeof(rk));
+        rc = newton_core(p, gamma, sk_use, x, ok, &rk, st);
+        for (int i = 0; i < rk.newton_its && tot.newton_its + i < 64; ++i)
+            tot.lin_its[tot.newton_its + i] = rk.lin_its[i];
+        for (int i = 1; i <= rk.newton_its && tot.newton_its + i <= 64; ++i)
+            tot.res_hist[tot.newton_its + i] = rk.res_hist[i];
+        tot.newton_its += rk.newton_its;
+        tot.lin_its_total += rk.lin_its_total;
+        tot.t_jv_s += rk.t_jv_s;
+        tot.t_prec_s += rk.t_prec_s;
+        tot.t_orth_s += rk.t_orth_s;
+        tot.t_res_s += rk.t_res_s;
+        tot.t_setup_s += rk.t_setup_s;
+        tot.res_final = rk.res_final;
+        tot.lambda_last = rk.lambda_last;
+        tot.ramp_stages = k;
+        if (rc != FE_OK) break;
+    }
+    dfree(p, x0);
+    dfree(p, sk);
+    if (e != hipSuccess) return hip_fail(e, "newton_solve (ramp)");
+    tot.status = rc;
+    tot.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_report(report, tot);
+    if (rc == FE_NOT_CONVERGED) set_error("newton_solve: not converged after heat-source ramping");
+    return rc;
 }
 
 int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const double *s_elem,

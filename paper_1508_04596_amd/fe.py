@@ -47,7 +47,8 @@ class FeSolveOpts(ctypes.Structure):
                 ("max_lin", ctypes.c_int), ("n_refine", ctypes.c_int),
                 ("krylov_op_prec", ctypes.c_int), ("ls_lambda_min", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
-                ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double)]
+                ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double),
+                ("ramp_steps", ctypes.c_int)]
 
 
 class FeSolveReport(ctypes.Structure):
@@ -58,7 +59,8 @@ class FeSolveReport(ctypes.Structure):
                 ("t_prec_s", ctypes.c_double), ("t_orth_s", ctypes.c_double),
                 ("t_res_s", ctypes.c_double), ("t_setup_s", ctypes.c_double),
                 ("lin_its", ctypes.c_int * 64), ("res_hist", ctypes.c_double * 65),
-                ("precond", ctypes.c_int), ("mg_levels", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("mg_levels", ctypes.c_int),
+                ("ramp_stages", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         n = min(self.newton_its, 64)
@@ -69,7 +71,7 @@ class FeSolveReport(ctypes.Structure):
                 "t_res_s": self.t_res_s, "t_setup_s": self.t_setup_s,
                 "lin_its": list(self.lin_its[:n]), "res_hist": list(self.res_hist[:n + 1]),
                 "precond": {1: "bjacobi", 2: "multigrid"}.get(self.precond, "none"),
-                "mg_levels": self.mg_levels}
+                "mg_levels": self.mg_levels, "ramp_stages": self.ramp_stages}
 
 
 class FeError(RuntimeError):

@@ -56,6 +56,7 @@ class Problem:
     s: np.ndarray  # [n_el] float64
     mask_walls: np.ndarray  # [n_dof] uint8, walls only
     mask_solve: np.ndarray  # [n_dof] uint8, walls + pinned pressure at node 0
+    design: Optional[np.ndarray] = None  # [n_el] bool, design domain (None: every element)
 
     @property
     def n_el(self) -> int:
@@ -258,3 +259,87 @@ def tiny_problem(nx, ny, nz, Gr=1.0e3, seed=7, h=None, **kw) -> Problem:
     if h is None:
         h = 1.0 / max(nx, ny, nz)
     return make_problem(f"tiny {nx}x{ny}x{nz}", nx, ny, nz, h, Gr, g, **kw)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own test problem (Sec. "Numerical examples", heat sink in a
+# closed cubic cavity): unit cube, heat-generating solid block at the middle of
+# the bottom, design box of edge 0.75 resting on it, T = 0 and no-slip on the
+# vertical walls and the top, insulated no-slip bottom, volume fraction 5 %.
+# Vertical axis z (gravity -z).  The quarter domain [0, 1/2]^2 x [0, 1] uses
+# the planes x = 1/2 and y = 1/2 as symmetry planes (normal velocity 0, every
+# other field free there).  Figure 1 with the exact placement is not part of
+# the text, so the block and the design box are centred in x and y, the block
+# (0.1 x 0.1 in plan, 0.05 high) sits on the bottom and the design box starts
+# on the block's top face.
+
+CAVITY_SOURCE = ((0.45, 0.55), (0.45, 0.55), (0.0, 0.05))
+CAVITY_DESIGN = ((0.125, 0.875), (0.125, 0.875), (0.05, 0.80))
+
+
+def _centre_in(n_el: int, lo: float, hi: float, n_per_unit: int) -> np.ndarray:
+    """Elements whose centre (i + 1/2) / n_per_unit lies in [lo, hi] (bounds
+    given in 1/1000 so that the test is exact in integers)."""
+    i = np.arange(n_el)
+    c = 2000 * i + 1000  # 2000 * (i + 1/2)
+    return (c >= round(2000 * lo * 1000) * n_per_unit // 1000) & \
+           (c <= round(2000 * hi * 1000) * n_per_unit // 1000)
+
+
+def cavity_mask(nx: int, ny: int, nz: int, quarter: bool, pin_pressure: bool) -> np.ndarray:
+    """Dirichlet DOFs of the cavity: no-slip on x = 0, y = 0, z = 0, z = top
+    (and x = 1, y = 1 for the full cube); T = 0 on those walls except the
+    bottom; for the quarter domain the normal velocity on x = nx (u) and
+    y = ny (v)."""
+    I = np.arange(nx + 1)[None, None, :]
+    J = np.arange(ny + 1)[None, :, None]
+    K = np.arange(nz + 1)[:, None, None]
+    full = (nz + 1, ny + 1, nx + 1)
+    side_lo = (I == 0) | (J == 0)
+    side_hi = np.zeros(full, dtype=bool) if quarter else ((I == nx) | (J == ny))
+    cold = np.broadcast_to(side_lo | side_hi | (K == nz), full)
+    wall = cold | np.broadcast_to(K == 0, full)
+    m = np.zeros(full + (NF,), dtype=np.uint8)
+    for f in (0, 1, 2):
+        m[..., f] = wall
+    m[..., 4] = cold
+    if quarter:
+        m[..., 0] |= np.broadcast_to(I == nx, full)
+        m[..., 1] |= np.broadcast_to(J == ny, full)
+    m = m.reshape(-1)
+    if pin_pressure:
+        m[3] = 1
+    return m
+
+
+def cavity_problem(N: int, Gr: float, *, quarter: bool = True, vf: float = 0.05, s0: float = 1.0e4,
+                   Ck: float = 1.0e-2, Pr: float = 1.0, qf: float = 0.881, q_alpha: float = 8.0,
+                   alpha_max: float = 1.0e5, design: Optional[np.ndarray] = None) -> Problem:
+    """The cavity at N elements per unit length (N even, N >= 20 so that the
+    0.05-high block spans an element).  ``design``: gamma on the design box
+    (default: the uniform initial design 1 - vf); gamma = 1 (fluid) elsewhere
+    and 0 on the block.  Default parameters: Ck, s0, Pr of the paper's examples
+    and the first continuation step (qf, q_alpha, alpha_max)."""
+    if N % 2 or N < 20:
+        raise ValueError("cavity_problem: N must be even and >= 20")
+    nx = ny = N // 2 if quarter else N
+    nz = N
+    h = 1.0 / N
+    ax = lambda n, b: _centre_in(n, b[0], b[1], N)
+    def region(box):
+        return (ax(nz, box[2])[:, None, None] & ax(ny, box[1])[None, :, None]
+                & ax(nx, box[0])[None, None, :]).reshape(-1)
+    omega = region(CAVITY_SOURCE)
+    dom = region(CAVITY_DESIGN) & ~omega
+    gamma = np.ones(nx * ny * nz)
+    if design is None:
+        gamma[dom] = 1.0 - vf
+    else:
+        gamma[dom] = np.asarray(design, dtype=np.float64)
+    gamma[omega] = 0.0
+    s = np.where(omega, s0, 0.0).astype(np.float64)
+    name = f"cavity {'quarter' if quarter else 'full'} N={N} Gr={Gr:g}"
+    return Problem(name=name, nx=nx, ny=ny, nz=nz, h=h, Pr=Pr, Gr=Gr, Ck=Ck, qf=qf,
+                   alpha_max=alpha_max, q_alpha=q_alpha, eg=(0.0, 0.0, -1.0), gamma=gamma, s=s,
+                   mask_walls=cavity_mask(nx, ny, nz, quarter, False),
+                   mask_solve=cavity_mask(nx, ny, nz, quarter, True), design=dom)

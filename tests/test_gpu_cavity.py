@@ -1,0 +1,81 @@
+"""The paper's cavity test problem on the GPU: quarter domain with symmetry
+planes, heat-source block s0 = 1e4, C_k = 1e-2, first continuation step; the
+heat-source ramping recovery of the Newton solver; the symmetry-plane reading
+checked against the mirrored full cavity, all through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solve as osolve
+from paper_1508_04596_amd import inputs
+from tests.test_cavity import _mirror_pair
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def solve(fe, p, **kw):
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    g = torch.from_numpy(p.gamma).cuda()
+    s = torch.from_numpy(p.s).cuda()
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    rep = fe.newton_solve(prob, g, s, x, fe.solve_opts(**kw), allow_not_converged=True)
+    f = fe.fe_compliance(prob, x, s) if rep["status"] == fe.FE_OK else None
+    prob.close()
+    return x.cpu().numpy(), rep, f
+
+
+def oracle_rel_residual(p, x):
+    r = np.linalg.norm(oracle.residual(p, x, mask="solve"))
+    r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+    return r / r0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cavity_solve_against_oracle(fe, prec):
+    p = inputs.cavity_problem(32, 1e4)
+    x, rep, f = solve(fe, p, rtol_newton=1e-8, krylov_op_prec=prec)
+    print(f"[cavity] N=32 Gr=1e4 {prec}: newton {rep['newton_its']} lin {rep['lin_its']} "
+          f"precond {rep['precond']}")
+    assert rep["status"] == fe.FE_OK and rep["ramp_stages"] == 0
+    assert oracle_rel_residual(p, x) <= 1e-8 * 1.0001
+    # objective: integral of s T over the block
+    assert abs(f - osolve.compliance(p, x)) <= 1e-12 * abs(f)
+    # insulated bottom: T is free there and positive under the hot block
+    T = x.reshape(p.nz + 1, p.ny + 1, p.nx + 1, 5)[..., 4]
+    assert T[0, -1, -1] > 0.5 * T.max()
+
+
+def test_heat_source_ramping_recovers(fe):
+    """s0 = 1e5 at Gr = 1e5: Newton from zero fails; ramping the heat source in
+    four stages, each warm-started from the last, reaches the original
+    tolerance of the original problem."""
+    p = inputs.cavity_problem(32, 1e5, s0=1e5)
+    kw = dict(rtol_newton=1e-8, max_newton=20, max_lin=600)
+    _, rep0, _ = solve(fe, p, ramp_steps=0, **kw)
+    assert rep0["status"] == fe.FE_NOT_CONVERGED
+    x, rep, _ = solve(fe, p, ramp_steps=4, **kw)
+    print(f"[cavity] ramping: status {rep['status']} stages {rep['ramp_stages']} "
+          f"newton {rep['newton_its']} rel {rep['res_final'] / rep['res0']:.2e}")
+    assert rep["status"] == fe.FE_OK and rep["ramp_stages"] == 4
+    assert oracle_rel_residual(p, x) <= 1e-8 * 1.0001
+
+
+def test_symmetry_planes_match_mirrored_full_cavity_on_gpu(fe):
+    full, quarter = _mirror_pair()
+    xf, rf, _ = solve(fe, full, rtol_newton=1e-12)
+    xq, rq, _ = solve(fe, quarter, rtol_newton=1e-12)
+    assert rf["status"] == fe.FE_OK and rq["status"] == fe.FE_OK
+    Xf = xf.reshape(full.nz + 1, full.ny + 1, full.nx + 1, 5)
+    restricted = Xf[:, :quarter.ny + 1, :quarter.nx + 1, :].reshape(-1)
+    assert np.abs(restricted - xq).max() <= 1e-8 * np.abs(xq).max()
