@@ -231,6 +231,14 @@ int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
 /* gamma_host, s_host: host FP64[n_el]; copied.  Returns at once with a ticket. */
 int serve_submit(fe_server *s, const fe_grid *grid, const fe_phys *phys, const double *gamma_host,
                  const double *s_host, const fe_solve_opts *opts, uint64_t *ticket);
+/* As serve_submit, with an initial vector for Newton: x0_host, host
+ * FP64[n_dof] (copied; NULL: zero), typically the solution of the previous
+ * design of an optimisation (Sec. "Solving the non-linear system": the
+ * previous design iteration's state is the initial vector).  Its prescribed
+ * entries must hold the Dirichlet values (0 on the walls). */
+int serve_submit_x0(fe_server *s, const fe_grid *grid, const fe_phys *phys,
+                    const double *gamma_host, const double *s_host, const double *x0_host,
+                    const fe_solve_opts *opts, uint64_t *ticket);
 /* FE_PENDING while queued or running; otherwise the request's final status
  * (FE_OK, FE_NOT_CONVERGED or an error) with x_host_out (host FP64[n_dof], may
  * be NULL) and report filled.  A finished ticket can be polled again. */

@@ -117,7 +117,7 @@ struct Request {
     fe_grid grid;
     fe_phys phys;
     fe_solve_opts opts;
-    std::vector<double> gamma, s, x;
+    std::vector<double> gamma, s, x, x0;  // x0: initial vector (empty: zero)
     size_t footprint = 0;
     ReqState state = Q_WAITING;
     int status = FE_PENDING;
@@ -172,7 +172,12 @@ int run_request(fe_server *S, Request *r, hipStream_t st)
     if (e == hipSuccess) e = dalloc(p, &x, sizeof(double) * ndof);
     if (e == hipSuccess) e = hipMemcpyAsync(g, r->gamma.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(s, r->s.data(), sizeof(double) * ne, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(x, 0, sizeof(double) * ndof, st);
+    if (e == hipSuccess) {
+        if (r->x0.empty())
+            e = hipMemsetAsync(x, 0, sizeof(double) * ndof, st);
+        else
+            e = hipMemcpyAsync(x, r->x0.data(), sizeof(double) * ndof, hipMemcpyHostToDevice, st);
+    }
     if (e != hipSuccess) {
         rc = hip_fail(e, "serve: request set-up");
     } else {
@@ -258,8 +263,15 @@ int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out)
 int serve_submit(fe_server *S, const fe_grid *grid, const fe_phys *phys, const double *gamma_host,
                  const double *s_host, const fe_solve_opts *opts, uint64_t *ticket)
 {
+    return serve_submit_x0(S, grid, phys, gamma_host, s_host, nullptr, opts, ticket);
+}
+
+int serve_submit_x0(fe_server *S, const fe_grid *grid, const fe_phys *phys,
+                    const double *gamma_host, const double *s_host, const double *x0_host,
+                    const fe_solve_opts *opts, uint64_t *ticket)
+{
     if (!S || !grid || !phys || !gamma_host || !s_host || !ticket) {
-        set_error("serve_submit: NULL argument");
+        set_error("serve_submit_x0: NULL argument");
         return FE_EINVAL;
     }
     if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->h > 0)) {
@@ -275,6 +287,10 @@ int serve_submit(fe_server *S, const fe_grid *grid, const fe_phys *phys, const d
     const int64_t ne = (int64_t)grid->nx * grid->ny * grid->nz;
     r->gamma.assign(gamma_host, gamma_host + ne);
     r->s.assign(s_host, s_host + ne);
+    if (x0_host) {
+        const int64_t ndof = (int64_t)NF * (grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
+        r->x0.assign(x0_host, x0_host + ndof);
+    }
     std::memset(&r->rep, 0, sizeof(r->rep));
     r->footprint = request_footprint(r->grid, r->opts);
     std::lock_guard<std::mutex> lk(S->mu);

@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         L.serve_create.argtypes = [ctypes.c_size_t, i32, P(vp)]
         L.serve_submit.argtypes = [vp, P(FeGrid), P(FePhys), vp, vp, P(FeSolveOpts),
                                    P(ctypes.c_uint64)]
+        L.serve_submit_x0.argtypes = [vp, P(FeGrid), P(FePhys), vp, vp, vp, P(FeSolveOpts),
+                                      P(ctypes.c_uint64)]
         L.serve_poll.argtypes = [vp, ctypes.c_uint64, vp, P(FeSolveReport)]
         L.serve_times.argtypes = [vp, ctypes.c_uint64, P(dbl), P(dbl), P(dbl)]
         L.serve_destroy.argtypes = [vp]
@@ -356,16 +358,28 @@ class Server:
         self.n_dof = {}
 
     def submit(self, nx, ny, nz, h, phys: FePhys, gamma, s, opts: Optional[FeSolveOpts] = None,
-               allow_enomem=False) -> int:
+               allow_enomem=False, x0=None) -> int:
+        """Queue a state solve; ``x0`` (host, n_dof) warm-starts Newton (default zero)."""
         import numpy as np
         g = np.ascontiguousarray(gamma, dtype=np.float64)
         ss = np.ascontiguousarray(s, dtype=np.float64)
         assert g.size == nx * ny * nz and ss.size == nx * ny * nz
         t = ctypes.c_uint64()
         grid = FeGrid(nx, ny, nz, h)
-        rc = lib().serve_submit(self.handle, ctypes.byref(grid), ctypes.byref(phys),
-                                g.ctypes.data_as(ctypes.c_void_p), ss.ctypes.data_as(ctypes.c_void_p),
-                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(t))
+        if x0 is None:
+            rc = lib().serve_submit(self.handle, ctypes.byref(grid), ctypes.byref(phys),
+                                    g.ctypes.data_as(ctypes.c_void_p),
+                                    ss.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(opts) if opts is not None else None, ctypes.byref(t))
+        else:
+            xx = np.ascontiguousarray(x0, dtype=np.float64)
+            assert xx.size == 5 * (nx + 1) * (ny + 1) * (nz + 1)
+            rc = lib().serve_submit_x0(self.handle, ctypes.byref(grid), ctypes.byref(phys),
+                                       g.ctypes.data_as(ctypes.c_void_p),
+                                       ss.ctypes.data_as(ctypes.c_void_p),
+                                       xx.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(t))
         _check(rc, "serve_submit", ok=(FE_OK, FE_ENOMEM) if allow_enomem else (FE_OK,))
         self.n_dof[t.value] = 5 * (nx + 1) * (ny + 1) * (nz + 1)
         return t.value

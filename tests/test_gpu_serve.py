@@ -114,3 +114,29 @@ def test_no_read_before_write_with_poisoned_memory(fe, monkeypatch, prec, pc):
         err = srv.error(t)
     assert clean[0] == fe.FE_OK and poisoned[0] == fe.FE_OK, err
     assert np.array_equal(clean[1], poisoned[1])
+
+
+def test_warm_start_from_previous_design(fe):
+    """Two successive designs (the second a small perturbation of the first, as
+    between optimisation iterations): starting the second solve from the
+    first solution converges to the same tolerance with fewer Newton steps."""
+    p1 = inputs.scaled_config(24, 24, 24, 1e4, seed=31, extra_passes=1)
+    rng = np.random.default_rng(3)
+    p2 = inputs.scaled_config(24, 24, 24, 1e4, seed=31, extra_passes=1)
+    p2.gamma = np.clip(p1.gamma + 0.02 * rng.standard_normal(p1.n_el), 0.0, 1.0)
+    p2.gamma[p1.s > 0] = 0.0
+    opts = fe.solve_opts(rtol_newton=1e-8)
+    with fe.Server(2 << 30, max_active=2) as srv:
+        rc1, x1, _ = srv.wait(submit(fe, srv, p1, opts))
+        assert rc1 == fe.FE_OK
+        cold = srv.wait(submit(fe, srv, p2, opts))
+        ph = fe.make_phys(p2.Pr, p2.Gr, p2.Ck, p2.qf, p2.alpha_max, p2.q_alpha, p2.eg)
+        warm_opts = fe.solve_opts(rtol_newton=1e-8, atol_newton=1e-8 * cold[2]["res0"])
+        warm = srv.wait(srv.submit(p2.nx, p2.ny, p2.nz, p2.h, ph, p2.gamma, p2.s, warm_opts, x0=x1))
+    assert cold[0] == fe.FE_OK and warm[0] == fe.FE_OK
+    print(f"[serve] warm start: cold newton {cold[2]['newton_its']} lin {cold[2]['lin_its_total']}, "
+          f"warm newton {warm[2]['newton_its']} lin {warm[2]['lin_its_total']}")
+    assert warm[2]["newton_its"] < cold[2]["newton_its"]
+    r0 = np.linalg.norm(oracle.residual(p2, np.zeros(p2.n_dof), mask="solve"))
+    for x in (cold[1], warm[1]):
+        assert np.linalg.norm(oracle.residual(p2, x, mask="solve")) <= 1e-8 * r0 * 1.0001
