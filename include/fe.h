@@ -250,6 +250,81 @@ int serve_times(fe_server *s, uint64_t ticket, double *t_submit, double *t_admit
 const char *serve_error(fe_server *s, uint64_t ticket);
 int serve_destroy(fe_server *s);
 
+/* ---- optimisation loop (Sec. "Optimisation problem", Sec. "Continuation scheme") ----
+ *
+ * PDE density filter.  -r^2 lap(psi) + psi = gamma on the box grid with zero
+ * normal derivative, r = radius / (2 sqrt 3); psi trilinear on the nodes, the
+ * element design value a constant load; the filtered element value is the mean
+ * of psi over the element's nodes.  apply: out = F in; apply_transpose:
+ * out = F^T in (element vectors, device FP64[n_el]; in and out may alias).
+ * The nodal solve is conjugate gradients with Jacobi preconditioning to a
+ * relative residual of 1e-12 (FE_NOT_CONVERGED after 5000 iterations). */
+typedef struct fe_filter fe_filter;
+int fe_filter_create(const fe_grid *grid, double radius, fe_filter **out);
+int fe_filter_apply(fe_filter *f, const double *in, double *out, hipStream_t stream);
+int fe_filter_apply_transpose(fe_filter *f, const double *in, double *out, hipStream_t stream);
+int fe_filter_iterations(const fe_filter *f); /* CG iterations of the last call */
+int fe_filter_destroy(fe_filter *f);
+
+/* Method of moving asymptotes for min f0(x) s.t. f1(x) <= 0, xmin <= x <= xmax,
+ * n variables, with a move limit (fraction of xmax - xmin).  update: one
+ * iteration from x (device FP64[n], overwritten with the new iterate) given
+ * the gradients df0, df1 (device FP64[n]) and the constraint value f1;
+ * lambda_out (host, may be NULL) receives the subproblem's multiplier.  The
+ * handle keeps the asymptotes and the last two iterates between calls. */
+typedef struct fe_mma fe_mma;
+int fe_mma_create(int64_t n, double xmin, double xmax, double move, fe_mma **out);
+int fe_mma_update(fe_mma *m, double *x, const double *df0, double f1, const double *df1,
+                  double *lambda_out, hipStream_t stream);
+int fe_mma_destroy(fe_mma *m);
+
+/* Design loop: minimise the thermal compliance subject to
+ * mean over the design domain of (1 - gamma~) <= vf, gamma~ = filtered design
+ * on the design domain and gamma_fixed elsewhere.  Each design iteration
+ * filters, solves the state warm-started from the previous state (with
+ * heat-source ramping on failure), evaluates the compliance, solves the
+ * adjoint, forms the design sensitivities, takes them through the filter
+ * transpose and updates the design by MMA (objective scaled by its first
+ * value).  Continuation: n_steps steps of iters_per_step[k] iterations with
+ * the material parameters (q_f, q_alpha, alpha_max)[k]. */
+typedef struct {
+    int n_steps;               /* 1..5 (default 5) */
+    int iters_per_step[5];     /* default 100 each */
+    double q_f[5], q_alpha[5], alpha_max[5]; /* default: the paper's five steps */
+    double vf;                 /* volume fraction (default 0.05) */
+    double filter_radius;      /* R in element sizes (default 2.5) */
+    double move;               /* MMA move limit (default 0.2) */
+    fe_solve_opts state;       /* state solves (default rtol_newton 1e-4, ramp_steps 4) */
+    fe_solve_opts adjoint;     /* adjoint solves (default rtol_lin 1e-6) */
+} fe_topopt_opts;
+typedef struct {
+    int iter, step;            /* design iteration, continuation step */
+    double f, f_scaled, g;     /* compliance, compliance / first compliance, constraint */
+    double change;             /* largest design change of the MMA update */
+    double lambda_mma;         /* MMA subproblem multiplier */
+    int newton_its, lin_its, adj_its, ramp_stages;
+    double t_state_s, t_adjoint_s, t_total_s;
+} fe_topopt_record;
+typedef struct fe_topopt fe_topopt;
+void fe_topopt_opts_default(fe_topopt_opts *opts);
+/* p: the state problem (its mask and grid; its material parameters are set by
+ * the continuation); design_mask: device uint8[n_el], 1 = design element;
+ * gamma_fixed, s_elem: device FP64[n_el] (gamma off the design domain, heat
+ * source), borrowed until fe_topopt_destroy. */
+int fe_topopt_create(fe_problem *p, const uint8_t *design_mask, const double *gamma_fixed,
+                     const double *s_elem, const fe_topopt_opts *opts, fe_topopt **out);
+/* f, g and (if not NULL) their gradients with respect to the design values
+ * rho (device FP64[n_el], entries off the design domain ignored; gradients 0
+ * there) at rho; x: device FP64[n_dof], initial vector in, state out. */
+int fe_topopt_evaluate(fe_topopt *t, const double *rho, double *x, double *f, double *g,
+                       double *dfdrho, double *dgdrho, fe_topopt_record *rec, hipStream_t stream);
+/* One design iteration: evaluate at rho, then rho <- MMA update (design entries). */
+int fe_topopt_step(fe_topopt *t, double *rho, double *x, fe_topopt_record *rec, hipStream_t stream);
+/* The whole continuation; hist (host, cap records, may be NULL), n_done: iterations run. */
+int fe_topopt_run(fe_topopt *t, double *rho, double *x, fe_topopt_record *hist, int cap,
+                  int *n_done, hipStream_t stream);
+int fe_topopt_destroy(fe_topopt *t);
+
 const char *fe_last_error(void);
 const char *fe_version(void);
 

@@ -74,6 +74,27 @@ class FeSolveReport(ctypes.Structure):
                 "mg_levels": self.mg_levels, "ramp_stages": self.ramp_stages}
 
 
+class FeTopoptOpts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int), ("iters_per_step", ctypes.c_int * 5),
+                ("q_f", ctypes.c_double * 5), ("q_alpha", ctypes.c_double * 5),
+                ("alpha_max", ctypes.c_double * 5), ("vf", ctypes.c_double),
+                ("filter_radius", ctypes.c_double), ("move", ctypes.c_double),
+                ("state", FeSolveOpts), ("adjoint", FeSolveOpts)]
+
+
+class FeTopoptRecord(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int), ("step", ctypes.c_int), ("f", ctypes.c_double),
+                ("f_scaled", ctypes.c_double), ("g", ctypes.c_double),
+                ("change", ctypes.c_double), ("lambda_mma", ctypes.c_double),
+                ("newton_its", ctypes.c_int), ("lin_its", ctypes.c_int),
+                ("adj_its", ctypes.c_int), ("ramp_stages", ctypes.c_int),
+                ("t_state_s", ctypes.c_double), ("t_adjoint_s", ctypes.c_double),
+                ("t_total_s", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FeError(RuntimeError):
     def __init__(self, code: int, what: str, msg: str):
         super().__init__(f"{what} failed with code {code}: {msg}")
@@ -102,6 +123,21 @@ def lib() -> ctypes.CDLL:
         L.fe_jvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.fe_adjoint_jtvp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.fe_jacobian_dense.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fe_filter_create.argtypes = [P(FeGrid), dbl, P(vp)]
+        L.fe_filter_apply.argtypes = [vp, vp, vp, vp]
+        L.fe_filter_apply_transpose.argtypes = [vp, vp, vp, vp]
+        L.fe_filter_iterations.argtypes = [vp]
+        L.fe_filter_destroy.argtypes = [vp]
+        L.fe_mma_create.argtypes = [ctypes.c_int64, dbl, dbl, dbl, P(vp)]
+        L.fe_mma_update.argtypes = [vp, vp, vp, dbl, vp, P(dbl), vp]
+        L.fe_mma_destroy.argtypes = [vp]
+        L.fe_topopt_opts_default.argtypes = [P(FeTopoptOpts)]
+        L.fe_topopt_opts_default.restype = None
+        L.fe_topopt_create.argtypes = [vp, vp, vp, vp, P(FeTopoptOpts), P(vp)]
+        L.fe_topopt_evaluate.argtypes = [vp, vp, vp, P(dbl), P(dbl), vp, vp, P(FeTopoptRecord), vp]
+        L.fe_topopt_step.argtypes = [vp, vp, vp, P(FeTopoptRecord), vp]
+        L.fe_topopt_run.argtypes = [vp, vp, vp, P(FeTopoptRecord), i32, P(i32), vp]
+        L.fe_topopt_destroy.argtypes = [vp]
         L.fe_kernel_timer.argtypes = [vp, i32]
         L.fe_kernel_timer_read.argtypes = [vp, P(dbl), P(ctypes.c_int64)]
         L.fe_dR_dgamma.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -432,3 +468,140 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+# ---- optimisation loop ----------------------------------------------------------------
+
+class Filter:
+    """PDE density filter on an element grid (radius R in length units)."""
+
+    def __init__(self, nx, ny, nz, h, radius):
+        self.n_el = nx * ny * nz
+        h_ = ctypes.c_void_p()
+        _check(lib().fe_filter_create(ctypes.byref(FeGrid(nx, ny, nz, h)), radius, ctypes.byref(h_)),
+               "fe_filter_create")
+        self.handle = h_
+
+    def apply(self, x, out=None, stream=None):
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().fe_filter_apply(self.handle, _ptr(x, torch.float64), _ptr(out, torch.float64),
+                                     _stream(stream)), "fe_filter_apply")
+        return out
+
+    def apply_transpose(self, x, out=None, stream=None):
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().fe_filter_apply_transpose(self.handle, _ptr(x, torch.float64),
+                                               _ptr(out, torch.float64), _stream(stream)),
+               "fe_filter_apply_transpose")
+        return out
+
+    @property
+    def iterations(self) -> int:
+        return int(lib().fe_filter_iterations(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().fe_filter_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MMA:
+    """Method of moving asymptotes, one constraint, on the device."""
+
+    def __init__(self, n, xmin=0.0, xmax=1.0, move=0.2):
+        h_ = ctypes.c_void_p()
+        _check(lib().fe_mma_create(n, xmin, xmax, move, ctypes.byref(h_)), "fe_mma_create")
+        self.handle = h_
+
+    def update(self, x, df0, f1, df1, stream=None) -> float:
+        lam = ctypes.c_double()
+        _check(lib().fe_mma_update(self.handle, _ptr(x, torch.float64), _ptr(df0, torch.float64),
+                                   float(f1), _ptr(df1, torch.float64), ctypes.byref(lam),
+                                   _stream(stream)), "fe_mma_update")
+        return lam.value
+
+    def close(self):
+        if self.handle:
+            lib().fe_mma_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def topopt_opts(**kw) -> FeTopoptOpts:
+    o = FeTopoptOpts()
+    lib().fe_topopt_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k in ("state", "adjoint") and isinstance(v, dict):
+            sub = getattr(o, k)
+            for kk, vv in v.items():
+                if kk == "krylov_op_prec" and isinstance(vv, str):
+                    vv = FE_FP32 if vv in ("fp32", "mixed") else FE_FP64
+                setattr(sub, kk, vv)
+        elif k in ("iters_per_step", "q_f", "q_alpha", "alpha_max"):
+            arr = getattr(o, k)
+            for i, vv in enumerate(v):
+                arr[i] = vv
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class TopOpt:
+    """Design loop on a state problem; design_mask (uint8), gamma_fixed, s: device tensors
+    of length n_el, kept alive by this object."""
+
+    def __init__(self, prob: Problem, design_mask, gamma_fixed, s, opts: Optional[FeTopoptOpts] = None):
+        self.prob = prob
+        self._keep = (design_mask, gamma_fixed, s)
+        h_ = ctypes.c_void_p()
+        _check(lib().fe_topopt_create(prob.handle, _ptr(design_mask, torch.uint8),
+                                      _ptr(gamma_fixed, torch.float64), _ptr(s, torch.float64),
+                                      ctypes.byref(opts) if opts is not None else None,
+                                      ctypes.byref(h_)), "fe_topopt_create")
+        self.handle = h_
+
+    def evaluate(self, rho, x, grads=True, stream=None):
+        f, g = ctypes.c_double(), ctypes.c_double()
+        df = torch.zeros_like(rho) if grads else None
+        dg = torch.zeros_like(rho) if grads else None
+        rec = FeTopoptRecord()
+        _check(lib().fe_topopt_evaluate(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
+                                        ctypes.byref(f), ctypes.byref(g), _ptr(df, torch.float64),
+                                        _ptr(dg, torch.float64), ctypes.byref(rec), _stream(stream)),
+               "fe_topopt_evaluate")
+        return f.value, g.value, df, dg, rec.as_dict()
+
+    def step(self, rho, x, stream=None) -> dict:
+        rec = FeTopoptRecord()
+        _check(lib().fe_topopt_step(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
+                                    ctypes.byref(rec), _stream(stream)), "fe_topopt_step")
+        return rec.as_dict()
+
+    def run(self, rho, x, cap=10000, stream=None):
+        hist = (FeTopoptRecord * cap)()
+        n = ctypes.c_int()
+        _check(lib().fe_topopt_run(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
+                                   hist, cap, ctypes.byref(n), _stream(stream)), "fe_topopt_run")
+        return [hist[i].as_dict() for i in range(min(n.value, cap))]
+
+    def close(self):
+        if self.handle:
+            lib().fe_topopt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,128 @@
+"""Optimisation loop on the GPU through the C-ABI: PDE filter and MMA against
+the oracle's, the design gradient against the oracle's chain, and a short run
+on the paper's cavity."""
+import numpy as np
+import pytest
+
+from oracle import topopt as otop
+from oracle.filter import Filter as OFilter
+from oracle.mma import MMA as OMMA
+from paper_1508_04596_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def rel_max(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("dims", [(13, 9, 11), (32, 32, 64)])
+def test_filter_parity(fe, dims):
+    nx, ny, nz = dims
+    h = 1.0 / max(dims)
+    rng = np.random.default_rng(11)
+    gam = rng.uniform(0.0, 1.0, nx * ny * nz)
+    ref = OFilter(nx, ny, nz, h, 2.5 * h)
+    f = fe.Filter(nx, ny, nz, h, 2.5 * h)
+    out = f.apply(dev(gam)).cpu().numpy()
+    its = f.iterations
+    outT = f.apply_transpose(dev(gam)).cpu().numpy()
+    print(f"[filter] {dims}: CG iterations {its}")
+    assert rel_max(out, ref.apply(gam)) <= 1e-10
+    assert rel_max(outT, ref.apply_transpose(gam)) <= 1e-10
+    ones = f.apply(dev(np.ones(nx * ny * nz))).cpu().numpy()
+    assert np.abs(ones - 1.0).max() <= 1e-11
+    f.close()
+
+
+def test_mma_parity(fe):
+    n = 3000
+    rng = np.random.default_rng(12)
+    x = rng.uniform(0.1, 0.9, n)
+    ref = OMMA(n, move=0.2)
+    m = fe.MMA(n, move=0.2)
+    xg = dev(x)
+    xr = x.copy()
+    for k in range(4):
+        df0 = rng.uniform(-2.0, 0.5, n)
+        df1 = np.full(n, 1.0 / n) + 1e-3 * rng.standard_normal(n)
+        f1 = [0.05, -0.01, 0.02, 0.0][k]
+        xr, lr = ref.update(xr, 1.0, df0, f1, df1)
+        lg = m.update(xg, dev(df0), f1, dev(df1))
+        xa = xg.cpu().numpy()
+        print(f"[mma] update {k}: lambda gpu {lg:.15e} oracle {lr:.15e}")
+        assert abs(lg - lr) <= 1e-10 * max(abs(lr), 1e-300) or lr == lg == 0.0
+        assert np.abs(xa - xr).max() <= 1e-10
+        xg = dev(xr)  # continue both from the oracle's iterate
+    m.close()
+
+
+def cavity_setup(fe, N=20, Gr=1e3, s0=10.0, seed=4):
+    p = inputs.cavity_problem(N, Gr, s0=s0)
+    rng = np.random.default_rng(seed)
+    rho = np.where(p.design, rng.uniform(0.3, 1.0, p.n_el), 0.0)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    return p, prob, rho
+
+
+def test_design_gradient_parity(fe):
+    p, prob, rho = cavity_setup(fe)
+    design = dev(p.design.astype(np.uint8), torch.uint8)
+    gfix, s = dev(p.gamma), dev(p.s)
+    opts = fe.topopt_opts(vf=0.05, state=dict(rtol_newton=1e-12, ramp_steps=0),
+                          adjoint=dict(rtol_lin=1e-12))
+    T = fe.TopOpt(prob, design, gfix, s, opts)
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    f, g, df, dg, rec = T.evaluate(dev(rho), x)
+    ofilt = OFilter(p.nx, p.ny, p.nz, p.h, 2.5 * p.h)
+    fr, gr, dfr, dgr, _ = otop.evaluate(p, ofilt, rho, p.design, p.gamma, vf=0.05)
+    print(f"[topopt] f {f:.12e} oracle {fr:.12e}; g {g:.6e} oracle {gr:.6e}; rec {rec}")
+    assert abs(f - fr) <= 1e-10 * abs(fr)
+    assert abs(g - gr) <= 1e-12
+    assert rel_max(df.cpu().numpy(), dfr) <= 1e-8
+    assert rel_max(dg.cpu().numpy(), dgr) <= 1e-10
+    T.close()
+    prob.close()
+
+
+def test_short_optimisation_run(fe):
+    """12 design iterations of the first continuation step: the compliance falls,
+    the volume constraint ends satisfied, and the run is bitwise repeatable."""
+    p, prob, _ = cavity_setup(fe)
+    design = dev(p.design.astype(np.uint8), torch.uint8)
+    gfix, s = dev(p.gamma), dev(p.s)
+    opts = fe.topopt_opts(vf=0.05, n_steps=1, iters_per_step=[12, 0, 0, 0, 0],
+                          state=dict(rtol_newton=1e-6))
+    results = []
+    for _ in range(2):
+        T = fe.TopOpt(prob, design, gfix, s, opts)
+        rho = dev(np.where(p.design, 0.95, 0.0))
+        x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+        hist = T.run(rho, x)
+        results.append((rho.cpu().numpy(), hist))
+        T.close()
+    rho1, hist = results[0]
+    for r in hist:
+        print(f"[topopt] it {r['iter']} f {r['f']:.6e} g {r['g']:+.3e} change {r['change']:.3f} "
+              f"newton {r['newton_its']} lin {r['lin_its']} adj {r['adj_its']} t {r['t_total_s']*1e3:.0f} ms")
+    assert len(hist) == 12
+    assert hist[-1]["f"] < hist[0]["f"]
+    assert hist[-1]["g"] <= 1e-3
+    assert np.array_equal(results[0][0], results[1][0])
+    assert np.all((rho1[p.design] >= 0.0) & (rho1[p.design] <= 1.0))
+    prob.close()
