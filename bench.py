@@ -255,10 +255,24 @@ def cpu_baseline(p, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return {"value": p.n_dof * n / el / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same on one thread, a shorter sample
+    oracle.set_num_threads(1)
+    n1 = 0
+    t1 = time.perf_counter()
+    while True:
+        oracle.jvp(p, x, v, mask="solve")
+        n1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= seconds / 3:
+            break
+    oracle.set_num_threads(cores)
+    return {"value": p.n_dof * n / el / 1e9, "unit": "GDOF/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} FP64 J v products of the CPU oracle on the same 64^3 problem "
-                      f"({el:.1f} s)"}
+                      f"({el:.1f} s)",
+            "value_1_thread": p.n_dof * n1 / el1 / 1e9,
+            "sample_1_thread": f"{n1} products on one thread ({el1:.1f} s)"}
 
 
 if __name__ == "__main__":

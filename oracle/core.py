@@ -167,6 +167,14 @@ def num_threads() -> int:
     return int(_load().or_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's element loops (timing only)."""
+    L = _load()
+    L.or_set_num_threads.argtypes = [ctypes.c_int]
+    L.or_set_num_threads.restype = None
+    L.or_set_num_threads(int(n))
+
+
 def _mask(p, mask):
     if mask is None:
         return None

@@ -574,6 +574,15 @@ int or_gauss_points(int nx, int ny, int nz, double h, double *xg)
     return 0;
 }
 
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP
