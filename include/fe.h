@@ -145,6 +145,10 @@ typedef struct {
                                with the heat source scaled by k/ramp_steps, k = 1..ramp_steps, each
                                warm-started from the previous one; the last one is held to the
                                original tolerance.  0 (default) = off */
+    int mg_assembled_nodes; /* multigrid: levels above the coarsest with at most this many nodes
+                               apply their operator as an assembled 27-point block stencil (built
+                               from element Jacobians once per Newton step) instead of the
+                               matrix-free element pass; -1 (default) = 10000, 0 = none */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

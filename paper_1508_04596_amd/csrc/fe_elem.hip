@@ -1253,6 +1253,47 @@ __global__ __launch_bounds__(256) void k_probe_from_jac(Geo g, const double *__r
     probe_out[tid] = acc;
 }
 
+// The assembled operator of a small grid as a 27-point block stencil, from its
+// element Jacobians: S[((d 5 + g) 5 + f) nn + N] is entry (N g, M f) with
+// M = N + (dx, dy, dz), d = (dx + 1) + 3 (dy + 1) + 9 (dz + 1).  The entry sums
+// one element entry per element around N that also holds M, in increasing
+// element order (the order of the probing products above).  Prescribed rows
+// are identity rows; prescribed columns are zero in Je already; neighbours
+// outside the grid give zero entries.
+__global__ __launch_bounds__(256) void k_stencil_from_jac(Geo g, const double *__restrict__ Je,
+                                                          const uint8_t *__restrict__ nmask,
+                                                          double *__restrict__ S)
+{
+    const int64_t nn = n_nodes(g);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= 675 * nn) return;
+    const int q = (int)(tid / nn);
+    const int64_t N = tid - (int64_t)q * nn;
+    const int d = q / 25, gr = (q / NF) % NF, f = q % NF;
+    const int ddx = d % 3 - 1, ddy = (d / 3) % 3 - 1, ddz = d / 9 - 1;
+    const int I = (int)(N % (g.nx + 1)), J = (int)((N / (g.nx + 1)) % (g.ny + 1)),
+              K = (int)(N / ((int64_t)(g.nx + 1) * (g.ny + 1)));
+    if ((nmask[N] >> gr) & 1) {
+        S[tid] = (d == 13 && f == gr) ? 1.0 : 0.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int dz = -1; dz <= 0; ++dz)
+        for (int dy = -1; dy <= 0; ++dy)
+            for (int dx = -1; dx <= 0; ++dx) {
+                const int ei = I + dx, ej = J + dy, ek = K + dz;
+                if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx || ej >= g.ny || ek >= g.nz) continue;
+                // corners of N and of M in this element
+                const int bx = -dx + ddx, by = -dy + ddy, bz = -dz + ddz;
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                const int64_t e = ei + (int64_t)g.nx * (ej + (int64_t)g.ny * ek);
+                const int aN = (-dx) | ((-dy) << 1) | ((-dz) << 2);
+                const int b = bx | (by << 1) | (bz << 2);
+                acc += Je[(e * 40 + 8 * gr + aN) * 40 + 8 * f + b];
+            }
+    S[tid] = acc;
+}
+
 // ---- launchers ----------------------------------------------------------------------
 
 template <typename Tin, typename Tout>
@@ -1353,6 +1394,18 @@ template hipError_t launch_elem_smooth<float>(bool, const Geo &, const float *, 
                                               const double *, const double *, const uint8_t *,
                                               float *, float *, const float *, const float *, float,
                                               hipStream_t);
+
+hipError_t launch_stencil_assemble(const Geo &g, const double *x, const double *gamma,
+                                   const double *s, const uint8_t *nmask, double *Je, double *S,
+                                   hipStream_t st)
+{
+    const int64_t ne = n_elem(g), nn = n_nodes(g);
+    hipLaunchKernelGGL(k_elem_jac, dim3((unsigned)((ne * 40 + 63) / 64)), dim3(64), 0, st, g, x,
+                       gamma, s, nmask, Je);
+    hipLaunchKernelGGL(k_stencil_from_jac, dim3((unsigned)((675 * nn + 255) / 256)), dim3(256), 0,
+                       st, g, (const double *)Je, nmask, S);
+    return hipGetLastError();
+}
 
 hipError_t launch_probe_products(const Geo &g, const double *x, const double *gamma,
                                  const double *s, const uint8_t *nmask, double *Je,

@@ -75,6 +75,11 @@ template <typename T>
 hipError_t launch_elem_smooth(bool tr, const Geo &g, const T *xs, T *x, const double *gamma,
                               const double *s, const uint8_t *nmask, T *t, T *slots, const T *D,
                               const T *b, T omega, hipStream_t st);
+// Element Jacobians of grid g into Je (1600 per element), then its 27-point block
+// stencil S (675 per node, [offset][row field][column field][node]).
+hipError_t launch_stencil_assemble(const Geo &g, const double *x, const double *gamma,
+                                   const double *s, const uint8_t *nmask, double *Je, double *S,
+                                   hipStream_t st);
 // The 135 colour-by-field probing products J p_q of a small grid, from element
 // Jacobians (Je: n_elem * 1600 doubles of work space; probe_out: 135 * n_dof,
 // product q at offset q * n_dof).

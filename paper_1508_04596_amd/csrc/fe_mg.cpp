@@ -6,10 +6,14 @@
 // the design and source are averaged over the eight child elements, the
 // linearisation state is injected from the coincident fine nodes, and the
 // element kernels of the fine level evaluate J v on every level.  Smoothing is
-// damped nodal block-Jacobi; the coarsest level is solved directly with a band
-// LU factorisation of its assembled Jacobian (assembled on the GPU by 135
-// probing products, one per (node colour mod 3^3, field)).  V-cycles run in
-// FP64, or in FP32 when the Krylov operator is FP32.
+// damped nodal block-Jacobi; small levels apply their operator as an assembled
+// 27-point block stencil (from element Jacobians, once per Newton step), since
+// the element pass costs the same latency however few tiles a grid has.  The
+// coarsest level is solved directly: its Jacobian is assembled from 135
+// probing products (one per (node colour mod 3^3, field)), factorised by band
+// LU on the host, and inverted explicitly on the GPU from the factors, so that
+// each V-cycle's coarse solve is one matrix-vector product on the device.
+// V-cycles run in FP64, or in FP32 when the Krylov operator is FP32.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -33,6 +37,13 @@ hipError_t mg_prolong_add(int nfx, int nfy, int nfz, const T *xc, const uint8_t 
 template <typename T>
 hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T omega, bool transpose,
                      bool accumulate, hipStream_t st);
+template <typename T>
+hipError_t mg_stencil_apply(int nx, int ny, int nz, const T *S, const T *v, T *out, bool transpose,
+                            hipStream_t st);
+hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const double *Uc,
+                             const double *Ud, const int *piv, double *X, hipStream_t st);
+template <typename T>
+hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, bool transpose, hipStream_t st);
 
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
@@ -50,6 +61,8 @@ static void free_level(fe_problem *p, MgLevel &L, bool owned)
         dfree(p, L.slots);
         dfree(p, L.slots25);
     }
+    dfree(p, L.S);
+    dfree(p, L.S32);
     dfree(p, L.b);
     dfree(p, L.xs);
     dfree(p, L.t);
@@ -65,9 +78,16 @@ void mg_free(Mg *mg)
     for (size_t l = 0; l < mg->lev.size(); ++l) free_level(p, mg->lev[l], l > 0);
     dfree(p, mg->probe);
     dfree(p, mg->probe_out);
+    dfree(p, mg->dfac);
+    dfree(p, mg->dpiv);
+    dfree(p, mg->Xinv);
     hfree(p, mg->hbuf);
+    hfree(p, mg->hfac);
+    hfree(p, mg->hpiv);
     delete mg;
 }
+
+int64_t mg_asm_nodes(int opt) { return opt < 0 ? MG_ASM_NODES_DEFAULT : (int64_t)opt; }
 
 int mg_num_levels(const fe_grid &g)
 {
@@ -88,13 +108,19 @@ int mg_num_levels(const fe_grid &g)
 
 static int64_t r256(int64_t b) { return (b + 255) / 256 * 256; }
 
+// Half bandwidth of the coarsest matrix in lexicographic node order, NF DOF per node.
+static int64_t coarse_band(const fe_grid &c)
+{
+    return NF * (1 + (c.nx + 1) + (int64_t)(c.nx + 1) * (c.ny + 1)) + NF - 1;
+}
+
 // Device bytes mg_create allocates for grid g (each allocation rounded up to 256 B).
-int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed)
+int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed, int64_t asm_nodes)
 {
     const int nl = mg_num_levels(g0);
     if (nl < 2) return 0;
     fe_grid g = g0;
-    int64_t b = 0, ndof_c = 0, ne_c = 0;
+    int64_t b = 0, ndof_c = 0, ne_c = 0, ne_je = 0;
     for (int l = 0; l < nl; ++l) {
         if (l > 0) {
             g.nx /= 2;
@@ -114,15 +140,22 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed)
         }
         b += r256(8 * ndof);
         if (mixed) b += r256(4 * ndof);
+        if (l < nl - 1 && nn <= asm_nodes) {
+            b += r256(8 * 675 * nn);
+            if (mixed) b += r256(4 * 675 * nn);
+            ne_je = std::max(ne_je, ne);
+        }
         ndof_c = ndof;
         ne_c = ne;
     }
-    b += r256(8 * 1600 * ne_c) + r256(8 * 135 * ndof_c);
+    b += r256(8 * 1600 * std::max(ne_c, ne_je)) + r256(8 * 135 * ndof_c);
+    const int64_t bw = coarse_band(g);
+    b += r256(8 * ndof_c * (3 * bw + 1)) + r256(4 * ndof_c) + r256(8 * ndof_c * ndof_c);
     return b;
 }
 
 // Allocate the hierarchy for problem p (levels >= 1 own their data).
-int mg_create(fe_problem *p, bool mixed, Mg **out)
+int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
 {
     *out = nullptr;
     const int nl = mg_num_levels(p->grid);
@@ -134,6 +167,7 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
     Mg *mg = new Mg();
     mg->owner = p;
     mg->mixed = mixed;
+    mg->asm_nodes = asm_nodes;
     mg->lev.resize(nl);
     hipError_t e = hipSuccess;
     fe_grid g = p->grid;
@@ -170,23 +204,33 @@ int mg_create(fe_problem *p, bool mixed, Mg **out)
         }
         if (e == hipSuccess) e = dalloc(p, &L.t, nb);
         if (e == hipSuccess && mixed) e = dalloc(p, &L.t32, sizeof(float) * L.ndof);
+        L.assembled = l < nl - 1 && L.nn <= asm_nodes;
+        if (L.assembled) {
+            if (e == hipSuccess) e = dalloc(p, &L.S, sizeof(double) * 675 * L.nn);
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.S32, sizeof(float) * 675 * L.nn);
+        }
     }
     const MgLevel &C = mg->lev.back();
     mg->nc = C.ndof;
-    if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 1600 * C.ne);  // element Jacobians
+    int64_t ne_je = C.ne;
+    for (const MgLevel &L : mg->lev)
+        if (L.assembled) ne_je = std::max(ne_je, L.ne);
+    if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 1600 * ne_je);  // element Jacobians
     if (e == hipSuccess) e = dalloc(p, &mg->probe_out, sizeof(double) * 135 * C.ndof);
     if (e == hipSuccess) e = halloc(p, &mg->hbuf, sizeof(double) * 135 * C.ndof);
+    const int bw = (int)coarse_band(C.grid);
+    mg->kl = mg->ku = bw;
+    const size_t nfac = (size_t)C.ndof * (3 * bw + 1);
+    if (e == hipSuccess) e = halloc(p, &mg->hfac, sizeof(double) * nfac);
+    if (e == hipSuccess) e = halloc(p, &mg->hpiv, sizeof(int) * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->dfac, sizeof(double) * nfac);
+    if (e == hipSuccess) e = dalloc(p, &mg->dpiv, sizeof(int) * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->Xinv, sizeof(double) * C.ndof * C.ndof);
     if (e != hipSuccess) {
         mg_free(mg);
         return hip_fail(e, "hipMalloc (multigrid)");
     }
-    const int bw = (int)(NF * (1 + (C.grid.nx + 1) + (int64_t)(C.grid.nx + 1) * (C.grid.ny + 1)) + NF - 1);
-    mg->kl = mg->ku = bw;
     mg->A.assign((size_t)C.ndof * C.ndof, 0.0);
-    mg->piv.assign(C.ndof, 0);
-    mg->Lc.assign((size_t)C.ndof * bw, 0.0);
-    mg->Uc.assign((size_t)C.ndof * 2 * bw, 0.0);
-    mg->hb.assign(C.ndof + 2 * bw, 0.0);  // 2 bw entries of scratch, then the vector
     *out = mg;
     return FE_OK;
 }
@@ -208,12 +252,16 @@ int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, h
     return FE_OK;
 }
 
-// Band LU with partial pivoting of the dense-stored coarsest matrix.
+// Band LU with partial pivoting of the dense-stored coarsest matrix; the
+// factors go to the pinned buffers in the layout the device inverse reads.
 static int band_lu(Mg *mg)
 {
     const int64_t n = mg->nc;
     const int kl = mg->kl, ku = mg->ku;
+    const int64_t w = kl + ku;
     double *A = mg->A.data();
+    double *Lc = mg->hfac, *Uc = Lc + n * kl, *Ud = Uc + n * w;
+    int *piv = mg->hpiv;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t iend = std::min<int64_t>(n - 1, k + kl);
         int64_t p = k;
@@ -223,7 +271,7 @@ static int band_lu(Mg *mg)
                 best = std::fabs(A[i * n + k]);
                 p = i;
             }
-        mg->piv[k] = (int)p;
+        piv[k] = (int)p;
         if (best == 0.0 || !std::isfinite(best)) {
             set_error("multigrid: singular or non-finite coarsest-level matrix");
             return FE_ENAN;
@@ -235,69 +283,21 @@ static int band_lu(Mg *mg)
         for (int64_t i = k + 1; i <= iend; ++i) {
             const double l = A[i * n + k] * inv;
             A[i * n + k] = l;
-            mg->Lc[k * kl + (i - k - 1)] = l;
+            Lc[k * kl + (i - k - 1)] = l;
             if (l != 0.0)
                 for (int64_t j = k + 1; j <= jend; ++j) A[i * n + j] -= l * A[k * n + j];
         }
-        for (int64_t i = iend + 1; i <= k + kl; ++i) mg->Lc[k * kl + (i - k - 1)] = 0.0;
+        for (int64_t i = iend + 1; i <= k + kl; ++i) Lc[k * kl + (i - k - 1)] = 0.0;
     }
-    // U by columns for the back substitution: Uc[k w + t] = U(k - w + t, k), w = kl + ku
-    const int64_t w = kl + ku;
-    for (int64_t k = 0; k < n; ++k)
+    // U by columns: Uc[k w + t] = U(k - w + t, k), and its diagonal
+    for (int64_t k = 0; k < n; ++k) {
         for (int64_t t = 0; t < w; ++t) {
             const int64_t r = k - w + t;
-            mg->Uc[k * w + t] = r >= 0 ? A[r * n + k] : 0.0;
+            Uc[k * w + t] = r >= 0 ? A[r * n + k] : 0.0;
         }
-    return FE_OK;
-}
-
-// b: the right-hand side on entry, the solution on exit; it is preceded by
-// kl + ku entries of scratch (the back substitution's column updates run into
-// them instead of being clipped).  Both sweeps of the forward solve are
-// contiguous multiply-subtract loops over a column of L or U.
-static void band_solve(const Mg *mg, double *b, bool transpose)
-{
-    const int64_t n = mg->nc;
-    const int kl = mg->kl, ku = mg->ku;
-    const double *A = mg->A.data();
-    if (!transpose) {
-        const double *__restrict__ Lc = mg->Lc.data();  // multipliers of column k, contiguous
-        for (int64_t k = 0; k < n; ++k) {
-            const int64_t p = mg->piv[k];
-            if (p != k) std::swap(b[k], b[p]);
-            const int64_t cnt = std::min<int64_t>(n - 1, k + kl) - k;
-            const double bk = b[k];
-            const double *__restrict__ l = Lc + k * kl;
-            double *__restrict__ y = b + k + 1;
-            for (int64_t q = 0; q < cnt; ++q) y[q] -= l[q] * bk;
-        }
-        const int64_t w = kl + ku;
-        for (int64_t t = 1; t <= w; ++t) b[-t] = 0.0;
-        for (int64_t k = n - 1; k >= 0; --k) {
-            const double xk = b[k] / A[k * n + k];
-            b[k] = xk;
-            const double *__restrict__ u = mg->Uc.data() + k * w;
-            double *__restrict__ y = b + k - w;
-            for (int64_t t = 0; t < w; ++t) y[t] -= u[t] * xk;
-        }
-    } else {
-        // A^T x = b with A = P^T L U: U^T y = b, then L^T and the swaps in reverse
-        for (int64_t k = 0; k < n; ++k) {
-            const int64_t j0 = std::max<int64_t>(0, k - kl - ku);
-            double s = b[k];
-            for (int64_t j = j0; j < k; ++j) s -= A[j * n + k] * b[j];
-            b[k] = s / A[k * n + k];
-        }
-        const double *Lc = mg->Lc.data();
-        for (int64_t k = n - 1; k >= 0; --k) {
-            const int64_t cnt = std::min<int64_t>(n - 1, k + kl) - k;
-            double s = b[k];
-            for (int64_t q = 0; q < cnt; ++q) s -= Lc[k * kl + q] * b[k + 1 + q];
-            b[k] = s;
-            const int64_t p = mg->piv[k];
-            if (p != k) std::swap(b[k], b[p]);
-        }
+        Ud[k] = A[k * n + k];
     }
+    return FE_OK;
 }
 
 // Per Newton step: linearisation states and block diagonals on every level,
@@ -320,6 +320,13 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
             if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(C.x, C.x32, C.ndof, st)));
         }
     }
+    // assembled levels: element Jacobians, then the 27-point block stencil
+    for (int l = 0; l < nl - 1; ++l) {
+        MgLevel &L = mg->lev[l];
+        if (!L.assembled) continue;
+        FE_CHECK_HIP(launch_stencil_assemble(L.geo, L.x, L.gamma, L.s, L.nmask, mg->probe, L.S, st));
+        if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.S, L.S32, 675 * L.nn, st)));
+    }
     // coarsest level: the 135 probing products J p_(colour,field) in FP64, from
     // its element Jacobians (two launches)
     MgLevel &C = mg->lev.back();
@@ -329,7 +336,17 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
                                 hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipStreamSynchronize(st));
     assemble_from_probes(C.grid, mg->hbuf, mg->A.data());
-    return band_lu(mg);
+    int rc = band_lu(mg);
+    if (rc) return rc;
+    // the factors to the device (the next host write to hfac follows a stream
+    // synchronisation above), then A^{-1} column by column
+    const int64_t n = mg->nc, w = mg->kl + mg->ku;
+    FE_CHECK_HIP(hipMemcpyAsync(mg->dfac, mg->hfac, sizeof(double) * n * (mg->kl + w + 1),
+                                hipMemcpyHostToDevice, st));
+    FE_CHECK_HIP(hipMemcpyAsync(mg->dpiv, mg->hpiv, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    const double *Lc = mg->dfac, *Uc = Lc + n * mg->kl, *Ud = Uc + n * w;
+    FE_CHECK_HIP(mg_coarse_inverse((int)n, mg->kl, mg->ku, Lc, Uc, Ud, mg->dpiv, mg->Xinv, st));
+    return FE_OK;
 }
 
 // Dense row-major J from the 135 colour-by-field probing products: entry
@@ -378,24 +395,41 @@ template <>
 const float *blocksT<float>(const MgLevel &L) { return L.D32; }
 
 template <typename T>
+static const T *stencilT(const MgLevel &L);
+template <>
+const double *stencilT<double>(const MgLevel &L) { return L.S; }
+template <>
+const float *stencilT<float>(const MgLevel &L) { return L.S32; }
+
+template <typename T>
 static hipError_t op(const MgLevel &L, const T *v, T *out, bool tr, hipStream_t st)
 {
+    if (L.assembled)
+        return mg_stencil_apply<T>(L.grid.nx, L.grid.ny, L.grid.nz, stencilT<T>(L), v, out, tr, st);
     return launch_elem<T, T>(tr ? OP_JTV : OP_JV, L.geo, stateT<T>(L), v, L.gamma, L.s, L.nmask, out,
                              (T *)L.slots, st);
 }
 
+// One damped block-Jacobi sweep x += omega D^{-1} (b - A x) (transposed when tr):
+// fused with the element pass on matrix-free levels, stencil product then
+// nodal update on assembled ones.
 template <typename T>
-static int coarse_solve(Mg *mg, MgLevel &C, const T *b, T *x, bool tr, hipStream_t st)
+static hipError_t smooth_sweep(const MgLevel &L, const T *D, const T *b, T *x, T *t, T om, bool tr,
+                               hipStream_t st)
 {
-    const int64_t n = C.ndof;
-    T *h = reinterpret_cast<T *>(mg->hbuf);
-    FE_CHECK_HIP(hipMemcpyAsync(h, b, sizeof(T) * n, hipMemcpyDeviceToHost, st));
-    FE_CHECK_HIP(hipStreamSynchronize(st));
-    double *hb = mg->hb.data() + (mg->kl + mg->ku);
-    for (int64_t i = 0; i < n; ++i) hb[i] = (double)h[i];
-    band_solve(mg, hb, tr);
-    for (int64_t i = 0; i < n; ++i) h[i] = (T)hb[i];
-    FE_CHECK_HIP(hipMemcpyAsync(x, h, sizeof(T) * n, hipMemcpyHostToDevice, st));
+    if (L.assembled) {
+        hipError_t e = op<T>(L, x, t, tr, st);
+        if (e != hipSuccess) return e;
+        return mg_smooth<T>(D, b, t, x, L.nn, om, tr, true, st);
+    }
+    return launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t, (T *)L.slots,
+                                 D, b, om, st);
+}
+
+template <typename T>
+static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
+{
+    FE_CHECK_HIP(mg_coarse_apply<T>((int)mg->nc, mg->Xinv, b, x, tr, st));
     return FE_OK;
 }
 
@@ -404,14 +438,12 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
 {
     MgLevel &L = mg->lev[l];
     const int nl = (int)mg->lev.size();
-    if (l == nl - 1) return coarse_solve<T>(mg, L, b, x, tr, st);
+    if (l == nl - 1) return coarse_solve<T>(mg, b, x, tr, st);
     const T om = (T)mg->omega;
     const T *D = blocksT<T>(L);
     T *t = vecT<T>(L, 2);
     FE_CHECK_HIP(mg_smooth<T>(D, b, nullptr, x, L.nn, om, tr, false, st));
-    for (int it = 1; it < mg->nu1; ++it)
-        FE_CHECK_HIP(launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t,
-                                           (T *)L.slots, D, b, om, st));
+    for (int it = 1; it < mg->nu1; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
     MgLevel &C = mg->lev[l + 1];
     FE_CHECK_HIP(op<T>(L, x, t, tr, st));
     T *bc = vecT<T>(C, 0), *xc = vecT<T>(C, 1);
@@ -419,9 +451,7 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
     int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st);
     if (rc) return rc;
     FE_CHECK_HIP(mg_prolong_add<T>(L.grid.nx, L.grid.ny, L.grid.nz, xc, L.nmask, x, st));
-    for (int it = 0; it < mg->nu2; ++it)
-        FE_CHECK_HIP(launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t,
-                                           (T *)L.slots, D, b, om, st));
+    for (int it = 0; it < mg->nu2; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
     return FE_OK;
 }
 

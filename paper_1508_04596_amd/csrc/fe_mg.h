@@ -20,6 +20,10 @@ struct MgLevel {
     double *slots = nullptr, *slots25 = nullptr;
     double *b = nullptr, *xs = nullptr, *t = nullptr;    // FP64 rhs, correction, work
     float *b32 = nullptr, *xs32 = nullptr, *t32 = nullptr;
+    // small levels: the operator assembled as a 27-point block stencil (675 per node)
+    bool assembled = false;
+    double *S = nullptr;
+    float *S32 = nullptr;
 };
 
 struct Mg {
@@ -28,13 +32,19 @@ struct Mg {
     bool mixed = false;
     int nu1 = 2, nu2 = 2;
     double omega = 0.6;
-    // coarsest level: dense-stored band LU
+    // coarsest level: band LU of the dense-stored matrix on the host, explicit
+    // inverse from its factors on the device
     int64_t nc = 0;
     int kl = 0, ku = 0;
-    std::vector<double> A, hb, Lc;  // dense band LU, work vector, L multipliers by column
-    std::vector<double> Uc;         // U by columns, kl + ku entries above the diagonal each
-    std::vector<int> piv;
-    double *probe = nullptr;      // element Jacobians of the coarsest level, 1600 per element
+    std::vector<double> A;   // dense work matrix of the factorisation
+    double *hfac = nullptr;  // pinned: L by columns [nc kl], U above the diagonal by columns
+                             // [nc (kl + ku)], diagonal of U [nc]
+    int *hpiv = nullptr;     // pinned: pivot rows [nc]
+    double *dfac = nullptr;  // device copy of hfac
+    int *dpiv = nullptr;     // device copy of hpiv
+    double *Xinv = nullptr;  // device: A^{-1} by columns, nc x nc
+    int64_t asm_nodes = 0;        // levels with at most this many nodes are assembled
+    double *probe = nullptr;      // element Jacobians (coarsest or assembled level), 1600 per element
     double *probe_out = nullptr;  // 135 probing products, [q][n_dof]
     double *hbuf = nullptr;
 };
@@ -43,9 +53,15 @@ struct Mg {
 // (probe: [q][n_dof] on the host).
 void assemble_from_probes(const fe_grid &grid, const double *probe, double *A);
 
+// Default node-count limit of assembled levels (an assembled level streams 675
+// stencil entries per node instead of running the element pass, whose latency
+// does not shrink with the grid).
+constexpr int64_t MG_ASM_NODES_DEFAULT = 10000;
+int64_t mg_asm_nodes(int opt);  // option value -> limit (-1: default, 0: none)
+
 int mg_num_levels(const fe_grid &g);
-int64_t mg_footprint_bytes(const fe_grid &g, bool mixed);
-int mg_create(fe_problem *p, bool mixed, Mg **out);
+int64_t mg_footprint_bytes(const fe_grid &g, bool mixed, int64_t asm_nodes);
+int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out);
 void mg_free(Mg *mg);
 int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, hipStream_t st);
 int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const float *D032,

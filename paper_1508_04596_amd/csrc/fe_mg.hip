@@ -1,8 +1,10 @@
-// Grid-transfer and smoothing kernels of the matrix-free geometric multigrid
+// Grid-transfer, smoothing and small-level kernels of the geometric multigrid
 // preconditioner (Sec. "Solving the linear systems": flexible GMRES with a
 // geometric multigrid preconditioner; here the coarse operators are
 // rediscretised on the coarse grid instead of formed by Galerkin projection,
-// since no matrix is assembled).
+// since the fine operator is never assembled).  Small levels apply their
+// rediscretised operator as an assembled 27-point block stencil, and the
+// coarsest level through an explicit inverse formed from its band LU factors.
 //
 // Coarse grids halve the element count in every direction; coarse node
 // (I,J,K) coincides with fine node (2I,2J,2K).  Prolongation is trilinear
@@ -49,71 +51,345 @@ __global__ void k_inject(int ncx, int ncy, int ncz, const Tf *__restrict__ f, Tc
     for (int q = 0; q < NV; ++q) c[NV * n + q] = (Tc)f[NV * fn + q];
 }
 
-// b_c = R (b - t) on unprescribed coarse DOFs, 0 on prescribed ones.
+// b_c = R (b - t) on unprescribed coarse DOFs, 0 on prescribed ones; one
+// thread per coarse DOF.  The 27 fine neighbours are unrolled with clamped
+// addresses and a select for those outside the grid, so that their loads are
+// in flight together (a loop that skips them issues one neighbour at a time);
+// the sum keeps the dz, dy, dx order.
 template <typename T>
-__global__ void k_restrict(int ncx, int ncy, int ncz, const T *__restrict__ b,
-                           const T *__restrict__ t, const uint8_t *__restrict__ cmask,
-                           T *__restrict__ bc)
+__global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, const T *__restrict__ b,
+                                                  const T *__restrict__ t,
+                                                  const uint8_t *__restrict__ cmask,
+                                                  T *__restrict__ bc)
 {
     const int64_t nn = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NF * nn) return;
+    const int64_t n = q / NF;
+    const int f = (int)(q - NF * n);
     const int I = (int)(n % (ncx + 1));
     const int64_t r = n / (ncx + 1);
     const int J = (int)(r % (ncy + 1)), K = (int)(r / (ncy + 1));
     const int nfx = 2 * ncx, nfy = 2 * ncy, nfz = 2 * ncz;
-    T acc[NF] = {T(0), T(0), T(0), T(0), T(0)};
+    T acc = T(0);
+#pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
         const int k = 2 * K + dz;
-        if (k < 0 || k > nfz) continue;
+        const bool inz = k >= 0 && k <= nfz;
+        const int kc = k < 0 ? 0 : (k > nfz ? nfz : k);
         const T wz = dz == 0 ? T(1) : T(0.5);
+#pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
             const int j = 2 * J + dy;
-            if (j < 0 || j > nfy) continue;
+            const bool iny = j >= 0 && j <= nfy;
+            const int jc = j < 0 ? 0 : (j > nfy ? nfy : j);
             const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 const int i = 2 * I + dx;
-                if (i < 0 || i > nfx) continue;
+                const bool in = inz && iny && i >= 0 && i <= nfx;
+                const int ic = i < 0 ? 0 : (i > nfx ? nfx : i);
                 const T w = (dx == 0 ? T(1) : T(0.5)) * wy * wz;
-                const int64_t fn = i + (int64_t)(nfx + 1) * (j + (int64_t)(nfy + 1) * k);
-#pragma unroll
-                for (int f = 0; f < NF; ++f) acc[f] += w * (b[NF * fn + f] - (t ? t[NF * fn + f] : T(0)));
+                const int64_t fn = ic + (int64_t)(nfx + 1) * (jc + (int64_t)(nfy + 1) * kc);
+                const T v = w * (b[NF * fn + f] - (t ? t[NF * fn + f] : T(0)));
+                acc += in ? v : T(0);
             }
         }
     }
-    const uint8_t m = cmask[n];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) bc[NF * n + f] = ((m >> f) & 1) ? T(0) : acc[f];
+    bc[q] = ((cmask[n] >> f) & 1) ? T(0) : acc;
 }
 
-// x += P xc on unprescribed fine DOFs (trilinear interpolation).
+// x += P xc on unprescribed fine DOFs (trilinear interpolation); one thread
+// per fine DOF.  The up to 8 coarse parents are unrolled (along an even index
+// the parent repeats with its term dropped) so that their loads issue together.
 template <typename T>
-__global__ void k_prolong_add(int nfx, int nfy, int nfz, const T *__restrict__ xc,
-                              const uint8_t *__restrict__ fmask, T *__restrict__ x)
+__global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, const T *__restrict__ xc,
+                                                     const uint8_t *__restrict__ fmask, T *__restrict__ x)
 {
     const int64_t nn = (int64_t)(nfx + 1) * (nfy + 1) * (nfz + 1);
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NF * nn) return;
+    const int64_t n = q / NF;
+    const int f = (int)(q - NF * n);
     const int i = (int)(n % (nfx + 1));
     const int64_t r = n / (nfx + 1);
     const int j = (int)(r % (nfy + 1)), k = (int)(r / (nfy + 1));
     const int ncx = nfx / 2, ncy = nfy / 2;
-    int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-    const T wi = ni == 2 ? T(0.5) : T(1), wj = nj == 2 ? T(0.5) : T(1), wk = nk == 2 ? T(0.5) : T(1);
-    T acc[NF] = {T(0), T(0), T(0), T(0), T(0)};
-    for (int c = 0; c < nk; ++c)
-        for (int bq = 0; bq < nj; ++bq)
-            for (int a = 0; a < ni; ++a) {
-                const int64_t cn = (I0 + a) + (int64_t)(ncx + 1) * ((J0 + bq) + (int64_t)(ncy + 1) * (K0 + c));
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    const int oi = i & 1, oj = j & 1, ok = k & 1;  // a second parent along odd directions
+    const T wi = oi ? T(0.5) : T(1), wj = oj ? T(0.5) : T(1), wk = ok ? T(0.5) : T(1);
+    T acc = T(0);
 #pragma unroll
-                for (int f = 0; f < NF; ++f) acc[f] += xc[NF * cn + f];
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const bool use = (c <= ok) && (bq <= oj) && (a <= oi);
+                const int64_t cn = (I0 + a * oi) + (int64_t)(ncx + 1) * ((J0 + bq * oj) + (int64_t)(ncy + 1) * (K0 + c * ok));
+                const T v = xc[NF * cn + f];
+                acc += use ? v : T(0);
             }
-    const T w = wi * wj * wk;
-    const uint8_t m = fmask[n];
+    if (!((fmask[n] >> f) & 1)) x[q] += wi * wj * wk * acc;
+}
+
+// out = A v (A^T v when TR) for an assembled 27-point block stencil
+// S[((d 5 + g) 5 + f) nn + N] (entry (N g, N + offset(d) f)).  A block of 9
+// waves computes 64 output DOFs (node index fastest, so that stencil loads
+// coalesce): wave p sums the three offsets d = 3p .. 3p + 2 over the five
+// fields, all 30 loads of a lane in flight together, and the nine partials are
+// added in wave order through LDS.  Row (N g) of A^T is column (N g) of A: entry
+// (M f, N g) sits in row M at the opposite offset 26 - d.  Neighbours outside
+// the grid load a clamped node and drop the term.
+template <typename T, bool TR>
+__global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, const T *__restrict__ S,
+                                                       const T *__restrict__ v, T *__restrict__ out)
+{
+    __shared__ T part[9][64];
+    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = q < NF * nn;
+    const int g = live ? (int)(q / nn) : 0;
+    const int64_t N = live ? q - (int64_t)g * nn : 0;
+    const int I = (int)(N % (nx + 1));
+    const int64_t r = N / (nx + 1);
+    const int J = (int)(r % (ny + 1)), K = (int)(r / (ny + 1));
+    const int j = J + p % 3 - 1, k = K + p / 3 - 1;
+    const bool injk = j >= 0 && j <= ny && k >= 0 && k <= nz;
+    T acc = T(0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-        if (!((m >> f) & 1)) x[NF * n + f] += w * acc[f];
+    for (int c = 0; c < 3; ++c) {
+        const int d = 3 * p + c, i = I + c - 1;
+        const bool in = live && injk && i >= 0 && i <= nx;
+        const int64_t M = in ? i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k) : N;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const T a = TR ? S[((26 - d) * 25 + f * NF + g) * nn + M] : S[(d * 25 + g * NF + f) * nn + N];
+            const T t = a * v[NF * M + f];
+            acc += in ? t : T(0);
+        }
+    }
+    part[p][lane] = acc;
+    __syncthreads();
+    if (p == 0 && live) {
+        T sum = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < 9; ++w) sum += part[w][lane];
+        out[NF * N + g] = sum;
+    }
+}
+
+// ---- coarsest level: explicit inverse from the band LU factors ---------------
+
+// Factors of P A = L U as the host factorisation leaves them (partial pivoting
+// interleaved with the elimination): column k of L holds kl multipliers
+// Lc[k kl + q] (row k + 1 + q); column k of U above the diagonal holds
+// Uc[k w + t] = U(k - w + t, k), w = kl + ku; Ud[k] = U(k, k); row k was
+// swapped with row piv[k] >= k before column k was eliminated.
+//
+// A block of CI_T threads computes two columns j0, j0 + 1 of X = A^{-1} by the
+// same forward and back substitution as a single solve, applied to unit
+// vectors held in LDS (Y[i 2 + r], row i of right-hand side r).  Each step is
+// one multiply-subtract of a factor column followed by a barrier; the factor
+// column, pivot and diagonal of step k + CI_D are loaded at step k into one of
+// CI_D register sets (the step loop is unrolled CI_D times so the sets stay in
+// registers) and the barrier waits for LDS only, so these loads stay in flight
+// across CI_D steps.  With LONG, columns longer than the register sets load
+// the rest directly.  Forward steps before j0 - kl only move zeros and are
+// skipped.  The back substitution finishes row k at step k and writes it to X
+// (by columns: X[j n + i] = (A^{-1})_ij).
+constexpr int CI_T = 256;
+constexpr int CI_PFF = 2;  // forward: up to 2 CI_T entries (kl <= 256) from registers
+constexpr int CI_PFB = 4;  // back: up to 4 CI_T entries (kl + ku <= 512) from registers
+constexpr int CI_D = 8;
+
+// A zero the compiler cannot see through: indexing with it turns a uniform
+// load into a vector load, which the step loop waits for by vmcnt together
+// with the factor columns (a scalar load would be waited for by every LDS
+// access of the following steps).
+__device__ __forceinline__ int ci_vzero()
+{
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
+// Barrier for LDS only: the fences are restricted to the local address space,
+// so global loads in flight are not waited for.
+__device__ __forceinline__ void ci_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+struct CiFwd {
+    double v[CI_PFF];
+    int p;
+};
+struct CiBack {
+    double v[CI_PFB];
+    double d;
+};
+
+__device__ __forceinline__ void ci_load_fwd(int k, int n, int kl, const double *__restrict__ Lc,
+                                            const int *__restrict__ piv, int tid, CiFwd &c)
+{
+    // branch-free: entries past the column load its first entry and are zeroed
+    const bool live = k < n;
+    const int cnt = live ? (min(n - 1, k + kl) - k) * 2 : 0;
+    const double *col = Lc + (int64_t)(live ? k : 0) * kl;
+    const int pl = piv[(live ? k : 0) + ci_vzero()];
+    c.p = live ? pl : 0;
+#pragma unroll
+    for (int m = 0; m < CI_PFF; ++m) {
+        const int idx = tid + CI_T * m;
+        const double t = col[idx < cnt ? idx >> 1 : 0];
+        c.v[m] = idx < cnt ? t : 0.0;
+    }
+}
+
+__device__ __forceinline__ void ci_load_back(int k, int w, const double *__restrict__ Uc,
+                                             const double *__restrict__ Ud, int tid, CiBack &c)
+{
+    const bool live = k >= 0;
+    const int rows = live ? min(w, k) : 0, cnt = rows * 2;
+    const double *col = cnt > 0 ? Uc + (int64_t)k * w + (w - rows) : Uc;
+    const double dl = Ud[(live ? k : 0) + ci_vzero()];
+    c.d = live ? dl : 1.0;
+#pragma unroll
+    for (int m = 0; m < CI_PFB; ++m) {
+        const int idx = tid + CI_T * m;
+        const double t = col[idx < cnt ? idx >> 1 : 0];
+        c.v[m] = idx < cnt ? t : 0.0;
+    }
+}
+
+template <bool LONG>
+__global__ __launch_bounds__(CI_T) void k_coarse_inverse(int n, int kl, int w, const double *__restrict__ Lc,
+                                                         const double *__restrict__ Uc,
+                                                         const double *__restrict__ Ud,
+                                                         const int *__restrict__ piv,
+                                                         double *__restrict__ X)
+{
+    extern __shared__ double Y[];  // 2 n entries
+    const int tid = threadIdx.x;
+    const int j0 = 2 * blockIdx.x;
+    const bool two = j0 + 1 < n;
+    for (int idx = tid; idx < 2 * n; idx += CI_T) Y[idx] = ((idx >> 1) == j0 + (idx & 1)) ? 1.0 : 0.0;
+    ci_sync();
+    // forward: swaps and the multipliers of L
+    const int k0 = max(0, j0 - kl);
+    {
+        CiFwd F[CI_D];
+#pragma unroll
+        for (int u = 0; u < CI_D; ++u) ci_load_fwd(k0 + u, n, kl, Lc, piv, tid, F[u]);
+        for (int kb = k0; kb < n; kb += CI_D) {
+#pragma unroll
+            for (int u = 0; u < CI_D; ++u) {
+                const int k = kb + u;
+                if (k >= n) break;
+                const int p = __builtin_amdgcn_readfirstlane(F[u].p);
+                if (p != k) {
+                    if (tid < 2) {
+                        const double t = Y[2 * k + tid];
+                        Y[2 * k + tid] = Y[2 * p + tid];
+                        Y[2 * p + tid] = t;
+                    }
+                    ci_sync();
+                }
+                const double y0 = Y[2 * k], y1 = Y[2 * k + 1];
+                const int cnt = (min(n - 1, k + kl) - k) * 2;
+                double *yk = Y + 2 * (k + 1);
+#pragma unroll
+                for (int m = 0; m < CI_PFF; ++m) {
+                    const int idx = tid + CI_T * m;
+                    if (idx < cnt) yk[idx] -= F[u].v[m] * ((idx & 1) ? y1 : y0);
+                }
+                if (LONG) {
+                    const double *lk = Lc + (int64_t)k * kl;
+                    for (int idx = tid + CI_T * CI_PFF; idx < cnt; idx += CI_T)
+                        yk[idx] -= lk[idx >> 1] * ((idx & 1) ? y1 : y0);
+                }
+                ci_load_fwd(k + CI_D, n, kl, Lc, piv, tid, F[u]);
+                ci_sync();
+            }
+        }
+    }
+    // back substitution with U, by columns: step k updates rows max(0, k - w) .. k - 1
+    {
+        CiBack B[CI_D];
+#pragma unroll
+        for (int u = 0; u < CI_D; ++u) ci_load_back(n - 1 - u, w, Uc, Ud, tid, B[u]);
+        for (int kb = n - 1; kb >= 0; kb -= CI_D) {
+#pragma unroll
+            for (int u = 0; u < CI_D; ++u) {
+                const int k = kb - u;
+                if (k < 0) break;
+                const double x0 = Y[2 * k] / B[u].d, x1 = Y[2 * k + 1] / B[u].d;
+                const int rows = min(w, k), cnt = 2 * rows;
+                double *yr = Y + 2 * (k - rows);
+#pragma unroll
+                for (int m = 0; m < CI_PFB; ++m) {
+                    const int idx = tid + CI_T * m;
+                    if (idx < cnt) yr[idx] -= B[u].v[m] * ((idx & 1) ? x1 : x0);
+                }
+                if (LONG) {
+                    const double *uk = Uc + (int64_t)k * w + (w - rows);
+                    for (int idx = tid + CI_T * CI_PFB; idx < cnt; idx += CI_T)
+                        yr[idx] -= uk[idx >> 1] * ((idx & 1) ? x1 : x0);
+                }
+                if (tid == 0) X[(int64_t)j0 * n + k] = x0;
+                if (tid == 1 && two) X[(int64_t)(j0 + 1) * n + k] = x1;
+                ci_load_back(k - CI_D, w, Uc, Ud, tid, B[u]);
+                ci_sync();
+            }
+        }
+    }
+}
+
+// x = A^{-1} b on the coarsest level, FP64 accumulation.  16 waves per block,
+// 64 rows per block: wave q sums columns j = q, q + 16, ... of its rows (X is
+// stored by columns, so lanes read consecutive entries), then the 16 partials
+// are added in wave order.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_apply(int n, const double *__restrict__ X,
+                                                       const T *__restrict__ b, T *__restrict__ x)
+{
+    __shared__ double part[16][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int ic = i < n ? i : n - 1;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int j = q; j < n; j += 16) acc += X[(int64_t)j * n + ic] * (double)b[j];
+    part[q][lane] = acc;
+    __syncthreads();
+    if (q == 0 && i < n) {
+        double sum = part[0][lane];
+#pragma unroll
+        for (int m = 1; m < 16; ++m) sum += part[m][lane];
+        x[i] = (T)sum;
+    }
+}
+
+// x = A^{-T} b: row i of A^{-T} is column i of A^{-1}, contiguous.  One wave per
+// row: lane l sums j = l, l + 64, ..., then a fixed butterfly adds the lanes.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_apply_t(int n, const double *__restrict__ X,
+                                                         const T *__restrict__ b, T *__restrict__ x)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 16 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const double *col = X + (int64_t)i * n;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int j = lane; j < n; j += 64) acc += col[j] * (double)b[j];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) x[i] = (T)acc;
 }
 
 // x (+)= omega * D^{-1} (b - t) per node (D^{-T} when TR); t may be NULL (= 0);
@@ -169,7 +445,7 @@ hipError_t mg_restrict(int ncx, int ncy, int ncz, const T *b, const T *t, const 
                        T *bc, hipStream_t st)
 {
     const int64_t n = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(n)), dim3(256), 0, st, ncx, ncy, ncz, b, t, cmask, bc);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(NF * n)), dim3(256), 0, st, ncx, ncy, ncz, b, t, cmask, bc);
     return hipGetLastError();
 }
 
@@ -178,7 +454,19 @@ hipError_t mg_prolong_add(int nfx, int nfy, int nfz, const T *xc, const uint8_t 
                           hipStream_t st)
 {
     const int64_t n = (int64_t)(nfx + 1) * (nfy + 1) * (nfz + 1);
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblk(n)), dim3(256), 0, st, nfx, nfy, nfz, xc, fmask, x);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblk(NF * n)), dim3(256), 0, st, nfx, nfy, nfz, xc, fmask, x);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_stencil_apply(int nx, int ny, int nz, const T *S, const T *v, T *out, bool transpose,
+                            hipStream_t st)
+{
+    const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    if (transpose)
+        hipLaunchKernelGGL((k_stencil_apply<T, true>), dim3(nblk(NF * n, 64)), dim3(576), 0, st, nx, ny, nz, S, v, out);
+    else
+        hipLaunchKernelGGL((k_stencil_apply<T, false>), dim3(nblk(NF * n, 64)), dim3(576), 0, st, nx, ny, nz, S, v, out);
     return hipGetLastError();
 }
 
@@ -201,13 +489,39 @@ hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T ome
     return hipGetLastError();
 }
 
+hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const double *Uc,
+                             const double *Ud, const int *piv, double *X, hipStream_t st)
+{
+    const unsigned lds = (unsigned)(2 * n * sizeof(double));
+    if (2 * kl <= CI_T * CI_PFF && 2 * (kl + ku) <= CI_T * CI_PFB)
+        hipLaunchKernelGGL(k_coarse_inverse<false>, dim3((unsigned)((n + 1) / 2)), dim3(CI_T), lds, st,
+                           n, kl, kl + ku, Lc, Uc, Ud, piv, X);
+    else
+        hipLaunchKernelGGL(k_coarse_inverse<true>, dim3((unsigned)((n + 1) / 2)), dim3(CI_T), lds, st,
+                           n, kl, kl + ku, Lc, Uc, Ud, piv, X);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, bool transpose, hipStream_t st)
+{
+    if (transpose)
+        hipLaunchKernelGGL(k_coarse_apply_t<T>, dim3((unsigned)((n + 15) / 16)), dim3(1024), 0, st, n, X, b, x);
+    else
+        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, n, X, b, x);
+    return hipGetLastError();
+}
+
 #define FE_MG_INST(T)                                                                          \
     template hipError_t mg_restrict<T>(int, int, int, const T *, const T *, const uint8_t *, T *,  \
                                        hipStream_t);                                           \
     template hipError_t mg_prolong_add<T>(int, int, int, const T *, const uint8_t *, T *,        \
                                           hipStream_t);                                        \
     template hipError_t mg_smooth<T>(const T *, const T *, const T *, T *, int64_t, T, bool, bool, \
-                                     hipStream_t);
+                                     hipStream_t);                                             \
+    template hipError_t mg_stencil_apply<T>(int, int, int, const T *, const T *, T *, bool,      \
+                                            hipStream_t);                                      \
+    template hipError_t mg_coarse_apply<T>(int, const double *, const T *, T *, bool, hipStream_t);
 FE_MG_INST(double)
 FE_MG_INST(float)
 #undef FE_MG_INST

@@ -308,6 +308,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->mg_omega = 0.6;
     o->atol_newton = 0.0;
     o->ramp_steps = 0;
+    o->mg_assembled_nodes = -1;
 }
 
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
@@ -322,12 +323,13 @@ static int choose_precond(fe_problem *p, const fe_solve_opts &o, bool mixed, int
     *pc = want;
     if (want == FE_PC_MULTIGRID) {
         SolverWs *w = p->ws;
-        if (w->mg && mixed && !w->mg->mixed) {
+        const int64_t asm_nodes = mg_asm_nodes(o.mg_assembled_nodes);
+        if (w->mg && ((mixed && !w->mg->mixed) || w->mg->asm_nodes != asm_nodes)) {
             mg_free(w->mg);
             w->mg = nullptr;
         }
         if (!w->mg) {
-            int rc = mg_create(p, mixed, &w->mg);
+            int rc = mg_create(p, mixed, asm_nodes, &w->mg);
             if (rc) return rc;
         }
         w->mg->nu1 = w->mg->nu2 = o.mg_nu < 1 ? 1 : o.mg_nu;
@@ -358,7 +360,7 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
     // multigrid hierarchy
     const bool mg = opts->precond == FE_PC_MULTIGRID ||
                     (opts->precond == FE_PC_AUTO && mg_num_levels(*grid) >= 2);
-    if (mg) b += mg_footprint_bytes(*grid, mixed);
+    if (mg) b += mg_footprint_bytes(*grid, mixed, mg_asm_nodes(opts->mg_assembled_nodes));
     return b;
 }
 

@@ -48,7 +48,8 @@ class FeSolveOpts(ctypes.Structure):
                 ("krylov_op_prec", ctypes.c_int), ("ls_lambda_min", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
                 ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double),
-                ("ramp_steps", ctypes.c_int)]
+                ("ramp_steps", ctypes.c_int),
+                ("mg_assembled_nodes", ctypes.c_int)]
 
 
 class FeSolveReport(ctypes.Structure):
