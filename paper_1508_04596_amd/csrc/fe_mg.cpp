@@ -84,6 +84,7 @@ void mg_free(Mg *mg)
     hfree(p, mg->hbuf);
     hfree(p, mg->hfac);
     hfree(p, mg->hpiv);
+    if (mg->probe_ready) (void)hipEventDestroy(mg->probe_ready);
     delete mg;
 }
 
@@ -226,6 +227,7 @@ int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
     if (e == hipSuccess) e = dalloc(p, &mg->dfac, sizeof(double) * nfac);
     if (e == hipSuccess) e = dalloc(p, &mg->dpiv, sizeof(int) * C.ndof);
     if (e == hipSuccess) e = dalloc(p, &mg->Xinv, sizeof(double) * C.ndof * C.ndof);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&mg->probe_ready, hipEventDisableTiming);
     if (e != hipSuccess) {
         mg_free(mg);
         return hip_fail(e, "hipMalloc (multigrid)");
@@ -314,11 +316,21 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
     for (int l = 1; l < nl; ++l) {
         MgLevel &C = mg->lev[l], &F = mg->lev[l - 1];
         FE_CHECK_HIP(mg_inject_state(C.grid.nx, C.grid.ny, C.grid.nz, F.x, C.x, st));
-        if (l < nl - 1) {
-            FE_CHECK_HIP(launch_blockdiag(C.geo, C.x, C.gamma, C.s, C.nmask, C.D, C.slots25, st));
-            FE_CHECK_HIP(launch_invert_blocks(C.D, mg->mixed ? C.D32 : nullptr, C.nn, st));
-            if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(C.x, C.x32, C.ndof, st)));
-        }
+    }
+    // coarsest level first: the 135 probing products J p_(colour,field) in FP64
+    // from its element Jacobians (two launches), copied to the host, so that the
+    // host factorisation below overlaps the other levels' set-up on the GPU
+    MgLevel &C = mg->lev.back();
+    FE_CHECK_HIP(launch_probe_products(C.geo, C.x, C.gamma, C.s, C.nmask, mg->probe,
+                                       mg->probe_out, st));
+    FE_CHECK_HIP(hipMemcpyAsync(mg->hbuf, mg->probe_out, sizeof(double) * 135 * C.ndof,
+                                hipMemcpyDeviceToHost, st));
+    FE_CHECK_HIP(hipEventRecord(mg->probe_ready, st));
+    for (int l = 1; l < nl - 1; ++l) {
+        MgLevel &L = mg->lev[l];
+        FE_CHECK_HIP(launch_blockdiag(L.geo, L.x, L.gamma, L.s, L.nmask, L.D, L.slots25, st));
+        FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
+        if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.x, L.x32, L.ndof, st)));
     }
     // assembled levels: element Jacobians, then the 27-point block stencil
     for (int l = 0; l < nl - 1; ++l) {
@@ -327,19 +339,13 @@ int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const flo
         FE_CHECK_HIP(launch_stencil_assemble(L.geo, L.x, L.gamma, L.s, L.nmask, mg->probe, L.S, st));
         if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.S, L.S32, 675 * L.nn, st)));
     }
-    // coarsest level: the 135 probing products J p_(colour,field) in FP64, from
-    // its element Jacobians (two launches)
-    MgLevel &C = mg->lev.back();
-    FE_CHECK_HIP(launch_probe_products(C.geo, C.x, C.gamma, C.s, C.nmask, mg->probe,
-                                       mg->probe_out, st));
-    FE_CHECK_HIP(hipMemcpyAsync(mg->hbuf, mg->probe_out, sizeof(double) * 135 * C.ndof,
-                                hipMemcpyDeviceToHost, st));
-    FE_CHECK_HIP(hipStreamSynchronize(st));
+    // (the event also orders the previous set-up's copy out of hfac before the
+    // factorisation below rewrites it)
+    FE_CHECK_HIP(hipEventSynchronize(mg->probe_ready));
     assemble_from_probes(C.grid, mg->hbuf, mg->A.data());
     int rc = band_lu(mg);
     if (rc) return rc;
-    // the factors to the device (the next host write to hfac follows a stream
-    // synchronisation above), then A^{-1} column by column
+    // the factors to the device, then A^{-1} column by column
     const int64_t n = mg->nc, w = mg->kl + mg->ku;
     FE_CHECK_HIP(hipMemcpyAsync(mg->dfac, mg->hfac, sizeof(double) * n * (mg->kl + w + 1),
                                 hipMemcpyHostToDevice, st));
