@@ -302,30 +302,42 @@ static int band_lu(Mg *mg)
     return FE_OK;
 }
 
-// Per Newton step: linearisation states and block diagonals on every level,
-// FP32 copies in mixed mode, and the coarsest-level factorisation.
-int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const float *D032,
-             const float *x032, hipStream_t st)
+// Per Newton step, in two calls around the caller's own fine-level set-up:
+// mg_setup_begin injects the linearisation state into every level and starts
+// the coarsest level's probing products and their copy to the host;
+// mg_setup_finish builds the block diagonals (and FP32 copies in mixed mode)
+// and assembled stencils of the other levels, then factorises the coarsest
+// level on the host (overlapping that GPU work) and inverts it on the device.
+int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st)
 {
-    MgLevel &L0 = mg->lev[0];
-    L0.x = const_cast<double *>(x);
-    L0.D = const_cast<double *>(D0);
-    L0.D32 = const_cast<float *>(D032);
-    L0.x32 = const_cast<float *>(x032);
+    (void)p;
+    mg->lev[0].x = const_cast<double *>(x);
     const int nl = (int)mg->lev.size();
     for (int l = 1; l < nl; ++l) {
         MgLevel &C = mg->lev[l], &F = mg->lev[l - 1];
         FE_CHECK_HIP(mg_inject_state(C.grid.nx, C.grid.ny, C.grid.nz, F.x, C.x, st));
     }
-    // coarsest level first: the 135 probing products J p_(colour,field) in FP64
-    // from its element Jacobians (two launches), copied to the host, so that the
-    // host factorisation below overlaps the other levels' set-up on the GPU
+    // the 135 probing products J p_(colour,field) in FP64 from the coarsest
+    // level's element Jacobians (two launches), copied to the host
     MgLevel &C = mg->lev.back();
     FE_CHECK_HIP(launch_probe_products(C.geo, C.x, C.gamma, C.s, C.nmask, mg->probe,
                                        mg->probe_out, st));
     FE_CHECK_HIP(hipMemcpyAsync(mg->hbuf, mg->probe_out, sizeof(double) * 135 * C.ndof,
                                 hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipEventRecord(mg->probe_ready, st));
+    return FE_OK;
+}
+
+int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, const float *x032,
+                    hipStream_t st)
+{
+    (void)p;
+    MgLevel &L0 = mg->lev[0];
+    L0.D = const_cast<double *>(D0);
+    L0.D32 = const_cast<float *>(D032);
+    L0.x32 = const_cast<float *>(x032);
+    const int nl = (int)mg->lev.size();
+    MgLevel &C = mg->lev.back();
     for (int l = 1; l < nl - 1; ++l) {
         MgLevel &L = mg->lev[l];
         FE_CHECK_HIP(launch_blockdiag(L.geo, L.x, L.gamma, L.s, L.nmask, L.D, L.slots25, st));

@@ -65,8 +65,11 @@ int64_t mg_footprint_bytes(const fe_grid &g, bool mixed, int64_t asm_nodes);
 int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out);
 void mg_free(Mg *mg);
 int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, hipStream_t st);
-int mg_setup(Mg *mg, fe_problem *p, const double *x, const double *D0, const float *D032,
-             const float *x032, hipStream_t st);
+// Per Newton step: mg_setup_begin before the caller's fine-level block diagonal
+// (it starts the coarsest level's probing products), mg_setup_finish after it.
+int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st);
+int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, const float *x032,
+                    hipStream_t st);
 // z = M v with M one V-cycle (for J, or for J^T when tr)
 int mg_apply64(Mg *mg, const double *v, double *z, bool tr, hipStream_t st);
 int mg_apply32(Mg *mg, const double *v, float *z, bool tr, hipStream_t st);

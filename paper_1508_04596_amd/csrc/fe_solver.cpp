@@ -439,11 +439,21 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         if (rep.newton_its >= opts.max_newton) break;
         hipEvent_t e0 = w->ev[4], e1 = w->ev[5];
         FE_CHECK_HIP(hipEventRecord(e0, st));
+        // the multigrid's coarsest-level work starts first, so that its host
+        // factorisation overlaps the block diagonals below
+        if (pc == FE_PC_MULTIGRID) {
+            rc = mg_setup_begin(w->mg, p, x, st);
+            if (rc) {
+                rep.status = rc;
+                fill_report(report, rep);
+                return rc;
+            }
+        }
         FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
         FE_CHECK_HIP(launch_invert_blocks(w->D, mixed ? w->D32 : nullptr, p->nn, st));
         if (mixed) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
         if (pc == FE_PC_MULTIGRID) {
-            rc = mg_setup(w->mg, p, x, w->D, w->D32, w->x32, st);
+            rc = mg_setup_finish(w->mg, p, w->D, w->D32, w->x32, st);
             if (rc) {
                 rep.status = rc;
                 fill_report(report, rep);
@@ -648,11 +658,15 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
     int pc = FE_PC_BJACOBI;
     rc = choose_precond(p, opts, false, &pc);
     if (rc) return rc;
+    if (pc == FE_PC_MULTIGRID) {
+        rc = mg_set_design(w->mg, p, gamma, s_elem, st);
+        if (rc == FE_OK) rc = mg_setup_begin(w->mg, p, x, st);
+        if (rc) return rc;
+    }
     FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
     FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
     if (pc == FE_PC_MULTIGRID) {
-        rc = mg_set_design(w->mg, p, gamma, s_elem, st);
-        if (rc == FE_OK) rc = mg_setup(w->mg, p, x, w->D, nullptr, nullptr, st);
+        rc = mg_setup_finish(w->mg, p, w->D, nullptr, nullptr, st);
         if (rc) return rc;
     }
     LinSys L;
