@@ -43,7 +43,8 @@ hipError_t mg_stencil_apply(int nx, int ny, int nz, const T *S, const T *v, T *o
 hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const double *Uc,
                              const double *Ud, const int *piv, double *X, hipStream_t st);
 template <typename T>
-hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, bool transpose, hipStream_t st);
+hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, bool transpose,
+                           hipStream_t st);
 
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
@@ -81,6 +82,7 @@ void mg_free(Mg *mg)
     dfree(p, mg->dfac);
     dfree(p, mg->dpiv);
     dfree(p, mg->Xinv);
+    dfree(p, mg->cpart);
     hfree(p, mg->hbuf);
     hfree(p, mg->hfac);
     hfree(p, mg->hpiv);
@@ -152,6 +154,7 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed, int64_t asm_nodes)
     b += r256(8 * 1600 * std::max(ne_c, ne_je)) + r256(8 * 135 * ndof_c);
     const int64_t bw = coarse_band(g);
     b += r256(8 * ndof_c * (3 * bw + 1)) + r256(4 * ndof_c) + r256(8 * ndof_c * ndof_c);
+    b += r256(8 * ((ndof_c + 63) / 64) * ndof_c);
     return b;
 }
 
@@ -227,6 +230,7 @@ int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
     if (e == hipSuccess) e = dalloc(p, &mg->dfac, sizeof(double) * nfac);
     if (e == hipSuccess) e = dalloc(p, &mg->dpiv, sizeof(int) * C.ndof);
     if (e == hipSuccess) e = dalloc(p, &mg->Xinv, sizeof(double) * C.ndof * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->cpart, sizeof(double) * ((C.ndof + 63) / 64) * C.ndof);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&mg->probe_ready, hipEventDisableTiming);
     if (e != hipSuccess) {
         mg_free(mg);
@@ -447,7 +451,7 @@ static hipError_t smooth_sweep(const MgLevel &L, const T *D, const T *b, T *x, T
 template <typename T>
 static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
 {
-    FE_CHECK_HIP(mg_coarse_apply<T>((int)mg->nc, mg->Xinv, b, x, tr, st));
+    FE_CHECK_HIP(mg_coarse_apply<T>((int)mg->nc, mg->Xinv, b, x, mg->cpart, tr, st));
     return FE_OK;
 }
 

@@ -43,6 +43,7 @@ struct Mg {
     double *dfac = nullptr;  // device copy of hfac
     int *dpiv = nullptr;     // device copy of hpiv
     double *Xinv = nullptr;  // device: A^{-1} by columns, nc x nc
+    double *cpart = nullptr; // device: row partials of the coarse product, ceil(nc / 64) x nc
     hipEvent_t probe_ready = nullptr;  // the probing products have reached the host
     int64_t asm_nodes = 0;        // levels with at most this many nodes are assembled
     double *probe = nullptr;      // element Jacobians (coarsest or assembled level), 1600 per element

@@ -349,47 +349,70 @@ __global__ __launch_bounds__(CI_T) void k_coarse_inverse(int n, int kl, int w, c
     }
 }
 
-// x = A^{-1} b on the coarsest level, FP64 accumulation.  16 waves per block,
-// 64 rows per block: wave q sums columns j = q, q + 16, ... of its rows (X is
-// stored by columns, so lanes read consecutive entries), then the 16 partials
-// are added in wave order.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_apply(int n, const double *__restrict__ X,
-                                                       const T *__restrict__ b, T *__restrict__ x)
+// x = A^{-1} b (A^{-T} b when TR) on the coarsest level in two passes, FP64
+// accumulation in a fixed order.  Pass 1: block (rb, cb) multiplies the 64 x 64
+// tile of rows rb and columns cb of the operator by the matching 64 entries of
+// b and writes the 64 row partials to P[cb n + i]; pass 2 adds the partials of
+// each row in chunk order.  X is stored by columns (X[j n + i] = (A^{-1})_ij), so
+// for A^{-1} the tile is read along its rows' index i (wave q takes columns
+// q, q + 4, ...), for A^{-T} along j (wave q takes rows q, q + 4, ...; a row's 64
+// products are summed through LDS).
+constexpr int CA_B = 64;
+
+template <typename T, bool TR>
+__global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *__restrict__ X,
+                                                           const T *__restrict__ b, double *__restrict__ P)
 {
-    __shared__ double part[16][64];
+    __shared__ double tile[4][CA_B + 1];
+    __shared__ double prod[CA_B][CA_B + 1];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
-    const int ic = i < n ? i : n - 1;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int j = q; j < n; j += 16) acc += X[(int64_t)j * n + ic] * (double)b[j];
-    part[q][lane] = acc;
-    __syncthreads();
-    if (q == 0 && i < n) {
-        double sum = part[0][lane];
+    const int i0 = blockIdx.x * CA_B, j0 = blockIdx.y * CA_B;
+    if (!TR) {
+        const int i = i0 + lane;
+        const int ic = i < n ? i : n - 1;
+        double acc = 0.0;
 #pragma unroll
-        for (int m = 1; m < 16; ++m) sum += part[m][lane];
-        x[i] = (T)sum;
+        for (int m = 0; m < CA_B / 4; ++m) {
+            const int j = j0 + q + 4 * m;
+            const int jc = j < n ? j : n - 1;
+            const double t = X[(int64_t)jc * n + ic] * (double)b[jc];
+            acc += j < n ? t : 0.0;
+        }
+        tile[q][lane] = acc;
+        __syncthreads();
+        if (q == 0 && i < n)
+            P[(int64_t)blockIdx.y * n + i] = ((tile[0][lane] + tile[1][lane]) + tile[2][lane]) + tile[3][lane];
+    } else {
+        const int j = j0 + lane;
+        const int jc = j < n ? j : n - 1;
+        const double bj = j < n ? (double)b[jc] : 0.0;
+#pragma unroll
+        for (int m = 0; m < CA_B / 4; ++m) {
+            const int r = q + 4 * m;
+            const int i = i0 + r;
+            const int ic = i < n ? i : n - 1;
+            prod[r][lane] = X[(int64_t)ic * n + jc] * bj;
+        }
+        __syncthreads();
+        if (threadIdx.x < CA_B) {
+            const int i = i0 + threadIdx.x;
+            double acc = 0.0;
+            for (int l = 0; l < CA_B; ++l) acc += prod[threadIdx.x][l];
+            if (i < n) P[(int64_t)blockIdx.y * n + i] = acc;
+        }
     }
 }
 
-// x = A^{-T} b: row i of A^{-T} is column i of A^{-1}, contiguous.  One wave per
-// row: lane l sums j = l, l + 64, ..., then a fixed butterfly adds the lanes.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_apply_t(int n, const double *__restrict__ X,
-                                                         const T *__restrict__ b, T *__restrict__ x)
+__global__ __launch_bounds__(256) void k_coarse_apply_sum(int n, int nc, const double *__restrict__ P,
+                                                          T *__restrict__ x)
 {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 16 + (threadIdx.x >> 6);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *col = X + (int64_t)i * n;
     double acc = 0.0;
 #pragma unroll 8
-    for (int j = lane; j < n; j += 64) acc += col[j] * (double)b[j];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) x[i] = (T)acc;
+    for (int c = 0; c < nc; ++c) acc += P[(int64_t)c * n + i];
+    x[i] = (T)acc;
 }
 
 // x (+)= omega * D^{-1} (b - t) per node (D^{-T} when TR); t may be NULL (= 0);
@@ -502,13 +525,19 @@ hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const doub
     return hipGetLastError();
 }
 
+// P: work space of ceil(n / 64) * n doubles
 template <typename T>
-hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, bool transpose, hipStream_t st)
+hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, bool transpose,
+                           hipStream_t st)
 {
+    const int nc = (n + CA_B - 1) / CA_B;
+    const dim3 grid((unsigned)nc, (unsigned)nc);
     if (transpose)
-        hipLaunchKernelGGL(k_coarse_apply_t<T>, dim3((unsigned)((n + 15) / 16)), dim3(1024), 0, st, n, X, b, x);
+        hipLaunchKernelGGL((k_coarse_apply_part<T, true>), grid, dim3(256), 0, st, n, X, b, P);
     else
-        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, n, X, b, x);
+        hipLaunchKernelGGL((k_coarse_apply_part<T, false>), grid, dim3(256), 0, st, n, X, b, P);
+    hipLaunchKernelGGL(k_coarse_apply_sum<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, nc,
+                       (const double *)P, x);
     return hipGetLastError();
 }
 
@@ -521,7 +550,8 @@ hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, bool transp
                                      hipStream_t);                                             \
     template hipError_t mg_stencil_apply<T>(int, int, int, const T *, const T *, T *, bool,      \
                                             hipStream_t);                                      \
-    template hipError_t mg_coarse_apply<T>(int, const double *, const T *, T *, bool, hipStream_t);
+    template hipError_t mg_coarse_apply<T>(int, const double *, const T *, T *, double *, bool,    \
+                                           hipStream_t);
 FE_MG_INST(double)
 FE_MG_INST(float)
 #undef FE_MG_INST
