@@ -145,13 +145,55 @@ __global__ __launch_bounds__(RED_THREADS) void k_upd(const double *__restrict__ 
     block_sums<1>(acc, 1, partial);
 }
 
-// flag = 1 when the projected norm fell below 1/sqrt(2) of the original norm
-// (a second Gram-Schmidt pass is needed), else 0.
-__global__ void k_reorth_flag(const double *__restrict__ w2_before, const double *__restrict__ beta,
-                              double *__restrict__ flag)
+// The first pass's update fused with the second pass's projection: w -= V h
+// (h = V^T w from the first pass), then the partials of V^T w and |w|^2 of the
+// updated w, in the same per-thread order as k_upd followed by k_mdot<K, true>,
+// so V is read once for both.
+template <int K>
+__global__ __launch_bounds__(RED_THREADS) void k_upd_mdot(const double *__restrict__ V, int64_t ld,
+                                                          const double *__restrict__ h,
+                                                          double *__restrict__ w, int64_t n,
+                                                          double *__restrict__ partial)
 {
+    __shared__ double hs[K];
+    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[K + 1];
+#pragma unroll
+    for (int j = 0; j <= K; ++j) acc[j] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double vj[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
+        double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) wi -= hs[j] * vj[j];
+        w[i] = wi;
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] += vj[j] * wi;
+        acc[K] += wi * wi;
+    }
+    block_sums<K + 1>(acc, K + 1, partial);
+}
+
+// After the fused pass: flag = 1 when the projected norm beta1 fell below
+// 1/sqrt(2) of the original norm (the second pass's update is needed), else 0,
+// in which case the second-pass coefficients h2 are zeroed and beta = beta1.
+// One wave (k <= 32): lane j zeroes h2[j], lane 0 writes the flag and beta.
+__global__ void k_reorth_flag2(const double *__restrict__ w2_before, const double *__restrict__ beta1,
+                               double *__restrict__ flag, double *__restrict__ h2, int k,
+                               double *__restrict__ beta)
+{
+    const int t = threadIdx.x;
     const double nb = sqrt(w2_before[0]);
-    flag[0] = (beta[0] < 0.70710678118654752 * nb) ? 1.0 : 0.0;
+    const double b1 = beta1[0];
+    const double again = (b1 < 0.70710678118654752 * nb) ? 1.0 : 0.0;
+    if (t == 0) {
+        flag[0] = again;
+        if (again == 0.0) beta[0] = b1;
+    }
+    if (t < k && again == 0.0) h2[t] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial,
@@ -469,6 +511,23 @@ static hipError_t upd_exact(int k, const double *V, int64_t ld, const double *h,
     return hipGetLastError();
 }
 
+static hipError_t upd_mdot_exact(int k, const double *V, int64_t ld, const double *h, double *w,
+                                 int64_t n, double *partial, hipStream_t st)
+{
+    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    switch (k) {
+#define FE_UM(K)                                                                               \
+    case K:                                                                                    \
+        hipLaunchKernelGGL((k_upd_mdot<K>), g, b, 0, st, V, ld, h, w, n, partial);             \
+        break;
+        FE_K_CASES(FE_UM)
+#undef FE_UM
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, double *hbuf,
                       double *partial, hipStream_t st)
 {
@@ -482,18 +541,17 @@ hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, 
         return launch_reduce(partial, 1, hbuf + 130, nullptr, true, st);
     }
     double *flag = hbuf + 131;
-    // pass 1: h1 = V^T w and |w|^2 (stored at hbuf[k]), w -= V h1, beta = |w|
+    // pass 1: h1 = V^T w and |w|^2 (stored at hbuf[k])
     if ((e = mdot_exact(k, true, V, ld, w, n, partial, nullptr, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf, (const double *)nullptr,
                        k + 1, 0, (const double *)nullptr, 0);
-    if ((e = upd_exact(k, V, ld, hbuf, w, n, partial, nullptr, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
-                       (const double *)nullptr, 1, 1, (const double *)nullptr, 0);
-    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(1), 0, st, hbuf + k, hbuf + 130, flag);
-    // pass 2 only where the flag asks for it: h2 (zeros otherwise), w -= V h2, beta
-    if ((e = mdot_exact(k, false, V, ld, w, n, partial, flag, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, hbuf + 65, (const double *)nullptr,
-                       k, 0, flag, 1);
+    // w -= V h1 and, in the same read of V, h2 = V^T w and beta1 = |w| (hbuf[65 + k])
+    if ((e = upd_mdot_exact(k, V, ld, hbuf, w, n, partial, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf + 65,
+                       (const double *)nullptr, k + 1, 1, (const double *)nullptr, 0);
+    hipLaunchKernelGGL(k_reorth_flag2, dim3(1), dim3(64), 0, st, (const double *)(hbuf + k),
+                       (const double *)(hbuf + 65 + k), flag, hbuf + 65, k, hbuf + 130);
+    // the second pass's update only where the flag asks for it: w -= V h2, beta
     if ((e = upd_exact(k, V, ld, hbuf + 65, w, n, partial, flag, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
                        (const double *)nullptr, 1, 1, flag, 2);
