@@ -813,6 +813,8 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
 }
 
 // Tiles containing node coordinate I along one direction, in increasing order.
+// With one tile, the second entry repeats the first (a valid address for
+// unrolled loads whose term is dropped).
 __device__ __forceinline__ int tiles_of(int I, int n, int T_, int nt, int tl[2], int ll[2])
 {
     if (I % T_ == 0 && I > 0 && I < n) {
@@ -823,7 +825,42 @@ __device__ __forceinline__ int tiles_of(int I, int n, int T_, int nt, int tl[2],
     int t = I / T_;
     if (t >= nt) t = nt - 1;
     tl[0] = t; ll[0] = I - t * T_;
+    tl[1] = tl[0]; ll[1] = ll[0];
     return 1;
+}
+
+// Sum of the slot partials of node (I, J, K) over its cz x cy x cx tiles in the
+// fixed tile order (z, then y, then x).  The 2 x 2 x 2 candidates are unrolled,
+// absent ones loading nothing and adding zero, so that the slot loads of all
+// present tiles are in flight together.
+template <typename T>
+__device__ __forceinline__ void sum_slots5(const Geo &g, const T *__restrict__ slots, const int tx[2],
+                                           const int lx[2], const int ty[2], const int ly[2],
+                                           const int tz[2], const int lz[2], int cx, int cy, int cz,
+                                           T acc[NF])
+{
+#pragma unroll
+    for (int q = 0; q < NF; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const bool use = (a < cz) && (b < cy) && (cc < cx);
+                const int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[b] + (int64_t)g.nty * tz[a]);
+                const int nb = lx[cc] + BX * (ly[b] + BY * lz[a]);
+                const T *sl = slots + (tile * BOXN + nb) * NF;
+                T v[NF];
+#pragma unroll
+                for (int q = 0; q < NF; ++q) v[q] = T(0);
+                if (use) {
+#pragma unroll
+                    for (int q = 0; q < NF; ++q) v[q] = sl[q];
+                }
+#pragma unroll
+                for (int q = 0; q < NF; ++q) acc[q] += v[q];
+            }
 }
 
 // Sum the slot partials of nodes shared between tiles, in a fixed tile order.
@@ -845,17 +882,21 @@ __global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__
     int cz = tiles_of(K, g.nz, TZ, g.ntz, tz, lz);
     if (cx == 1 && cy == 1 && cz == 1) return;  // written by its only tile
     Tout acc[NV];
+    if (NV == NF) {
+        sum_slots5<Tout>(g, slots, tx, lx, ty, ly, tz, lz, cx, cy, cz, acc);
+    } else {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = Tout(0);
-    for (int a = 0; a < cz; ++a)
-        for (int b = 0; b < cy; ++b)
-            for (int cc = 0; cc < cx; ++cc) {
-                int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[b] + (int64_t)g.nty * tz[a]);
-                int nb = lx[cc] + BX * (ly[b] + BY * lz[a]);
-                const Tout *sl = slots + (tile * BOXN + nb) * NV;
+        for (int q = 0; q < NV; ++q) acc[q] = Tout(0);
+        for (int a = 0; a < cz; ++a)
+            for (int b = 0; b < cy; ++b)
+                for (int cc = 0; cc < cx; ++cc) {
+                    int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[b] + (int64_t)g.nty * tz[a]);
+                    int nb = lx[cc] + BX * (ly[b] + BY * lz[a]);
+                    const Tout *sl = slots + (tile * BOXN + nb) * NV;
 #pragma unroll
-                for (int q = 0; q < NV; ++q) acc[q] += sl[q];
-            }
+                    for (int q = 0; q < NV; ++q) acc[q] += sl[q];
+                }
+    }
     const uint8_t m = nmask[gn];
     if (NV == NF) {
 #pragma unroll
@@ -905,17 +946,7 @@ __global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restri
 #pragma unroll
         for (int f = 0; f < NF; ++f) tv[f] = t[NF * gn + f];
     } else {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) tv[f] = T(0);
-        for (int a = 0; a < cz; ++a)
-            for (int bb = 0; bb < cy; ++bb)
-                for (int cc = 0; cc < cx; ++cc) {
-                    int64_t tile = tx[cc] + (int64_t)g.ntx * (ty[bb] + (int64_t)g.nty * tz[a]);
-                    int nb = lx[cc] + BX * (ly[bb] + BY * lz[a]);
-                    const T *sl = slots + (tile * BOXN + nb) * NF;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) tv[f] += sl[f];
-                }
+        sum_slots5<T>(g, slots, tx, lx, ty, ly, tz, lz, cx, cy, cz, tv);
         const uint8_t m = nmask[gn];
 #pragma unroll
         for (int f = 0; f < NF; ++f)
