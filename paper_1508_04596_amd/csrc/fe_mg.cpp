@@ -40,6 +40,7 @@ hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T ome
 template <typename T>
 hipError_t mg_stencil_apply(int nx, int ny, int nz, const T *S, const T *v, T *out, bool transpose,
                             hipStream_t st);
+hipError_t mg_stencil_diag(int64_t nn, const double *S, double *D, hipStream_t st);
 hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const double *Uc,
                              const double *Ud, const int *piv, double *X, hipStream_t st);
 template <typename T>
@@ -344,16 +345,24 @@ int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, 
     MgLevel &C = mg->lev.back();
     for (int l = 1; l < nl - 1; ++l) {
         MgLevel &L = mg->lev[l];
-        FE_CHECK_HIP(launch_blockdiag(L.geo, L.x, L.gamma, L.s, L.nmask, L.D, L.slots25, st));
-        FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
+        if (!L.assembled) {
+            FE_CHECK_HIP(launch_blockdiag(L.geo, L.x, L.gamma, L.s, L.nmask, L.D, L.slots25, st));
+            FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
+        }
         if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.x, L.x32, L.ndof, st)));
     }
-    // assembled levels: element Jacobians, then the 27-point block stencil
+    // assembled levels: element Jacobians, then the 27-point block stencil, whose
+    // centre blocks are the smoother's diagonal blocks (below the finest level,
+    // whose blocks the caller provides)
     for (int l = 0; l < nl - 1; ++l) {
         MgLevel &L = mg->lev[l];
         if (!L.assembled) continue;
         FE_CHECK_HIP(launch_stencil_assemble(L.geo, L.x, L.gamma, L.s, L.nmask, mg->probe, L.S, st));
         if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.S, L.S32, 675 * L.nn, st)));
+        if (l > 0) {
+            FE_CHECK_HIP(mg_stencil_diag(L.nn, L.S, L.D, st));
+            FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
+        }
     }
     // (the event also orders the previous set-up's copy out of hfac before the
     // factorisation below rewrites it)

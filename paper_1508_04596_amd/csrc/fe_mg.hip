@@ -415,6 +415,19 @@ __global__ __launch_bounds__(256) void k_coarse_apply_sum(int n, int nc, const d
     x[i] = (T)acc;
 }
 
+// Nodal diagonal blocks of an assembled level from its stencil: D[n 25 + g 5 + f]
+// = S[((13 25) + g 5 + f) nn + n] (offset 13 is the node itself; prescribed rows
+// and columns already carry the identity pattern the smoother expects).
+__global__ __launch_bounds__(256) void k_stencil_diag(int64_t nn, const double *__restrict__ S,
+                                                      double *__restrict__ D)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 25 * nn) return;
+    const int64_t n = q / 25;
+    const int e = (int)(q - 25 * n);
+    D[q] = S[(int64_t)(13 * 25 + e) * nn + n];
+}
+
 // x (+)= omega * D^{-1} (b - t) per node (D^{-T} when TR); t may be NULL (= 0);
 // ACC = false overwrites x.
 template <typename T, bool TR, bool ACC>
@@ -509,6 +522,12 @@ hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T ome
         else
             hipLaunchKernelGGL((k_smooth<T, false, false>), g, bl, 0, st, D, b, t, x, nn, omega);
     }
+    return hipGetLastError();
+}
+
+hipError_t mg_stencil_diag(int64_t nn, const double *S, double *D, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stencil_diag, dim3(nblk(25 * nn)), dim3(256), 0, st, nn, S, D);
     return hipGetLastError();
 }
 

@@ -168,4 +168,15 @@ def test_multigrid_wide_band_coarsest_level(fe, prec):
     assert r <= 1e-8 * r0 * 1.0001
     assert rel_norm(xs, x_or) <= 1e-5
     assert max(rep["lin_its"]) <= 20
+    # the transposed V-cycle on the same hierarchy (adjoint solve, FP64)
+    s = dev(p.s)
+    c = torch.empty_like(x)
+    fe.fe_compliance(prob, x, s, c)
+    lam, arep = fe.fe_adjoint_solve(prob, x, dev(p.gamma), s, c,
+                                    opts=fe.solve_opts(rtol_lin=1e-10, precond="multigrid"))
+    cc = osolve.compliance_gradient_x(p, mask="solve")
+    bwd = np.linalg.norm(oracle.jtvp(p, xs, host(lam), mask="solve") - cc) / np.linalg.norm(cc)
+    print(f"[mg-slab] adjoint its {arep['lin_its_total']} oracle backward error {bwd:.3e}")
+    assert bwd <= 1e-8
+    assert arep["lin_its_total"] <= 25
     prob.close()
