@@ -137,7 +137,8 @@ typedef struct {
     double ls_lambda_min;   /* lower clamp of the line-search factor (default 0.05) */
     int verbose;            /* 0 silent, 1 one line per Newton step on stderr */
     int precond;            /* FE_PC_AUTO (default), FE_PC_BJACOBI or FE_PC_MULTIGRID */
-    int mg_nu;              /* multigrid: smoothing sweeps before and after (default 2) */
+    int mg_nu;              /* multigrid: smoothing sweeps before the coarse-grid correction
+                               (default 2; the first is x = omega D^-1 b) */
     double mg_omega;        /* multigrid: block-Jacobi damping (default 0.6) */
     double atol_newton;     /* also stop when |R|_2 <= atol_newton (default 0; for warm starts) */
     int ramp_steps;         /* recovery when Newton fails from the given vector (Sec. "Solving the
@@ -149,6 +150,8 @@ typedef struct {
                                apply their operator as an assembled 27-point block stencil (built
                                from element Jacobians once per Newton step) instead of the
                                matrix-free element pass; -1 (default) = 10000, 0 = none */
+    int mg_nu_post;         /* multigrid: smoothing sweeps after the coarse-grid correction
+                               (default 1; -1 = mg_nu) */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

@@ -30,7 +30,7 @@ struct Mg {
     fe_problem *owner = nullptr;  // allocations go through owner->alloc
     std::vector<MgLevel> lev;
     bool mixed = false;
-    int nu1 = 2, nu2 = 2;
+    int nu1 = 2, nu2 = 1;  // smoothing sweeps before and after the coarse-grid correction
     double omega = 0.6;
     // coarsest level: band LU of the dense-stored matrix on the host, explicit
     // inverse from its factors on the device

@@ -309,6 +309,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->atol_newton = 0.0;
     o->ramp_steps = 0;
     o->mg_assembled_nodes = -1;
+    o->mg_nu_post = 1;
 }
 
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
@@ -332,7 +333,8 @@ static int choose_precond(fe_problem *p, const fe_solve_opts &o, bool mixed, int
             int rc = mg_create(p, mixed, asm_nodes, &w->mg);
             if (rc) return rc;
         }
-        w->mg->nu1 = w->mg->nu2 = o.mg_nu < 1 ? 1 : o.mg_nu;
+        w->mg->nu1 = o.mg_nu < 1 ? 1 : o.mg_nu;
+        w->mg->nu2 = o.mg_nu_post < 0 ? w->mg->nu1 : o.mg_nu_post;
         w->mg->omega = o.mg_omega;
     }
     return FE_OK;

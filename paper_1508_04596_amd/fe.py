@@ -49,7 +49,7 @@ class FeSolveOpts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
                 ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double),
                 ("ramp_steps", ctypes.c_int),
-                ("mg_assembled_nodes", ctypes.c_int)]
+                ("mg_assembled_nodes", ctypes.c_int), ("mg_nu_post", ctypes.c_int)]
 
 
 class FeSolveReport(ctypes.Structure):
