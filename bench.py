@@ -29,11 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Floating-point work of one FP64 element J v evaluation: the modal 2x2x2
-# Gauss pass (points in pairs that share their y/z sums), counted from the
+# Gauss pass (points in pairs that share their y/z sums, both for the values and
+# gradients and for the test-side sums), counted from the
 # FP64 instructions of that element body built with compile-time Gauss-point
 # signs (FMA = 2 flops, add/mul = 1).  The kernel runs the same arithmetic with
 # run-time signs: multiplications by +-1 are not counted.
-FLOPS_PER_ELEM_JV = 3855.0
+FLOPS_PER_ELEM_JV = 3371.0
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP64 J v element-pass kernel on the 64^3 workload
@@ -42,7 +43,7 @@ PEAK_HBM = 8.0e12
 # torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
 # 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
 # whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14241.69, 17217.25
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = None, None
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)

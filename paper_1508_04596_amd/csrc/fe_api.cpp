@@ -39,6 +39,7 @@ Geo make_geo(const fe_grid &g, const fe_phys &ph)
     const double h = g.h;
     o.W = 0.125 * h * h * h;
     o.gs = 2.0 * 1.7320508075688772935 / h;
+    o.igs = h / (2.0 * 1.7320508075688772935);
     o.inv16h2 = 1.0 / (16.0 * h * h);
     o.cvisc = 16.0 * ph.Pr * ph.Pr / (h * h * h * h);
     o.c16h4 = 16.0 / (h * h * h * h);

@@ -52,6 +52,8 @@ struct EC {
     T cvisc;    // 16 Pr^2 / h^4 = 1/tau_2^2
     T c16h4;    // 16 / h^4: K^2 * c16h4 = 1/tau_2T^2
     T q0, q1, q2, q3;  // q^|m| / 8 for the modal scaling
+    T g1, g2, g3;      // gs q^|m| / 8: modes with |m| >= 1 held premultiplied by gs
+    T igs;             // 1 / gs
 };
 
 template <typename T>
@@ -72,6 +74,10 @@ __device__ __forceinline__ EC<T> make_ec(const Geo &g)
     c.q1 = (T)(0.125 * QG);
     c.q2 = (T)(0.125 / 3.0);
     c.q3 = (T)(0.125 * QG / 3.0);
+    c.g1 = (T)(g.gs * 0.125 * QG);
+    c.g2 = (T)(g.gs * 0.125 / 3.0);
+    c.g3 = (T)(g.gs * 0.125 * QG / 3.0);
+    c.igs = (T)g.igs;
     return c;
 }
 
@@ -115,6 +121,37 @@ __device__ __forceinline__ void to_modal(T f[8], const EC<T> &c)
     f[1] *= c.q1; f[2] *= c.q1; f[4] *= c.q1;
     f[3] *= c.q2; f[5] *= c.q2; f[6] *= c.q2;
     f[7] *= c.q3;
+}
+
+// As to_modal, with the modes m >= 1 also multiplied by gs (the form eval_pair
+// takes): gradients are then plain signed sums of coefficients.
+template <typename T>
+__device__ __forceinline__ void to_modal_g(T f[8], const EC<T> &c)
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int bit = 1 << d;
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+            if (!(a & bit)) {
+                T lo = f[a], hi = f[a | bit];
+                f[a] = lo + hi;
+                f[a | bit] = hi - lo;
+            }
+    }
+    f[0] *= c.q0;
+    f[1] *= c.g1; f[2] *= c.g1; f[4] *= c.g1;
+    f[3] *= c.g2; f[5] *= c.g2; f[6] *= c.g2;
+    f[7] *= c.g3;
+}
+
+template <bool G, typename T>
+__device__ __forceinline__ void to_modal_sel(T f[8], const EC<T> &c)
+{
+    if (G)
+        to_modal_g(f, c);
+    else
+        to_modal(f, c);
 }
 
 // Signs of the Gauss point coordinates (+1 / -1 per direction) and their
@@ -199,29 +236,31 @@ __device__ __forceinline__ void accum(const SGT &SG, T Y[8], T c, T Cx, T Cy, T 
     }
 
 // Gauss points in pairs that differ only in the x sign: the sums over the
-// y/z modes are shared by both points, so a field's value and gradient at the
-// two points cost 21 operations instead of 2 x 23.  With (sy, sz) fixed:
-//   value = A0 + sx A1,  d/dx = gs A1,  d/dy = gs (B0 + sx B1),  d/dz = gs (C0 + sx C1)
-// where A0 = m0 + sy m2 + sz m4 + sy sz m6, A1 = m1 + sy m3 + sz m5 + sy sz m7,
-// B0 = m2 + sz m6, B1 = m3 + sz m7, C0 = m4 + sy m6, C1 = m5 + sy m7.
+// y/z modes are shared by both points.  With the coefficients m[k >= 1] held
+// premultiplied by gs (to_modal_g) and (sy, sz) fixed:
+//   B0 = m2 + sz m6,  B1 = m3 + sz m7,  C0 = m4 + sy m6,  C1 = m5 + sy m7,
+//   A0 = sy B0 + sz m4,  A1 = m1 + sz m5 + sy B1,
+//   value = m0 + (A0 + sx A1) / gs,  d/dx = A1,  d/dy = B0 + sx B1,  d/dz = C0 + sx C1,
+// 15 operations per field for the two points instead of 2 x 23.
 // vm / vp receive {value, d/dx, d/dy, d/dz} at sx = -1 / +1.
 #ifndef FE_GP_PAIRS
 #define FE_GP_PAIRS 1
 #endif
 template <typename T>
-__device__ __forceinline__ void eval_pair(T sy, T sz, T syz, const T m[8], T gs, T vm[4], T vp[4])
+__device__ __forceinline__ void eval_pair(T sy, T sz, T igs, const T m[8], T vm[4], T vp[4])
 {
-    const T A0 = syz * m[6] + (sz * m[4] + (sy * m[2] + m[0]));
-    const T A1 = syz * m[7] + (sz * m[5] + (sy * m[3] + m[1]));
-    const T B0 = sz * m[6] + m[2], B1 = sz * m[7] + m[3];
-    const T C0 = sy * m[6] + m[4], C1 = sy * m[7] + m[5];
-    vm[0] = A0 - A1;
-    vp[0] = A0 + A1;
-    vm[1] = vp[1] = gs * A1;
-    vm[2] = gs * (B0 - B1);
-    vp[2] = gs * (B0 + B1);
-    vm[3] = gs * (C0 - C1);
-    vp[3] = gs * (C0 + C1);
+    const T B0 = fma(sz, m[6], m[2]), B1 = fma(sz, m[7], m[3]);
+    const T C0 = fma(sy, m[6], m[4]), C1 = fma(sy, m[7], m[5]);
+    const T A1 = fma(sy, B1, fma(sz, m[5], m[1]));
+    const T A0 = fma(sy, B0, sz * m[4]);
+    const T V0 = fma(igs, A0, m[0]);
+    vm[0] = fma(-igs, A1, V0);
+    vp[0] = fma(igs, A1, V0);
+    vm[1] = vp[1] = A1;
+    vm[2] = B0 - B1;
+    vp[2] = B0 + B1;
+    vm[3] = C0 - C1;
+    vp[3] = C0 + C1;
 }
 
 // Signs of one point of a pair: sx fixed at compile time, sy and sz at run time.
@@ -244,15 +283,68 @@ struct SgPair {
 #else  // compile-time signs; used to count the arithmetic of the element body
 #define FE_PAIR_LOOP_PRAGMA _Pragma("unroll")
 #endif
+//
+// BODY(sg, V, ACC) hands each test-side term to ACC(sg, f, c, Cx, Cy, Cz).  With
+// FE_PAIR_SUM the terms of both points are kept and the pair is added to the
+// modal sums at once (accum_pair); otherwise each point is added as it comes.
+#ifndef FE_PAIR_SUM
+#define FE_PAIR_SUM 1
+#endif
+#define FE_ACC_NOW(SG, F, C, X, Y, Z) accum(SG, out[F], C, X, Y, Z, gs);
+#define FE_ACC_M(SG, F, C, X, Y, Z) { Pm_[F][0] = C; Pm_[F][1] = X; Pm_[F][2] = Y; Pm_[F][3] = Z; }
+#define FE_ACC_P(SG, F, C, X, Y, Z) { Pp_[F][0] = C; Pp_[F][1] = X; Pp_[F][2] = Y; Pp_[F][3] = Z; }
+#if FE_PAIR_SUM
 #define FE_GAUSS_PAIRS(T, EVAL, BODY)                                            \
     FE_PAIR_LOOP_PRAGMA for (int q_ = 0; q_ < 4; ++q_) {                         \
         const T sy_ = (q_ & 1) ? T(1) : T(-1);                                   \
         const T sz_ = (q_ & 2) ? T(1) : T(-1);                                   \
         const T syz_ = sy_ * sz_;                                                \
         EVAL(sy_, sz_, syz_)                                                     \
-        { SgPair<T, false> sg(sy_, sz_, syz_); BODY(sg, Vm_) }                    \
-        { SgPair<T, true> sg(sy_, sz_, syz_); BODY(sg, Vp_) }                     \
+        T Pm_[NF][4], Pp_[NF][4];                                                \
+        { SgPair<T, false> sg(sy_, sz_, syz_); BODY(sg, Vm_, FE_ACC_M) }          \
+        { SgPair<T, true> sg(sy_, sz_, syz_); BODY(sg, Vp_, FE_ACC_P) }           \
+        _Pragma("unroll") for (int f_ = 0; f_ < NF; ++f_)                        \
+            accum_pair(sy_, sz_, syz_, out[f_], Pm_[f_], Pp_[f_], gs);           \
     }
+#else
+#define FE_GAUSS_PAIRS(T, EVAL, BODY)                                            \
+    FE_PAIR_LOOP_PRAGMA for (int q_ = 0; q_ < 4; ++q_) {                         \
+        const T sy_ = (q_ & 1) ? T(1) : T(-1);                                   \
+        const T sz_ = (q_ & 2) ? T(1) : T(-1);                                   \
+        const T syz_ = sy_ * sz_;                                                \
+        EVAL(sy_, sz_, syz_)                                                     \
+        { SgPair<T, false> sg(sy_, sz_, syz_); BODY(sg, Vm_, FE_ACC_NOW) }        \
+        { SgPair<T, true> sg(sy_, sz_, syz_); BODY(sg, Vp_, FE_ACC_NOW) }         \
+    }
+#endif
+
+// Test-side sums of a pair of Gauss points that differ only in the x sign (the
+// transpose of eval_pair).  pm / pp hold {c, Cx, Cy, Cz} of the points at
+// sx = -1 / +1; with _s / _d their sum / difference (p - m) and e = c_d + gs Cx_s:
+//   Y0 += c_s             Y1 += e
+//   Y2 += sy c_s + gs Cy_s                Y3 += sy e + gs Cy_d
+//   Y4 += sz c_s + gs Cz_s                Y5 += sz e + gs Cz_d
+//   Y6 += syz c_s + gs (sz Cy_s + sy Cz_s)  Y7 += syz e + gs (sz Cy_d + sy Cz_d)
+// which is accum applied to both points (Cx_d drops out).
+template <typename T>
+__device__ __forceinline__ void accum_pair(T sy, T sz, T syz, T Y[8], const T pm[4],
+                                           const T pp[4], T gs)
+{
+    const T cs = pp[0] + pm[0], cd = pp[0] - pm[0];
+    const T xs = pp[1] + pm[1];
+    const T ys = pp[2] + pm[2], yd = pp[2] - pm[2];
+    const T zs = pp[3] + pm[3], zd = pp[3] - pm[3];
+    const T e = fma(gs, xs, cd);
+    Y[0] += cs;
+    Y[1] += e;
+    Y[2] = fma(sy, cs, fma(gs, ys, Y[2]));
+    Y[3] = fma(sy, e, fma(gs, yd, Y[3]));
+    Y[4] = fma(sz, cs, fma(gs, zs, Y[4]));
+    Y[5] = fma(sz, e, fma(gs, zd, Y[5]));
+    const T gsy = gs * sy, gsz = gs * sz;  // shared by the five fields of a pair
+    Y[6] = fma(gsy, zs, fma(gsz, ys, fma(syz, cs, Y[6])));
+    Y[7] = fma(gsy, zd, fma(gsz, yd, fma(syz, e, Y[7])));
+}
 
 // Modal test-side sums -> nodal rows: out_a = W sum_m S[a][m] q^|m|/8 Y[m].
 template <typename T>
@@ -482,6 +574,7 @@ template <typename T, bool UNR, typename XS, typename VS>
 __device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T Kc, T s,
                                         T out[NF][8])
 {
+    constexpr bool PG = !UNR && FE_GP_PAIRS;  // paired Gauss points: gs-scaled modes
     T mu[3][8], md[3][8], mp[8], mT[8], mdp[8], mdT[8];
     T U2 = T(0), udu = T(0);
 #pragma unroll
@@ -494,8 +587,8 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T
             mu[i][a] = xa;
             md[i][a] = va;
         }
-        to_modal(mu[i], c);
-        to_modal(md[i], c);
+        to_modal_sel<PG>(mu[i], c);
+        to_modal_sel<PG>(md[i], c);
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -504,10 +597,10 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T
         mdp[a] = vs(3, a);
         mdT[a] = vs(4, a);
     }
-    to_modal(mp, c);
-    to_modal(mT, c);
-    to_modal(mdp, c);
-    to_modal(mdT, c);
+    to_modal_sel<PG>(mp, c);
+    to_modal_sel<PG>(mT, c);
+    to_modal_sel<PG>(mdp, c);
+    to_modal_sel<PG>(mdT, c);
     const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
     const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
     const T dtau = -(tau * tau * tau) * udu * c.inv16h2;
@@ -532,14 +625,14 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T
 #define FE_JV_EVAL2(SY, SZ, SYZ)                                                              \
     T Vm_[10][4], Vp_[10][4];                                                                \
     _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                          \
-        eval_pair(SY, SZ, SYZ, mu[i], gs, Vm_[i], Vp_[i]);                                    \
-        eval_pair(SY, SZ, SYZ, md[i], gs, Vm_[3 + i], Vp_[3 + i]);                            \
+        eval_pair(SY, SZ, c.igs, mu[i], Vm_[i], Vp_[i]);                                    \
+        eval_pair(SY, SZ, c.igs, md[i], Vm_[3 + i], Vp_[3 + i]);                            \
     }                                                                                        \
-    eval_pair(SY, SZ, SYZ, mp, gs, Vm_[6], Vp_[6]);                                           \
-    eval_pair(SY, SZ, SYZ, mT, gs, Vm_[7], Vp_[7]);                                           \
-    eval_pair(SY, SZ, SYZ, mdp, gs, Vm_[8], Vp_[8]);                                          \
-    eval_pair(SY, SZ, SYZ, mdT, gs, Vm_[9], Vp_[9]);
-#define FE_JV_POINT(SG, V)                                                                    \
+    eval_pair(SY, SZ, c.igs, mp, Vm_[6], Vp_[6]);                                           \
+    eval_pair(SY, SZ, c.igs, mT, Vm_[7], Vp_[7]);                                           \
+    eval_pair(SY, SZ, c.igs, mdp, Vm_[8], Vp_[8]);                                          \
+    eval_pair(SY, SZ, c.igs, mdT, Vm_[9], Vp_[9]);
+#define FE_JV_POINT(SG, V, ACC)                                                                  \
     {                                                                                        \
         T u[3], Gd[3][3], du[3], dG[3][3];                                                   \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
@@ -576,15 +669,14 @@ __device__ __forceinline__ void elem_jv(const EC<T> &c, XS xs, VS vs, T alpha, T
             if (i == 0) C0 -= dpv;                                                           \
             if (i == 1) C1 -= dpv;                                                           \
             if (i == 2) C2 -= dpv;                                                           \
-            accum(SG, out[i], dgal[i], C0, C1, C2, gs);                                       \
+            ACC(SG, i, dgal[i], C0, C1, C2)                                                  \
         }                                                                                    \
-        accum(SG, out[3], dG[0][0] + dG[1][1] + dG[2][2], A[0], A[1], A[2], gs);              \
+        ACC(SG, 3, dG[0][0] + dG[1][1] + dG[2][2], A[0], A[1], A[2])                         \
         T AT = dtauT * rT + tauT * drT, BT = tauT * rT;                                      \
-        accum(SG, out[4], drT, Kc * gdT[0] + u[0] * AT + du[0] * BT,                          \
-                 Kc * gdT[1] + u[1] * AT + du[1] * BT, Kc * gdT[2] + u[2] * AT + du[2] * BT, \
-                 gs);                                                                        \
+        ACC(SG, 4, drT, Kc * gdT[0] + u[0] * AT + du[0] * BT,                                 \
+            Kc * gdT[1] + u[1] * AT + du[1] * BT, Kc * gdT[2] + u[2] * AT + du[2] * BT)      \
     }
-#define FE_JV_GP(SG) { FE_JV_EVAL1(SG) FE_JV_POINT(SG, V1_) }
+#define FE_JV_GP(SG) { FE_JV_EVAL1(SG) FE_JV_POINT(SG, V1_, FE_ACC_NOW) }
     if (UNR || !FE_GP_PAIRS) {
         FE_GAUSS_LOOP(UNR, T, FE_JV_GP)
     } else {
@@ -607,6 +699,7 @@ template <typename T, bool UNR>
 __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], const T (*sv)[BOXN],
                                          const int nb[8], T alpha, T Kc, T s, T out[NF][8])
 {
+    constexpr bool PG = !UNR && FE_GP_PAIRS;  // paired Gauss points: gs-scaled modes
     T mu[3][8], mL[3][8], mp[8], mT[8], mP[8], mTh[8];
     T U2 = T(0);
 #pragma unroll
@@ -618,8 +711,8 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
             mu[i][a] = xa;
             mL[i][a] = sv[i][nb[a]];
         }
-        to_modal(mu[i], c);
-        to_modal(mL[i], c);
+        to_modal_sel<PG>(mu[i], c);
+        to_modal_sel<PG>(mL[i], c);
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -628,10 +721,10 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
         mP[a] = sv[3][nb[a]];
         mTh[a] = sv[4][nb[a]];
     }
-    to_modal(mp, c);
-    to_modal(mT, c);
-    to_modal(mP, c);
-    to_modal(mTh, c);
+    to_modal_sel<PG>(mp, c);
+    to_modal_sel<PG>(mT, c);
+    to_modal_sel<PG>(mP, c);
+    to_modal_sel<PG>(mTh, c);
     const T tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
     const T tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
     T Aacc = T(0), ATacc = T(0);
@@ -654,14 +747,14 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
 #define FE_JTV_EVAL2(SY, SZ, SYZ)                                                             \
     T Vm_[10][4], Vp_[10][4];                                                                \
     _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                          \
-        eval_pair(SY, SZ, SYZ, mu[i], gs, Vm_[i], Vp_[i]);                                    \
-        eval_pair(SY, SZ, SYZ, mL[i], gs, Vm_[3 + i], Vp_[3 + i]);                            \
+        eval_pair(SY, SZ, c.igs, mu[i], Vm_[i], Vp_[i]);                                    \
+        eval_pair(SY, SZ, c.igs, mL[i], Vm_[3 + i], Vp_[3 + i]);                            \
     }                                                                                        \
-    eval_pair(SY, SZ, SYZ, mp, gs, Vm_[6], Vp_[6]);                                           \
-    eval_pair(SY, SZ, SYZ, mT, gs, Vm_[7], Vp_[7]);                                           \
-    eval_pair(SY, SZ, SYZ, mP, gs, Vm_[8], Vp_[8]);                                           \
-    eval_pair(SY, SZ, SYZ, mTh, gs, Vm_[9], Vp_[9]);
-#define FE_JTV_POINT(SG, V)                                                                   \
+    eval_pair(SY, SZ, c.igs, mp, Vm_[6], Vp_[6]);                                           \
+    eval_pair(SY, SZ, c.igs, mT, Vm_[7], Vp_[7]);                                           \
+    eval_pair(SY, SZ, c.igs, mP, Vm_[8], Vp_[8]);                                           \
+    eval_pair(SY, SZ, c.igs, mTh, Vm_[9], Vp_[9]);
+#define FE_JTV_POINT(SG, V, ACC)                                                                 \
     {                                                                                        \
         T u[3], Gd[3][3], L[3], LG[3][3];                                                    \
         _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                      \
@@ -702,14 +795,13 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
             if (j == 0) C0 += Pv;                                                            \
             if (j == 1) C1 += Pv;                                                            \
             if (j == 2) C2 += Pv;                                                            \
-            accum(SG, out[j], cj, C0, C1, C2, gs);                                            \
+            ACC(SG, j, cj, C0, C1, C2)                                                       \
         }                                                                                    \
-        accum(SG, out[3], -(LG[0][0] + LG[1][1] + LG[2][2]), mI[0], mI[1], mI[2], gs);        \
-        accum(SG, out[4], c.B * (egv[0] * LM[0] + egv[1] * LM[1] + egv[2] * LM[2]),           \
-                 Kc * gTh[0] + ThM * u[0], Kc * gTh[1] + ThM * u[1], Kc * gTh[2] + ThM * u[2], \
-                 gs);                                                                        \
+        ACC(SG, 3, -(LG[0][0] + LG[1][1] + LG[2][2]), mI[0], mI[1], mI[2])                   \
+        ACC(SG, 4, c.B * (egv[0] * LM[0] + egv[1] * LM[1] + egv[2] * LM[2]),                  \
+            Kc * gTh[0] + ThM * u[0], Kc * gTh[1] + ThM * u[1], Kc * gTh[2] + ThM * u[2])    \
     }
-#define FE_JTV_GP(SG) { FE_JTV_EVAL1(SG) FE_JTV_POINT(SG, V1_) }
+#define FE_JTV_GP(SG) { FE_JTV_EVAL1(SG) FE_JTV_POINT(SG, V1_, FE_ACC_NOW) }
     if (UNR || !FE_GP_PAIRS) {
         FE_GAUSS_LOOP(UNR, T, FE_JTV_GP)
     } else {

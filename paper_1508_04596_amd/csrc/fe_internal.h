@@ -38,6 +38,7 @@ struct Geo {
     // derived per-launch constants (host-computed)
     double W;        // (h/2)^3
     double gs;       // 2/(h/sqrt(3))
+    double igs;      // 1/gs
     double inv16h2;  // 1/(16 h^2)
     double cvisc;    // 16 Pr^2 / h^4
     double c16h4;    // 16 / h^4
