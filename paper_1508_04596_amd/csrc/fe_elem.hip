@@ -432,19 +432,32 @@ __device__ __forceinline__ int64_t gnode(const Geo &g, int I, int J, int K)
 
 // Stage the node box of x (and of the masked direction v) in LDS; zero the
 // output accumulator.
+// threadIdx.x hidden from the optimiser (an empty asm statement that claims to
+// change it), so that index arithmetic derived from it is not specialised on
+// its range.  Used for the FP32 staging loop, where the code generated this way
+// measured 18 % faster on the 160x160x320 grid (12 % at 96^3, 2 % at 64^3); the
+// FP64 kernels measured 1-2 % slower with it and keep the plain index.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 template <typename T, int NVO, bool HASV>
 __device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
                                       const T *__restrict__ v, const uint8_t *__restrict__ nmask,
                                       T (*sx)[BOXN], T (*sv)[BOXN], T *so)
 {
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
+    const int tid = sizeof(T) == 4 ? opaque_tid() : (int)threadIdx.x;
     // fixed trip count, unrolled: every thread issues all of its global loads
     // before the first one is waited for
     constexpr int NIT = (BOXN * NF + NTHR - 1) / NTHR;
     T xv[NIT], vv[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int idx = threadIdx.x + it * NTHR;
+        const int idx = tid + it * NTHR;
         // branch-free: entries outside the box or the grid load node 0 and
         // are replaced by 0, so no load waits on a branch
         const int nb = idx / NF, f = idx - nb * NF;
@@ -464,7 +477,7 @@ __device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *_
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
-        const int idx = threadIdx.x + it * NTHR;
+        const int idx = tid + it * NTHR;
         if (idx < BOXN * NF) {
             int nb = idx / NF, f = idx - nb * NF;
             sx[f][nb] = xv[it];
