@@ -1036,7 +1036,10 @@ __global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restri
                                                         const T *__restrict__ b, T *x, T omega)
 {
     const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-    const int64_t gn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ T sD[256 * 25];
+    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const T *Dn = stage_blocks256(D, n0, nn, sD);
+    const int64_t gn = n0 + threadIdx.x;
     if (gn >= nn) return;
     const int I = (int)(gn % (g.nx + 1));
     const int64_t r = gn / (g.nx + 1);
@@ -1065,7 +1068,7 @@ __global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restri
         T acc = T(0);
 #pragma unroll
         for (int c = 0; c < NF; ++c)
-            acc += (OP == OP_JTV ? D[gn * 25 + c * NF + a] : D[gn * 25 + a * NF + c]) * rr[c];
+            acc += (OP == OP_JTV ? Dn[c * NF + a] : Dn[a * NF + c]) * rr[c];
         x[NF * gn + a] += omega * acc;
     }
 }

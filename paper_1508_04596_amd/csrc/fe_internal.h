@@ -53,6 +53,32 @@ __host__ __device__ inline int64_t n_nodes(const Geo &g)
 __host__ __device__ inline int64_t n_elem(const Geo &g) { return (int64_t)g.nx * g.ny * g.nz; }
 inline int64_t n_tiles(const Geo &g) { return (int64_t)g.ntx * g.nty * g.ntz; }
 
+// The nodal 5x5 blocks ([node][25], row-major) of the 256 consecutive nodes
+// n0 .. n0 + 255 copied to LDS with coalesced loads, for kernels that run one
+// thread per node: read directly, neighbouring lanes would fetch values 200 B
+// apart, 25 scattered requests per wave where 25 contiguous ones suffice.
+// Every thread of the 256-thread workgroup must call it (it synchronises the
+// workgroup).  Entries past node nn - 1 hold copies of the last block.
+// Returns this thread's block.
+template <typename T>
+__device__ __forceinline__ const T *stage_blocks256(const T *__restrict__ D, int64_t n0, int64_t nn,
+                                                    T *sD)
+{
+    const int64_t left = nn - n0;
+    const int cnt = (int)(left < 256 ? left : 256) * 25;
+    const T *src = D + n0 * 25;
+    T v[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        v[k] = src[q < cnt ? q : cnt - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 25; ++k) sD[threadIdx.x + 256 * k] = v[k];
+    __syncthreads();
+    return sD + threadIdx.x * 25;
+}
+
 // Which element operator a tile kernel evaluates.
 enum ElemOp { OP_RES = 0, OP_JV = 1, OP_JTV = 2 };
 

@@ -130,7 +130,10 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, 
                 const T v = xc[NF * cn + f];
                 acc += use ? v : T(0);
             }
-    if (!((fmask[n] >> f) & 1)) x[q] += wi * wj * wk * acc;
+    // branch-free: the load of x is issued with the mask load instead of after it
+    const int m = fmask[n];
+    const T xq = x[q];
+    x[q] = ((m >> f) & 1) ? xq : xq + wi * wj * wk * acc;
 }
 
 // out = A v (A^T v when TR) for an assembled 27-point block stencil
@@ -430,11 +433,16 @@ __global__ __launch_bounds__(256) void k_stencil_diag(int64_t nn, const double *
 
 // x (+)= omega * D^{-1} (b - t) per node (D^{-T} when TR); t may be NULL (= 0);
 // ACC = false overwrites x.
+// Launched with 256 threads per workgroup (the block staging assumes it).
 template <typename T, bool TR, bool ACC>
-__global__ void k_smooth(const T *__restrict__ D, const T *__restrict__ b, const T *__restrict__ t,
-                         T *__restrict__ x, int64_t nn, T omega)
+__global__ __launch_bounds__(256) void k_smooth(const T *__restrict__ D, const T *__restrict__ b,
+                                                const T *__restrict__ t, T *__restrict__ x,
+                                                int64_t nn, T omega)
 {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ T sD[256 * 25];
+    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const T *Dn = stage_blocks256(D, n0, nn, sD);
+    const int64_t n = n0 + threadIdx.x;
     if (n >= nn) return;
     T r[NF];
 #pragma unroll
@@ -443,7 +451,7 @@ __global__ void k_smooth(const T *__restrict__ D, const T *__restrict__ b, const
     for (int a = 0; a < NF; ++a) {
         T acc = T(0);
 #pragma unroll
-        for (int c = 0; c < NF; ++c) acc += (TR ? D[n * 25 + c * NF + a] : D[n * 25 + a * NF + c]) * r[c];
+        for (int c = 0; c < NF; ++c) acc += (TR ? Dn[c * NF + a] : Dn[a * NF + c]) * r[c];
         if (ACC)
             x[NF * n + a] += omega * acc;
         else

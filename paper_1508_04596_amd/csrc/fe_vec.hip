@@ -305,11 +305,17 @@ __global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32,
         }
 }
 
+// Launched with 256 threads per workgroup (the block staging assumes it).
 template <typename Tm, typename Tin, typename Tout, bool TR>
-__global__ void k_block_apply(const Tm *__restrict__ D, const Tin *__restrict__ v,
-                              Tout *__restrict__ z, int64_t nn, const double *__restrict__ scale)
+__global__ __launch_bounds__(256) void k_block_apply(const Tm *__restrict__ D,
+                                                     const Tin *__restrict__ v,
+                                                     Tout *__restrict__ z, int64_t nn,
+                                                     const double *__restrict__ scale)
 {
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ Tm sD[256 * 25];
+    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const Tm *Dn = stage_blocks256(D, n0, nn, sD);
+    const int64_t n = n0 + threadIdx.x;
     if (n >= nn) return;
     using Tc = Tm;
     Tc vv[5];
@@ -320,7 +326,7 @@ __global__ void k_block_apply(const Tm *__restrict__ D, const Tin *__restrict__ 
     for (int r = 0; r < 5; ++r) {
         Tc acc = 0;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) acc += (TR ? D[n * 25 + c * 5 + r] : D[n * 25 + r * 5 + c]) * vv[c];
+        for (int c = 0; c < 5; ++c) acc += (TR ? Dn[c * 5 + r] : Dn[r * 5 + c]) * vv[c];
         z[n * 5 + r] = (Tout)acc;
     }
 }
