@@ -47,6 +47,16 @@ ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.13, 17217.17
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)
+WORKLOADS = {
+    2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
+       "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+    3: "C3: 160x160x320 elements (41,603,205 DOF), Gr=1e6, 30% solid smoothed random design; "
+       "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+    4: "C4: 96x96x96 elements (4,563,365 DOF), Gr=1e5, 40% solid smoothed random design with "
+       "intermediate values; {reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+}
+
+
 # Algorithmic HBM bytes of one FP64 J v: x, v read and J v written (5 values per
 # node each), gamma and s read (one value per element each).
 def jv_bytes(n_nodes, n_el, word=8):
@@ -70,6 +80,9 @@ def main():
                     help="requests of the serving trace (Poisson arrivals, 20/s); 0 = skip")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-max-active", type=int, default=8)
+    ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
+                    help="workload: 2 = 64^3 (the reported line), 3 = 160x160x320 (the "
+                         "paper's 41.6 M DOF mesh), 4 = 96^3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -82,7 +95,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    p = inputs.config(2)
+    p = inputs.config(args.config)
     prob = fe.Problem.from_inputs(p, mask="solve")
     g = torch.from_numpy(p.gamma).to(dev)
     s = torch.from_numpy(p.s).to(dev)
@@ -165,12 +178,15 @@ def main():
     t_elem32 = float(np.median([q["t_elem32"] for q in recs]))
     bytes_alg = jv_bytes(n_nodes, n_el)
     achieved = FLOPS_PER_ELEM_JV * n_el / t_elem64
+    # the traffic counters were taken on the 64^3 workload only
+    traffic = ELEM_TRAFFIC_BYTES if args.config == 2 else None
+    n_tiles = -(-p.nx // 8) * -(-p.ny // 8) * -(-p.nz // 4)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
-            "traffic": ELEM_TRAFFIC_BYTES,
-            "kernel": "k_elem<double,double,JV> (FP64 J v element pass, 1024 tiles of 8x8x4)",
+            "traffic": traffic,
+            "kernel": f"k_elem<double,double,JV> (FP64 J v element pass, {n_tiles} tiles of 8x8x4)",
             "kernel_avg_us": t_elem64 * 1e6, "flops_per_elem": FLOPS_PER_ELEM_JV,
-            "traffic_GBps": ELEM_TRAFFIC_BYTES / t_elem64 / 1e9 if ELEM_TRAFFIC_BYTES else None,
+            "traffic_GBps": traffic / t_elem64 / 1e9 if traffic else None,
             "jv_alg_bytes": bytes_alg,
             "jv_op_alg_GBps": bytes_alg / t_jv64 / 1e9}
 
@@ -188,9 +204,7 @@ def main():
         "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid "
-                               "smoothed random design; 1000 Jv FP64 + 1000 Jv FP32 at x*, "
-                               "Newton to 1e-8 FP64 and mixed",
+        "config": {"workload": WORKLOADS[args.config].format(reps=args.jv_reps),
                    "jv_reps": args.jv_reps},
         "jv_fp64_ms": t_jv64 * 1e3, "jv_fp32_ms": t_jv32 * 1e3,
         "elem_fp64_us": t_elem64 * 1e6, "elem_fp32_us": t_elem32 * 1e6,
@@ -270,7 +284,7 @@ def cpu_baseline(p, seconds):
     oracle.set_num_threads(cores)
     return {"value": p.n_dof * n / el / 1e9, "unit": "GDOF/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} FP64 J v products of the CPU oracle on the same 64^3 problem "
+            "sample": f"{n} FP64 J v products of the CPU oracle on the same {p.nx}x{p.ny}x{p.nz} problem "
                       f"({el:.1f} s)",
             "value_1_thread": p.n_dof * n1 / el1 / 1e9,
             "sample_1_thread": f"{n1} products on one thread ({el1:.1f} s)"}
