@@ -20,5 +20,6 @@ def rel_max(a, b):
 
 def assert_parity(gpu, ref, tol=PARITY_FP64, what=""):
     rn, rm = rel_norm(gpu, ref), rel_max(gpu, ref)
+    print(f"[parity] {what}: rel norm {rn:.2e}, rel max {rm:.2e}", flush=True)
     assert rn <= tol and rm <= tol, f"{what}: rel norm {rn:.3e}, rel max {rm:.3e} > {tol:.1e}"
     return rn, rm
