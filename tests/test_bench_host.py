@@ -1,0 +1,30 @@
+"""Host-side contract of bench.py (no GPU needed): more than one GPU is
+refused with a message and exit status 2, and the workload table names every
+configuration the --config option accepts."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("cfg", [2, 3, 4])
+def test_workload_names(cfg):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1508_04596_amd import inputs
+    text = bench.WORKLOADS[cfg].format(reps=10)
+    p = inputs.config(cfg) if cfg == 2 else None
+    assert f"C{cfg}:" in text and "10 Jv FP64" in text
+    if p is not None:
+        assert f"{p.nx}x{p.ny}x{p.nz}" in text and f"{p.n_dof:,}" in text
