@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--max-lin", type=int, default=3000)
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving trace (Poisson arrivals, 20/s); 0 = skip")
+    ap.add_argument("--serve-rate", type=float, default=20.0,
+                    help="mean arrival rate of the serving trace (requests/s)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-max-active", type=int, default=8)
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
@@ -193,7 +195,7 @@ def main():
     serve = None
     if args.serve_requests > 0:
         serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                            args.serve_max_active)
+                            args.serve_max_active, args.serve_rate)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -226,12 +228,12 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def serve_trace(fe, inputs, n, budget_gb, max_active):
-    """Serving workload: n requests with Poisson arrivals at 20/s, grids uniform
+def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0):
+    """Serving workload: n requests with Poisson arrivals (20/s by default), grids uniform
     over {16,24,32,48}^3, log10 Gr uniform in [3,5], 40 %-solid smoothed random
     designs, mixed precision to 1e-8; latency = completion - arrival."""
     import time as _t
-    reqs = inputs.serving_trace(n_requests=n, rate_per_s=20.0, seed=4000)
+    reqs = inputs.serving_trace(n_requests=n, rate_per_s=rate, seed=4000)
     probs = [inputs.request_problem(r) for r in reqs]
     opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
     lat, tickets, statuses = [], [], []
@@ -249,7 +251,7 @@ def serve_trace(fe, inputs, n, budget_gb, max_active):
         times = [srv.times(t) for t in tickets]
     lat = np.array([d - a for a, _, d in times])
     makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
-    return {"requests": n, "rate_per_s": 20.0, "budget_gb": budget_gb, "max_active": max_active,
+    return {"requests": n, "rate_per_s": rate, "budget_gb": budget_gb, "max_active": max_active,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "solves_per_s": n / makespan, "all_converged": all(s == 0 for s in statuses),
             "queue_wait_p50_s": float(np.percentile([b - a for a, b, _ in times], 50))}

@@ -220,19 +220,26 @@ int fe_jacobian_dense(fe_problem *p, const double *x, const double *gamma, const
  * phi(l) = |R(x + l delta)|^2 at l = 0, 1/2, 1 (host-only helper). */
 double fe_line_search_lambda(double phi0, double phi_half, double phi1, double lambda_min);
 
-/* Device bytes newton_solve allocates for a grid (for memory admission). */
+/* Device bytes newton_solve allocates for a grid (for memory admission),
+ * including the problem handle's own buffers; opts NULL = defaults. */
 int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts);
 
 /* ---- continuous-batching server ------------------------------------------
  * Requests (grid, parameters, design, source, options) are copied in at
- * submit and queued.  A scheduler thread admits queued requests in arrival
- * order while the device memory they need fits in hbm_budget_bytes and fewer
- * than max_active are running, keeps every admitted problem's state in device
- * memory, and advances all of them together: each phase (residual, J v,
- * preconditioner, orthogonalisation) is one batched launch over the table of
- * active problems.  Finished requests retire and free their memory at once.
- * Walls (u, v, w, T = 0 on every boundary node) and the pressure pin at node 0
- * are applied to every request; the initial state is 0. */
+ * submit and queued.  serve_create allocates one device arena of
+ * hbm_budget_bytes and starts max_active (1..64) worker threads, each with its
+ * own HIP stream.  Workers admit queued requests in arrival order: the head
+ * request is admitted as soon as the arena has a free contiguous block of its
+ * footprint (fe_solve_footprint_bytes plus its design, source and state), and
+ * its whole working set is carved from that block, so requests never compete
+ * for memory while running and no device allocation happens after
+ * serve_create.  Running requests' kernels overlap on the device; each request
+ * runs the same kernels as a standalone newton_solve, so its result does not
+ * depend on what else runs.  A finished request returns its block at once.
+ * A request whose footprint exceeds the arena is refused at submit
+ * (FE_ENOMEM).  Walls (u, v, w, T = 0 on every boundary node) and the pressure
+ * pin at node 0 are applied to every request; the initial state is 0 unless
+ * given (serve_submit_x0). */
 typedef struct fe_server fe_server;
 int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
 /* gamma_host, s_host: host FP64[n_el]; copied.  Returns at once with a ticket. */

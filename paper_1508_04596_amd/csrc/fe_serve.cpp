@@ -1,15 +1,16 @@
 // Continuous-batching solve server.
 //
-// One device arena of hbm_budget_bytes is allocated at creation; every admitted
-// request takes its whole working set (problem handle, solver workspace,
-// multigrid hierarchy, design, source and state) from it through a first-fit
-// sub-allocator, so admission is decided by memory footprint and no device
-// allocation or free (and no implicit device synchronisation) happens while
-// requests run.  max_active worker threads, each with its own HIP stream, take
-// requests from the queue in arrival order as soon as the head request's
-// footprint fits in the unreserved part of the arena; a request therefore
+// One device arena of hbm_budget_bytes is allocated at creation.  An admitted
+// request takes one contiguous block of the arena, sized by its predicted
+// footprint, and its whole working set (problem handle, solver workspace,
+// multigrid hierarchy, design, source and state) is carved from that block in
+// order, so admission is decided by memory footprint, requests cannot fragment
+// each other's memory, and no device allocation or free (and no implicit device
+// synchronisation) happens while requests run.  max_active worker threads, each
+// with its own HIP stream, take requests from the queue in arrival order as
+// soon as the arena has a free block for the head request; a request therefore
 // starts while others are still on the GPU, and the kernels of all running
-// requests overlap on the device.  A finished request releases its memory and
+// requests overlap on the device.  A finished request returns its block and
 // wakes the admission of the next.  Each request runs the same deterministic
 // kernels as a standalone newton_solve, so its result does not depend on what
 // else is running.
@@ -59,9 +60,6 @@ class Arena final : public Allocator {
             if (sz > n) free_[off + n] = sz - n;
             used_[off] = n;
             *p = static_cast<char *>(base_) + off;
-            // debugging aid: fill fresh blocks with NaN bytes so that a read
-            // before the first write shows up as a non-finite result
-            if (poison_) return hipMemset(*p, 0xFF, n);
             return hipSuccess;
         }
         *p = nullptr;
@@ -100,6 +98,14 @@ class Arena final : public Allocator {
     }
     void host_free(void *p) override { std::free(p); }
     size_t size() const { return size_; }
+    bool poison() const { return poison_; }
+    size_t largest_free()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        size_t m = 0;
+        for (const auto &f : free_) m = std::max(m, f.second);
+        return m;
+    }
 
   private:
     void *base_ = nullptr;
@@ -110,6 +116,43 @@ class Arena final : public Allocator {
     std::unordered_map<size_t, size_t> used_;  // offset -> size of live blocks
 };
 
+// One request's block of the arena: allocations are carved from it in order
+// (256-byte aligned); frees are ignored, the block returns to the arena when
+// the request ends.
+class Block final : public Allocator {
+  public:
+    Block(void *base, size_t size, bool poison)
+        : base_(static_cast<char *>(base)), size_(size), poison_(poison)
+    {
+    }
+    hipError_t dev_alloc(void **p, size_t n) override
+    {
+        n = std::max<size_t>(256, (n + 255) / 256 * 256);
+        if (n > size_ - used_) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        *p = base_ + used_;
+        used_ += n;
+        // debugging aid: fill fresh blocks with NaN bytes so that a read
+        // before the first write shows up as a non-finite result
+        if (poison_) return hipMemset(*p, 0xFF, n);
+        return hipSuccess;
+    }
+    void dev_free(void *) override {}
+    hipError_t host_alloc(void **p, size_t n) override
+    {
+        *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void host_free(void *p) override { std::free(p); }
+
+  private:
+    char *base_;
+    size_t size_, used_ = 0;
+    bool poison_;
+};
+
 enum ReqState { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2 };
 
 struct Request {
@@ -118,7 +161,8 @@ struct Request {
     fe_phys phys;
     fe_solve_opts opts;
     std::vector<double> gamma, s, x, x0;  // x0: initial vector (empty: zero)
-    size_t footprint = 0;
+    size_t footprint = 0;  // bytes of the request's block
+    void *block = nullptr;
     ReqState state = Q_WAITING;
     int status = FE_PENDING;
     fe_solve_report rep;
@@ -157,13 +201,16 @@ size_t request_footprint(const fe_grid &g, const fe_solve_opts &o)
     const int64_t ne = (int64_t)g.nx * g.ny * g.nz;
     const int64_t ndof = (int64_t)NF * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
-    return (size_t)(ws + 2 * r(8 * ne) + r(8 * ndof) + 64 * 256);
+    const int64_t b = ws + 2 * r(8 * ne) + r(8 * ndof) + 64 * 256;
+    // margin for the allocations' own rounding
+    return (size_t)r(b + b / 256 + ((int64_t)1 << 20));
 }
 
 int run_request(fe_server *S, Request *r, hipStream_t st)
 {
+    Block mem(r->block, r->footprint, S->arena.poison());
     fe_problem *p = nullptr;
-    int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &S->arena, st, &p);
+    int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &mem, st, &p);
     if (rc) return rc;
     const int64_t ne = p->ne, ndof = p->ndof;
     double *g = nullptr, *s = nullptr, *x = nullptr;
@@ -205,18 +252,33 @@ void worker_main(fe_server *S)
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv.wait(lk, [&] {
                 return S->stop ||
-                       (!S->queue.empty() && S->reserved + S->queue.front()->footprint <= S->budget);
+                       (!S->queue.empty() && S->arena.largest_free() >= S->queue.front()->footprint);
             });
             if (S->stop) break;
             r = S->queue.front();
             S->queue.pop_front();
+            // the arena changes only here and at a request's end, both under S->mu,
+            // so the block found free above is still free
+            if (S->arena.dev_alloc(&r->block, r->footprint) != hipSuccess) {
+                r->status = r->rep.status = FE_ENOMEM;
+                r->error = "serve: no arena block for the request";
+                r->state = Q_DONE;
+                r->t_admit = r->t_done = S->now();
+                S->cv.notify_all();
+                continue;
+            }
             S->reserved += r->footprint;
             r->state = Q_RUNNING;
             r->t_admit = S->now();
         }
         int rc = run_request(S, r, st);
+        // the request's kernels and copies have finished (run_request ends with a
+        // stream synchronisation), so its block can be handed out again
+        (void)hipStreamSynchronize(st);
         {
             std::lock_guard<std::mutex> lk(S->mu);
+            S->arena.dev_free(r->block);
+            r->block = nullptr;
             S->reserved -= r->footprint;
             r->status = rc;
             if (rc < 0) r->rep.status = rc;

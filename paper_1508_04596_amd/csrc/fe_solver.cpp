@@ -363,6 +363,8 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
     const bool mg = opts->precond == FE_PC_MULTIGRID ||
                     (opts->precond == FE_PC_AUTO && mg_num_levels(*grid) >= 2);
     if (mg) b += mg_footprint_bytes(*grid, mixed, mg_asm_nodes(opts->mg_assembled_nodes));
+    // heat-source ramping keeps the initial vector and a scaled source
+    if (opts->ramp_steps > 0) b += r(8 * ndof) + r(8 * ((int64_t)grid->nx * grid->ny * grid->nz));
     return b;
 }
 

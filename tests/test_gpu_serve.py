@@ -147,3 +147,22 @@ def test_warm_start_from_previous_design(fe):
     r0 = np.linalg.norm(oracle.residual(p2, np.zeros(p2.n_dof), mask="solve"))
     for x in (cold[1], warm[1]):
         assert np.linalg.norm(oracle.residual(p2, x, mask="solve")) <= 1e-8 * r0 * 1.0001
+
+
+def test_burst_into_a_tight_budget_all_succeed(fe):
+    """A burst of mixed-size requests into an arena that holds only a few of
+    them at a time: requests of different sizes finish in a different order
+    than they started, so the arena's free space breaks up; every request must
+    still get its memory (it waits for a free block instead of failing)."""
+    reqs = inputs.serving_trace(n_requests=40, rate_per_s=1000.0, seed=4100,
+                                sizes=(16, 24, 32))
+    probs = [inputs.request_problem(r) for r in reqs]
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    big = fe.fe_solve_footprint_bytes(32, 32, 32, 1.0 / 32, opts)
+    with fe.Server(int(2.5 * big), max_active=8) as srv:
+        tickets = [submit(fe, srv, p, opts) for p in probs]
+        res = [srv.wait(t) for t in tickets]
+        errs = [srv.error(t) for t in tickets]
+    failed = [(i, rc, e) for i, ((rc, _, _), e) in enumerate(zip(res, errs)) if rc != fe.FE_OK]
+    print(f"[serve] burst of {len(probs)}: {len(failed)} failed {failed[:3]}")
+    assert not failed
