@@ -91,3 +91,12 @@ def test_footprint_counts_assembled_levels(fe):
         stencil = per * 675 * (4913 + 729)
         je = 8 * 1600 * (16 ** 3 - 4 ** 3)  # element Jacobians sized for the 16^3 level
         assert full - base == pytest.approx(stencil + je, abs=4 * 256)
+
+
+def test_footprint_counts_ramping_buffers(fe):
+    """Heat-source ramping keeps the initial vector (FP64 per DOF) and a scaled
+    source (FP64 per element)."""
+    r = lambda b: (b + 255) // 256 * 256
+    a = fe.fe_solve_footprint_bytes(16, 16, 16, opts=fe.solve_opts())
+    b = fe.fe_solve_footprint_bytes(16, 16, 16, opts=fe.solve_opts(ramp_steps=3))
+    assert b - a == r(8 * 5 * 17 ** 3) + r(8 * 16 ** 3)

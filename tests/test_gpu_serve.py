@@ -166,3 +166,18 @@ def test_burst_into_a_tight_budget_all_succeed(fe):
     failed = [(i, rc, e) for i, ((rc, _, _), e) in enumerate(zip(res, errs)) if rc != fe.FE_OK]
     print(f"[serve] burst of {len(probs)}: {len(failed)} failed {failed[:3]}")
     assert not failed
+
+
+def test_request_with_ramping_fits_its_block(fe):
+    """With heat-source ramping enabled the solve keeps two more buffers; the
+    request's block (sized by the footprint) must hold them."""
+    p = inputs.scaled_config(16, 16, 16, 1e4, seed=13)
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed", ramp_steps=2)
+    fp = fe.fe_solve_footprint_bytes(16, 16, 16, p.h, opts)
+    assert fp > fe.fe_solve_footprint_bytes(16, 16, 16, p.h,
+                                            fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed"))
+    with fe.Server(1 << 30, max_active=2) as srv:
+        t = submit(fe, srv, p, opts)
+        rc, x, rep = srv.wait(t)
+        err = srv.error(t)
+    assert rc == fe.FE_OK, err
