@@ -25,15 +25,18 @@
 
 namespace fe {
 
-hipError_t mg_coarsen_elem(int ncx, int ncy, int ncz, const double *f, double *c, hipStream_t st);
-hipError_t mg_inject_state(int ncx, int ncy, int ncz, const double *f, double *c, hipStream_t st);
-hipError_t mg_inject_mask(int ncx, int ncy, int ncz, const uint8_t *f, uint8_t *c, hipStream_t st);
-template <typename T>
-hipError_t mg_restrict(int ncx, int ncy, int ncz, const T *b, const T *t, const uint8_t *cmask, T *bc,
-                       hipStream_t st);
-template <typename T>
-hipError_t mg_prolong_add(int nfx, int nfy, int nfz, const T *xc, const uint8_t *fmask, T *x,
+hipError_t mg_coarsen_elem(const fe_grid &c, const fe_grid &f, const double *fv, double *cv,
                           hipStream_t st);
+hipError_t mg_inject_state(const fe_grid &c, const fe_grid &f, const double *fv, double *cv,
+                           hipStream_t st);
+hipError_t mg_inject_mask(const fe_grid &c, const fe_grid &f, const uint8_t *fv, uint8_t *cv,
+                          hipStream_t st);
+template <typename T>
+hipError_t mg_restrict(const fe_grid &c, const fe_grid &f, const T *b, const T *t,
+                       const uint8_t *cmask, T *bc, hipStream_t st);
+template <typename T>
+hipError_t mg_prolong_add(const fe_grid &f, const fe_grid &c, const T *xc, const uint8_t *fmask,
+                          T *x, hipStream_t st);
 template <typename T>
 hipError_t mg_smooth(const T *D, const T *b, const T *t, T *x, int64_t nn, T omega, bool transpose,
                      bool accumulate, hipStream_t st);
@@ -93,21 +96,42 @@ void mg_free(Mg *mg)
 
 int64_t mg_asm_nodes(int opt) { return opt < 0 ? MG_ASM_NODES_DEFAULT : (int64_t)opt; }
 
-int mg_num_levels(const fe_grid &g)
+// Next coarser grid: elements of twice the edge, ceil(n / 2) per direction.  An
+// odd fine count leaves the last coarse layer half outside the fine grid; its
+// nodes past the end take their values from the fine boundary nodes.
+static fe_grid coarser(fe_grid g)
 {
-    int nx = g.nx, ny = g.ny, nz = g.nz, n = 1;
+    g.nx = (g.nx + 1) / 2;
+    g.ny = (g.ny + 1) / 2;
+    g.nz = (g.nz + 1) / 2;
+    g.h *= 2.0;
+    return g;
+}
+
+// Levels while the coarse grids stay nested (every count even) or, with pad,
+// also through odd counts; 0 when that gives no usable hierarchy.
+static int count_levels(fe_grid g, bool pad)
+{
+    int n = 1;
     while (true) {
-        const int64_t ndof = (int64_t)NF * (nx + 1) * (ny + 1) * (nz + 1);
+        const int64_t ndof = (int64_t)NF * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
         if (ndof <= MG_TARGET_COARSE_DOF) break;
-        if (nx % 2 || ny % 2 || nz % 2 || nx < 4 || ny < 4 || nz < 4) break;
-        nx /= 2;
-        ny /= 2;
-        nz /= 2;
+        if (g.nx < 4 || g.ny < 4 || g.nz < 4) break;
+        if (!pad && (g.nx % 2 || g.ny % 2 || g.nz % 2)) break;
+        g = coarser(g);
         ++n;
     }
-    const int64_t ndof = (int64_t)NF * (nx + 1) * (ny + 1) * (nz + 1);
-    if (n < 2 || ndof > MG_MAX_COARSE_DOF) return 0;  // no usable hierarchy
+    const int64_t ndof = (int64_t)NF * (g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    if (n < 2 || ndof > MG_MAX_COARSE_DOF) return 0;
     return n;
+}
+
+// Nested levels where they give a hierarchy; otherwise (odd counts before the
+// coarse problem is small enough) padded ones.
+int mg_num_levels(const fe_grid &g)
+{
+    const int n = count_levels(g, false);
+    return n ? n : count_levels(g, true);
 }
 
 static int64_t r256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -126,11 +150,7 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed, int64_t asm_nodes)
     fe_grid g = g0;
     int64_t b = 0, ndof_c = 0, ne_c = 0, ne_je = 0;
     for (int l = 0; l < nl; ++l) {
-        if (l > 0) {
-            g.nx /= 2;
-            g.ny /= 2;
-            g.nz /= 2;
-        }
+        if (l > 0) g = coarser(g);
         const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1), ndof = NF * nn;
         const int64_t ne = (int64_t)g.nx * g.ny * g.nz;
         const int64_t nt = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
@@ -178,12 +198,7 @@ int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
     fe_grid g = p->grid;
     for (int l = 0; l < nl; ++l) {
         MgLevel &L = mg->lev[l];
-        if (l > 0) {
-            g.nx /= 2;
-            g.ny /= 2;
-            g.nz /= 2;
-            g.h *= 2.0;
-        }
+        if (l > 0) g = coarser(g);
         L.grid = g;
         L.geo = make_geo(g, p->phys);
         L.nn = n_nodes(L.geo);
@@ -252,9 +267,9 @@ int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, h
     for (auto &L : mg->lev) L.geo = make_geo(L.grid, p->phys);  // parameters may have changed
     for (size_t l = 1; l < mg->lev.size(); ++l) {
         MgLevel &C = mg->lev[l], &F = mg->lev[l - 1];
-        FE_CHECK_HIP(mg_coarsen_elem(C.grid.nx, C.grid.ny, C.grid.nz, F.gamma, C.gamma, st));
-        FE_CHECK_HIP(mg_coarsen_elem(C.grid.nx, C.grid.ny, C.grid.nz, F.s, C.s, st));
-        FE_CHECK_HIP(mg_inject_mask(C.grid.nx, C.grid.ny, C.grid.nz, F.nmask, C.nmask, st));
+        FE_CHECK_HIP(mg_coarsen_elem(C.grid, F.grid, F.gamma, C.gamma, st));
+        FE_CHECK_HIP(mg_coarsen_elem(C.grid, F.grid, F.s, C.s, st));
+        FE_CHECK_HIP(mg_inject_mask(C.grid, F.grid, F.nmask, C.nmask, st));
     }
     return FE_OK;
 }
@@ -320,7 +335,7 @@ int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st)
     const int nl = (int)mg->lev.size();
     for (int l = 1; l < nl; ++l) {
         MgLevel &C = mg->lev[l], &F = mg->lev[l - 1];
-        FE_CHECK_HIP(mg_inject_state(C.grid.nx, C.grid.ny, C.grid.nz, F.x, C.x, st));
+        FE_CHECK_HIP(mg_inject_state(C.grid, F.grid, F.x, C.x, st));
     }
     // the 135 probing products J p_(colour,field) in FP64 from the coarsest
     // level's element Jacobians (two launches), copied to the host
@@ -478,10 +493,10 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
     MgLevel &C = mg->lev[l + 1];
     FE_CHECK_HIP(op<T>(L, x, t, tr, st));
     T *bc = vecT<T>(C, 0), *xc = vecT<T>(C, 1);
-    FE_CHECK_HIP(mg_restrict<T>(C.grid.nx, C.grid.ny, C.grid.nz, b, t, C.nmask, bc, st));
+    FE_CHECK_HIP(mg_restrict<T>(C.grid, L.grid, b, t, C.nmask, bc, st));
     int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st);
     if (rc) return rc;
-    FE_CHECK_HIP(mg_prolong_add<T>(L.grid.nx, L.grid.ny, L.grid.nz, xc, L.nmask, x, st));
+    FE_CHECK_HIP(mg_prolong_add<T>(L.grid, C.grid, xc, L.nmask, x, st));
     for (int it = 0; it < mg->nu2; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
     return FE_OK;
 }

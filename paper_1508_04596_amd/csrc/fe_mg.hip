@@ -16,9 +16,10 @@ namespace {
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-// coarse element = mean of its 8 children (design and source)
-__global__ void k_coarsen_elem(int ncx, int ncy, int ncz, const double *__restrict__ f,
-                               double *__restrict__ c)
+// coarse element = mean of its children (design and source): 8, or fewer where
+// an odd fine grid leaves the last coarse layer half outside it
+__global__ void k_coarsen_elem(int ncx, int ncy, int ncz, int nfx, int nfy, int nfz,
+                               const double *__restrict__ f, double *__restrict__ c)
 {
     const int64_t nc = (int64_t)ncx * ncy * ncz;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -26,18 +27,24 @@ __global__ void k_coarsen_elem(int ncx, int ncy, int ncz, const double *__restri
     const int I = (int)(e % ncx);
     const int64_t r = e / ncx;
     const int J = (int)(r % ncy), K = (int)(r / ncy);
-    const int nfx = 2 * ncx, nfy = 2 * ncy;
     double s = 0.0;
+    int cnt = 0;
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx)
-                s += f[(2 * I + dx) + (int64_t)nfx * ((2 * J + dy) + (int64_t)nfy * (2 * K + dz))];
-    c[e] = 0.125 * s;
+            for (int dx = 0; dx < 2; ++dx) {
+                const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
+                if (i >= nfx || j >= nfy || k >= nfz) continue;
+                s += f[i + (int64_t)nfx * (j + (int64_t)nfy * k)];
+                ++cnt;
+            }
+    c[e] = s / cnt;  // cnt is 1, 2, 4 or 8: the division is exact scaling
 }
 
 // coarse node values taken from the coincident fine node (NV values per node)
+// (a coarse node past the end of an odd fine grid takes the fine boundary node)
 template <typename Tf, typename Tc, int NV>
-__global__ void k_inject(int ncx, int ncy, int ncz, const Tf *__restrict__ f, Tc *__restrict__ c)
+__global__ void k_inject(int ncx, int ncy, int ncz, int nfx, int nfy, int nfz,
+                         const Tf *__restrict__ f, Tc *__restrict__ c)
 {
     const int64_t nn = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -45,8 +52,8 @@ __global__ void k_inject(int ncx, int ncy, int ncz, const Tf *__restrict__ f, Tc
     const int I = (int)(n % (ncx + 1));
     const int64_t r = n / (ncx + 1);
     const int J = (int)(r % (ncy + 1)), K = (int)(r / (ncy + 1));
-    const int nfx = 2 * ncx + 1, nfy = 2 * ncy + 1;
-    const int64_t fn = (int64_t)(2 * I) + nfx * ((int64_t)(2 * J) + (int64_t)nfy * (2 * K));
+    const int i = min(2 * I, nfx), j = min(2 * J, nfy), k = min(2 * K, nfz);
+    const int64_t fn = i + (int64_t)(nfx + 1) * (j + (int64_t)(nfy + 1) * k);
 #pragma unroll
     for (int q = 0; q < NV; ++q) c[NV * n + q] = (Tc)f[NV * fn + q];
 }
@@ -57,7 +64,8 @@ __global__ void k_inject(int ncx, int ncy, int ncz, const Tf *__restrict__ f, Tc
 // in flight together (a loop that skips them issues one neighbour at a time);
 // the sum keeps the dz, dy, dx order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, const T *__restrict__ b,
+__global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, int nfx, int nfy,
+                                                  int nfz, const T *__restrict__ b,
                                                   const T *__restrict__ t,
                                                   const uint8_t *__restrict__ cmask,
                                                   T *__restrict__ bc)
@@ -70,7 +78,6 @@ __global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, con
     const int I = (int)(n % (ncx + 1));
     const int64_t r = n / (ncx + 1);
     const int J = (int)(r % (ncy + 1)), K = (int)(r / (ncy + 1));
-    const int nfx = 2 * ncx, nfy = 2 * ncy, nfz = 2 * ncz;
     T acc = T(0);
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
@@ -103,7 +110,8 @@ __global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, con
 // per fine DOF.  The up to 8 coarse parents are unrolled (along an even index
 // the parent repeats with its term dropped) so that their loads issue together.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, const T *__restrict__ xc,
+__global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy,
+                                                     const T *__restrict__ xc,
                                                      const uint8_t *__restrict__ fmask, T *__restrict__ x)
 {
     const int64_t nn = (int64_t)(nfx + 1) * (nfy + 1) * (nfz + 1);
@@ -114,7 +122,6 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, 
     const int i = (int)(n % (nfx + 1));
     const int64_t r = n / (nfx + 1);
     const int j = (int)(r % (nfy + 1)), k = (int)(r / (nfy + 1));
-    const int ncx = nfx / 2, ncy = nfy / 2;
     const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
     const int oi = i & 1, oj = j & 1, ok = k & 1;  // a second parent along odd directions
     const T wi = oi ? T(0.5) : T(1), wj = oj ? T(0.5) : T(1), wk = ok ? T(0.5) : T(1);
@@ -461,44 +468,50 @@ __global__ __launch_bounds__(256) void k_smooth(const T *__restrict__ D, const T
 
 }  // namespace
 
-hipError_t mg_coarsen_elem(int ncx, int ncy, int ncz, const double *f, double *c, hipStream_t st)
-{
-    const int64_t n = (int64_t)ncx * ncy * ncz;
-    hipLaunchKernelGGL(k_coarsen_elem, dim3(nblk(n)), dim3(256), 0, st, ncx, ncy, ncz, f, c);
-    return hipGetLastError();
-}
-
-hipError_t mg_inject_state(int ncx, int ncy, int ncz, const double *f, double *c, hipStream_t st)
-{
-    const int64_t n = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    hipLaunchKernelGGL((k_inject<double, double, NF>), dim3(nblk(n)), dim3(256), 0, st, ncx, ncy,
-                       ncz, f, c);
-    return hipGetLastError();
-}
-
-hipError_t mg_inject_mask(int ncx, int ncy, int ncz, const uint8_t *f, uint8_t *c, hipStream_t st)
-{
-    const int64_t n = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    hipLaunchKernelGGL((k_inject<uint8_t, uint8_t, 1>), dim3(nblk(n)), dim3(256), 0, st, ncx, ncy,
-                       ncz, f, c);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t mg_restrict(int ncx, int ncy, int ncz, const T *b, const T *t, const uint8_t *cmask,
-                       T *bc, hipStream_t st)
-{
-    const int64_t n = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(NF * n)), dim3(256), 0, st, ncx, ncy, ncz, b, t, cmask, bc);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t mg_prolong_add(int nfx, int nfy, int nfz, const T *xc, const uint8_t *fmask, T *x,
+hipError_t mg_coarsen_elem(const fe_grid &c, const fe_grid &f, const double *fv, double *cv,
                           hipStream_t st)
 {
-    const int64_t n = (int64_t)(nfx + 1) * (nfy + 1) * (nfz + 1);
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblk(NF * n)), dim3(256), 0, st, nfx, nfy, nfz, xc, fmask, x);
+    const int64_t n = (int64_t)c.nx * c.ny * c.nz;
+    hipLaunchKernelGGL(k_coarsen_elem, dim3(nblk(n)), dim3(256), 0, st, c.nx, c.ny, c.nz, f.nx, f.ny,
+                       f.nz, fv, cv);
+    return hipGetLastError();
+}
+
+hipError_t mg_inject_state(const fe_grid &c, const fe_grid &f, const double *fv, double *cv,
+                           hipStream_t st)
+{
+    const int64_t n = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    hipLaunchKernelGGL((k_inject<double, double, NF>), dim3(nblk(n)), dim3(256), 0, st, c.nx, c.ny,
+                       c.nz, f.nx, f.ny, f.nz, fv, cv);
+    return hipGetLastError();
+}
+
+hipError_t mg_inject_mask(const fe_grid &c, const fe_grid &f, const uint8_t *fv, uint8_t *cv,
+                          hipStream_t st)
+{
+    const int64_t n = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    hipLaunchKernelGGL((k_inject<uint8_t, uint8_t, 1>), dim3(nblk(n)), dim3(256), 0, st, c.nx, c.ny,
+                       c.nz, f.nx, f.ny, f.nz, fv, cv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_restrict(const fe_grid &c, const fe_grid &f, const T *b, const T *t,
+                       const uint8_t *cmask, T *bc, hipStream_t st)
+{
+    const int64_t n = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(NF * n)), dim3(256), 0, st, c.nx, c.ny, c.nz, f.nx,
+                       f.ny, f.nz, b, t, cmask, bc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_prolong_add(const fe_grid &f, const fe_grid &c, const T *xc, const uint8_t *fmask,
+                          T *x, hipStream_t st)
+{
+    const int64_t n = (int64_t)(f.nx + 1) * (f.ny + 1) * (f.nz + 1);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(nblk(NF * n)), dim3(256), 0, st, f.nx, f.ny, f.nz,
+                       c.nx, c.ny, xc, fmask, x);
     return hipGetLastError();
 }
 
@@ -569,9 +582,11 @@ hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, 
 }
 
 #define FE_MG_INST(T)                                                                          \
-    template hipError_t mg_restrict<T>(int, int, int, const T *, const T *, const uint8_t *, T *,  \
+    template hipError_t mg_restrict<T>(const fe_grid &, const fe_grid &, const T *, const T *,      \
+                                       const uint8_t *, T *,                                      \
                                        hipStream_t);                                           \
-    template hipError_t mg_prolong_add<T>(int, int, int, const T *, const uint8_t *, T *,        \
+    template hipError_t mg_prolong_add<T>(const fe_grid &, const fe_grid &, const T *,           \
+                                          const uint8_t *, T *,                                   \
                                           hipStream_t);                                        \
     template hipError_t mg_smooth<T>(const T *, const T *, const T *, T *, int64_t, T, bool, bool, \
                                      hipStream_t);                                             \

@@ -112,6 +112,39 @@ def test_multigrid_newton_on_32_cubed(fe, prec):
     prob.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multigrid_on_odd_grids(fe, prec):
+    """Odd element counts: the coarse grid of ceil(n/2) elements sticks out of
+    the fine one by half a coarse element where n is odd.  The multigrid solve
+    must reach the oracle's backward error, and the adjoint solve through the
+    transposed V-cycle too."""
+    for dims in ((17, 13, 9), (21, 21, 21)):
+        p = inputs.scaled_config(*dims, 1e4, seed=1700 + dims[0])
+        print(f"[mg-odd] {dims} {prec}", flush=True)
+        prob = fe.Problem.from_inputs(p, mask="solve")
+        g, s = dev(p.gamma), dev(p.s)
+        x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+        rep = fe.newton_solve(prob, g, s, x, fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec,
+                                                           precond="multigrid"))
+        xs = host(x)
+        r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+        r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
+        print(f"[mg-odd] newton {rep['newton_its']} lin {rep['lin_its']} levels {rep['mg_levels']} "
+              f"rel {r / r0:.3e}")
+        assert rep["mg_levels"] >= 2
+        assert r <= 1e-8 * r0 * 1.0001
+        assert sum(rep["lin_its"]) <= 40 * rep["newton_its"]
+        c = torch.empty_like(x)
+        fe.fe_compliance(prob, x, s, c)
+        lam, arep = fe.fe_adjoint_solve(prob, x, g, s, c,
+                                        opts=fe.solve_opts(rtol_lin=1e-10, precond="multigrid"))
+        cc = osolve.compliance_gradient_x(p, mask="solve")
+        bwd = np.linalg.norm(oracle.jtvp(p, xs, host(lam), mask="solve") - cc) / np.linalg.norm(cc)
+        print(f"[mg-odd] adjoint its {arep['lin_its_total']} backward error {bwd:.3e}")
+        assert bwd <= 1e-9
+        prob.close()
+
+
 @pytest.mark.parametrize("case", ["C1 8^3", "32^3"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_assembled_levels_match_matrix_free(fe, case, prec):
