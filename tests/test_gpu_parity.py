@@ -86,8 +86,9 @@ def test_inner_product_identity_on_gpu(fe):
     prob.close()
 
 
-def test_fp32_jv_against_oracle(fe):
-    p = inputs.config(1)
+@pytest.mark.parametrize("name,make", CASES[:3] + CASES[4:], ids=[c[0] for c in CASES[:3] + CASES[4:]])
+def test_fp32_jv_against_oracle(fe, name, make):
+    p = make()
     prob = fe.Problem.from_inputs(p, mask="walls")
     x = inputs.random_state(p, 2001)
     g, s = dev(p.gamma), dev(p.s)
@@ -99,7 +100,7 @@ def test_fp32_jv_against_oracle(fe):
         vr = v.astype(np.float32).astype(np.float64)
         ref = oracle.jvp(p, xr, vr)
         err = rel_norm(jv32, ref)
-        print(f"[fp32] C1 jv rel err {err:.3e}")
+        print(f"[fp32] {name} jv rel err {err:.3e}")
         assert err <= 2e-5
         jt32 = host(fe.fe_adjoint_jtvp(prob, dev(x, torch.float32), g, s, dev(v, torch.float32)))
         assert rel_norm(jt32, oracle.jtvp(p, xr, vr)) <= 2e-5
