@@ -10,7 +10,9 @@
 // 27-point block stencil (from element Jacobians, once per Newton step), since
 // the element pass costs the same latency however few tiles a grid has.  The
 // coarsest level is solved directly: its Jacobian is assembled from 135
-// probing products (one per (node colour mod 3^3, field)), factorised by band
+// probing products (one per (node colour mod 3^3, field)), condensed to the
+// DOFs that are not prescribed (prescribed rows are identity rows and
+// prescribed columns are zero, so they drop out exactly), factorised by band
 // LU on the host, and inverted explicitly on the GPU from the factors, so that
 // each V-cycle's coarse solve is one matrix-vector product on the device.
 // V-cycles run in FP64, or in FP32 when the Krylov operator is FP32.
@@ -47,8 +49,8 @@ hipError_t mg_stencil_diag(int64_t nn, const double *S, double *D, hipStream_t s
 hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const double *Uc,
                              const double *Ud, const int *piv, double *X, hipStream_t st);
 template <typename T>
-hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, bool transpose,
-                           hipStream_t st);
+hipError_t mg_coarse_apply(int n, int m, const double *X, const int *fidx, const int *pos, const T *b,
+                           T *x, double *P, bool transpose, hipStream_t st);
 
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
@@ -85,11 +87,14 @@ void mg_free(Mg *mg)
     dfree(p, mg->probe_out);
     dfree(p, mg->dfac);
     dfree(p, mg->dpiv);
+    dfree(p, mg->dmap);
     dfree(p, mg->Xinv);
     dfree(p, mg->cpart);
     hfree(p, mg->hbuf);
     hfree(p, mg->hfac);
     hfree(p, mg->hpiv);
+    hfree(p, mg->hmask);
+    hfree(p, mg->hmap);
     if (mg->probe_ready) (void)hipEventDestroy(mg->probe_ready);
     delete mg;
 }
@@ -174,7 +179,7 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed, int64_t asm_nodes)
     }
     b += r256(8 * 1600 * std::max(ne_c, ne_je)) + r256(8 * 135 * ndof_c);
     const int64_t bw = coarse_band(g);
-    b += r256(8 * ndof_c * (3 * bw + 1)) + r256(4 * ndof_c) + r256(8 * ndof_c * ndof_c);
+    b += r256(8 * ndof_c * (3 * bw + 1)) + r256(4 * ndof_c) + r256(8 * ndof_c) + r256(8 * ndof_c * ndof_c);
     b += r256(8 * ((ndof_c + 63) / 64) * ndof_c);
     return b;
 }
@@ -238,13 +243,17 @@ int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
     if (e == hipSuccess) e = dalloc(p, &mg->probe, sizeof(double) * 1600 * ne_je);  // element Jacobians
     if (e == hipSuccess) e = dalloc(p, &mg->probe_out, sizeof(double) * 135 * C.ndof);
     if (e == hipSuccess) e = halloc(p, &mg->hbuf, sizeof(double) * 135 * C.ndof);
+    // sized for the full matrix: condensing never widens the band
     const int bw = (int)coarse_band(C.grid);
-    mg->kl = mg->ku = bw;
+    mg->bw = bw;
     const size_t nfac = (size_t)C.ndof * (3 * bw + 1);
     if (e == hipSuccess) e = halloc(p, &mg->hfac, sizeof(double) * nfac);
     if (e == hipSuccess) e = halloc(p, &mg->hpiv, sizeof(int) * C.ndof);
+    if (e == hipSuccess) e = halloc(p, &mg->hmask, C.nn);
+    if (e == hipSuccess) e = halloc(p, &mg->hmap, sizeof(int) * 2 * C.ndof);
     if (e == hipSuccess) e = dalloc(p, &mg->dfac, sizeof(double) * nfac);
     if (e == hipSuccess) e = dalloc(p, &mg->dpiv, sizeof(int) * C.ndof);
+    if (e == hipSuccess) e = dalloc(p, &mg->dmap, sizeof(int) * 2 * C.ndof);
     if (e == hipSuccess) e = dalloc(p, &mg->Xinv, sizeof(double) * C.ndof * C.ndof);
     if (e == hipSuccess) e = dalloc(p, &mg->cpart, sizeof(double) * ((C.ndof + 63) / 64) * C.ndof);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&mg->probe_ready, hipEventDisableTiming);
@@ -274,11 +283,91 @@ int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, h
     return FE_OK;
 }
 
-// Band LU with partial pivoting of the dense-stored coarsest matrix; the
-// factors go to the pinned buffers in the layout the device inverse reads.
-static int band_lu(Mg *mg)
+// Index maps of the coarsest level's free DOFs from its node mask (free DOFs
+// keep their lexicographic order), and the half bandwidths of the condensed
+// matrix: the largest index distance between two free DOFs of nodes at most one
+// node apart in each direction.
+static void condense_coarse(Mg *mg, const fe_grid &grid)
 {
     const int64_t n = mg->nc;
+    int *fidx = mg->hmap, *pos = mg->hmap + n;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if ((mg->hmask[i / NF] >> (i % NF)) & 1) {
+            pos[i] = -1;
+        } else {
+            pos[i] = (int)m;
+            fidx[m++] = (int)i;
+        }
+    }
+    mg->nf = m;
+    const int nx = grid.nx, ny = grid.ny, nz = grid.nz;
+    int64_t lo = 0, hi = 0;
+    for (int K = 0; K <= nz; ++K)
+        for (int J = 0; J <= ny; ++J)
+            for (int I = 0; I <= nx; ++I) {
+                const int64_t N = I + (int64_t)(nx + 1) * (J + (int64_t)(ny + 1) * K);
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int i = I + dx, j = J + dy, k = K + dz;
+                            if (i < 0 || j < 0 || k < 0 || i > nx || j > ny || k > nz) continue;
+                            const int64_t M = i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+                            for (int g = 0; g < NF; ++g) {
+                                const int r = pos[NF * N + g];
+                                if (r < 0) continue;
+                                for (int f = 0; f < NF; ++f) {
+                                    const int c = pos[NF * M + f];
+                                    if (c < 0) continue;
+                                    lo = std::max<int64_t>(lo, r - c);
+                                    hi = std::max<int64_t>(hi, c - r);
+                                }
+                            }
+                        }
+            }
+    // at least one sub- and super-diagonal (zero ones where the matrix has none)
+    mg->kl = (int)std::min<int64_t>(std::max<int64_t>(lo, 1), mg->bw);
+    mg->ku = (int)std::min<int64_t>(std::max<int64_t>(hi, 1), mg->bw);
+}
+
+// The coarsest matrix restricted to its free DOFs, dense row-major nf x nf, from
+// the 135 colour-by-field probing products: entry (pos[N g], pos[M f]) is row
+// N g of product (colour(M), f), M within one node of N, both DOFs free.
+static void assemble_free_from_probes(const fe_grid &grid, const double *probe, const int *pos,
+                                      int64_t m, double *A)
+{
+    const int nx = grid.nx, ny = grid.ny, nz = grid.nz;
+    const int64_t n = NF * (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    std::fill(A, A + m * m, 0.0);
+    for (int K = 0; K <= nz; ++K)
+        for (int J = 0; J <= ny; ++J)
+            for (int I = 0; I <= nx; ++I) {
+                const int64_t N = I + (int64_t)(nx + 1) * (J + (int64_t)(ny + 1) * K);
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int i = I + dx, j = J + dy, k = K + dz;
+                            if (i < 0 || j < 0 || k < 0 || i > nx || j > ny || k > nz) continue;
+                            const int64_t M = i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+                            const int col = (i % 3) + 3 * (j % 3) + 9 * (k % 3);
+                            for (int g = 0; g < NF; ++g) {
+                                const int r = pos[NF * N + g];
+                                if (r < 0) continue;
+                                for (int f = 0; f < NF; ++f) {
+                                    const int c = pos[NF * M + f];
+                                    if (c >= 0) A[r * m + c] = probe[(int64_t)(NF * col + f) * n + NF * N + g];
+                                }
+                            }
+                        }
+            }
+}
+
+// Band LU with partial pivoting of the dense-stored condensed coarsest matrix
+// (nf x nf); the factors go to the pinned buffers in the layout the device
+// inverse reads.
+static int band_lu(Mg *mg)
+{
+    const int64_t n = mg->nf;
     const int kl = mg->kl, ku = mg->ku;
     const int64_t w = kl + ku;
     double *A = mg->A.data();
@@ -344,6 +433,7 @@ int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st)
                                        mg->probe_out, st));
     FE_CHECK_HIP(hipMemcpyAsync(mg->hbuf, mg->probe_out, sizeof(double) * 135 * C.ndof,
                                 hipMemcpyDeviceToHost, st));
+    FE_CHECK_HIP(hipMemcpyAsync(mg->hmask, C.nmask, C.nn, hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipEventRecord(mg->probe_ready, st));
     return FE_OK;
 }
@@ -382,16 +472,20 @@ int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, 
     // (the event also orders the previous set-up's copy out of hfac before the
     // factorisation below rewrites it)
     FE_CHECK_HIP(hipEventSynchronize(mg->probe_ready));
-    assemble_from_probes(C.grid, mg->hbuf, mg->A.data());
+    condense_coarse(mg, C.grid);
+    assemble_free_from_probes(C.grid, mg->hbuf, mg->hmap + mg->nc, mg->nf, mg->A.data());
     int rc = band_lu(mg);
     if (rc) return rc;
-    // the factors to the device, then A^{-1} column by column
-    const int64_t n = mg->nc, w = mg->kl + mg->ku;
-    FE_CHECK_HIP(hipMemcpyAsync(mg->dfac, mg->hfac, sizeof(double) * n * (mg->kl + w + 1),
-                                hipMemcpyHostToDevice, st));
-    FE_CHECK_HIP(hipMemcpyAsync(mg->dpiv, mg->hpiv, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    // the factors and index maps to the device, then the inverse column by column
+    const int64_t n = mg->nf, w = mg->kl + mg->ku;
+    if (n > 0) {
+        FE_CHECK_HIP(hipMemcpyAsync(mg->dfac, mg->hfac, sizeof(double) * n * (mg->kl + w + 1),
+                                    hipMemcpyHostToDevice, st));
+        FE_CHECK_HIP(hipMemcpyAsync(mg->dpiv, mg->hpiv, sizeof(int) * n, hipMemcpyHostToDevice, st));
+    }
+    FE_CHECK_HIP(hipMemcpyAsync(mg->dmap, mg->hmap, sizeof(int) * 2 * mg->nc, hipMemcpyHostToDevice, st));
     const double *Lc = mg->dfac, *Uc = Lc + n * mg->kl, *Ud = Uc + n * w;
-    FE_CHECK_HIP(mg_coarse_inverse((int)n, mg->kl, mg->ku, Lc, Uc, Ud, mg->dpiv, mg->Xinv, st));
+    if (n > 0) FE_CHECK_HIP(mg_coarse_inverse((int)n, mg->kl, mg->ku, Lc, Uc, Ud, mg->dpiv, mg->Xinv, st));
     return FE_OK;
 }
 
@@ -475,7 +569,8 @@ static hipError_t smooth_sweep(const MgLevel &L, const T *D, const T *b, T *x, T
 template <typename T>
 static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
 {
-    FE_CHECK_HIP(mg_coarse_apply<T>((int)mg->nc, mg->Xinv, b, x, mg->cpart, tr, st));
+    FE_CHECK_HIP(mg_coarse_apply<T>((int)mg->nc, (int)mg->nf, mg->Xinv, mg->dmap, mg->dmap + mg->nc, b,
+                                    x, mg->cpart, tr, st));
     return FE_OK;
 }
 

@@ -32,18 +32,24 @@ struct Mg {
     bool mixed = false;
     int nu1 = 2, nu2 = 1;  // smoothing sweeps before and after the coarse-grid correction
     double omega = 0.6;
-    // coarsest level: band LU of the dense-stored matrix on the host, explicit
-    // inverse from its factors on the device
-    int64_t nc = 0;
-    int kl = 0, ku = 0;
-    std::vector<double> A;   // dense work matrix of the factorisation
-    double *hfac = nullptr;  // pinned: L by columns [nc kl], U above the diagonal by columns
-                             // [nc (kl + ku)], diagonal of U [nc]
-    int *hpiv = nullptr;     // pinned: pivot rows [nc]
+    // coarsest level: band LU on the host of the dense-stored matrix restricted
+    // to its nf free DOFs, explicit inverse from its factors on the device
+    int64_t nc = 0;          // DOFs of the coarsest level
+    int64_t nf = 0;          // of which not prescribed (set per Newton step from the mask)
+    int bw = 0;              // half bandwidth of the full coarsest matrix (buffer sizing)
+    int kl = 0, ku = 0;      // half bandwidths of the condensed matrix (<= bw)
+    std::vector<double> A;   // dense work matrix of the factorisation, nf x nf
+    double *hfac = nullptr;  // pinned: L by columns [nf kl], U above the diagonal by columns
+                             // [nf (kl + ku)], diagonal of U [nf]
+    int *hpiv = nullptr;     // pinned: pivot rows [nf]
+    uint8_t *hmask = nullptr;  // pinned: node mask of the coarsest level
+    int *hmap = nullptr;     // pinned: free -> full DOF index [nc] (first nf used), then
+                             // full -> free index or -1 for a prescribed DOF [nc]
     double *dfac = nullptr;  // device copy of hfac
     int *dpiv = nullptr;     // device copy of hpiv
-    double *Xinv = nullptr;  // device: A^{-1} by columns, nc x nc
-    double *cpart = nullptr; // device: row partials of the coarse product, ceil(nc / 64) x nc
+    int *dmap = nullptr;     // device copy of hmap
+    double *Xinv = nullptr;  // device: inverse of the condensed matrix by columns, nf x nf
+    double *cpart = nullptr; // device: row partials of the coarse product, ceil(nf / 64) x nf
     hipEvent_t probe_ready = nullptr;  // the probing products have reached the host
     int64_t asm_nodes = 0;        // levels with at most this many nodes are assembled
     double *probe = nullptr;      // element Jacobians (coarsest or assembled level), 1600 per element

@@ -360,10 +360,13 @@ __global__ __launch_bounds__(CI_T) void k_coarse_inverse(int n, int kl, int w, c
 }
 
 // x = A^{-1} b (A^{-T} b when TR) on the coarsest level in two passes, FP64
-// accumulation in a fixed order.  Pass 1: block (rb, cb) multiplies the 64 x 64
-// tile of rows rb and columns cb of the operator by the matching 64 entries of
-// b and writes the 64 row partials to P[cb n + i]; pass 2 adds the partials of
-// each row in chunk order.  X is stored by columns (X[j n + i] = (A^{-1})_ij), so
+// accumulation in a fixed order.  A is the matrix restricted to the n free DOFs
+// (fidx: free -> full index); prescribed DOFs have identity rows and zero
+// columns in the full matrix, so their x is b.  Pass 1: block (rb, cb)
+// multiplies the 64 x 64 tile of rows rb and columns cb of the condensed
+// inverse by the matching 64 free entries of b and writes the 64 row partials
+// to P[cb n + i]; pass 2 adds the partials of each row in chunk order and
+// scatters to the full vector.  X is stored by columns (X[j n + i] = (A^{-1})_ij), so
 // for A^{-1} the tile is read along its rows' index i (wave q takes columns
 // q, q + 4, ...), for A^{-T} along j (wave q takes rows q, q + 4, ...; a row's 64
 // products are summed through LDS).
@@ -371,6 +374,7 @@ constexpr int CA_B = 64;
 
 template <typename T, bool TR>
 __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *__restrict__ X,
+                                                           const int *__restrict__ fidx,
                                                            const T *__restrict__ b, double *__restrict__ P)
 {
     __shared__ double tile[4][CA_B + 1];
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *
         for (int m = 0; m < CA_B / 4; ++m) {
             const int j = j0 + q + 4 * m;
             const int jc = j < n ? j : n - 1;
-            const double t = X[(int64_t)jc * n + ic] * (double)b[jc];
+            const double t = X[(int64_t)jc * n + ic] * (double)b[fidx[jc]];
             acc += j < n ? t : 0.0;
         }
         tile[q][lane] = acc;
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *
     } else {
         const int j = j0 + lane;
         const int jc = j < n ? j : n - 1;
-        const double bj = j < n ? (double)b[jc] : 0.0;
+        const double bj = j < n ? (double)b[fidx[jc]] : 0.0;
 #pragma unroll
         for (int m = 0; m < CA_B / 4; ++m) {
             const int r = q + 4 * m;
@@ -413,15 +417,22 @@ __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *
     }
 }
 
+// Pass 2 over the full vector (nfull DOFs; pos: full -> free index, -1 when prescribed).
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_sum(int n, int nc, const double *__restrict__ P,
-                                                          T *__restrict__ x)
+__global__ __launch_bounds__(256) void k_coarse_apply_sum(int nfull, int n, int nc, const int *__restrict__ pos,
+                                                          const double *__restrict__ P,
+                                                          const T *__restrict__ b, T *__restrict__ x)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= nfull) return;
+    const int r = pos[i];
+    if (r < 0) {
+        x[i] = b[i];
+        return;
+    }
     double acc = 0.0;
 #pragma unroll 8
-    for (int c = 0; c < nc; ++c) acc += P[(int64_t)c * n + i];
+    for (int c = 0; c < nc; ++c) acc += P[(int64_t)c * n + r];
     x[i] = (T)acc;
 }
 
@@ -565,19 +576,21 @@ hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const doub
     return hipGetLastError();
 }
 
-// P: work space of ceil(n / 64) * n doubles
+// nfull DOFs, m of them free; X: m x m; P: work space of ceil(m / 64) * m doubles
 template <typename T>
-hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, bool transpose,
-                           hipStream_t st)
+hipError_t mg_coarse_apply(int nfull, int m, const double *X, const int *fidx, const int *pos, const T *b,
+                           T *x, double *P, bool transpose, hipStream_t st)
 {
-    const int nc = (n + CA_B - 1) / CA_B;
+    const int nc = (m + CA_B - 1) / CA_B;
     const dim3 grid((unsigned)nc, (unsigned)nc);
-    if (transpose)
-        hipLaunchKernelGGL((k_coarse_apply_part<T, true>), grid, dim3(256), 0, st, n, X, b, P);
-    else
-        hipLaunchKernelGGL((k_coarse_apply_part<T, false>), grid, dim3(256), 0, st, n, X, b, P);
-    hipLaunchKernelGGL(k_coarse_apply_sum<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, nc,
-                       (const double *)P, x);
+    if (m > 0) {
+        if (transpose)
+            hipLaunchKernelGGL((k_coarse_apply_part<T, true>), grid, dim3(256), 0, st, m, X, fidx, b, P);
+        else
+            hipLaunchKernelGGL((k_coarse_apply_part<T, false>), grid, dim3(256), 0, st, m, X, fidx, b, P);
+    }
+    hipLaunchKernelGGL(k_coarse_apply_sum<T>, dim3((unsigned)((nfull + 255) / 256)), dim3(256), 0, st, nfull,
+                       m, nc, pos, (const double *)P, b, x);
     return hipGetLastError();
 }
 
@@ -592,8 +605,8 @@ hipError_t mg_coarse_apply(int n, const double *X, const T *b, T *x, double *P, 
                                      hipStream_t);                                             \
     template hipError_t mg_stencil_apply<T>(int, int, int, const T *, const T *, T *, bool,      \
                                             hipStream_t);                                      \
-    template hipError_t mg_coarse_apply<T>(int, const double *, const T *, T *, double *, bool,    \
-                                           hipStream_t);
+    template hipError_t mg_coarse_apply<T>(int, int, const double *, const int *, const int *,    \
+                                           const T *, T *, double *, bool, hipStream_t);
 FE_MG_INST(double)
 FE_MG_INST(float)
 #undef FE_MG_INST

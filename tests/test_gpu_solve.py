@@ -180,9 +180,9 @@ def test_assembled_levels_match_matrix_free(fe, case, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_multigrid_wide_band_coarsest_level(fe, prec):
-    """16x16x4 slab: two levels, the coarsest (8x8x2, 1215 DOF) has half bandwidth
-    459, beyond the register-set size of the device inverse (its column-streaming
-    path); the fine level itself is assembled.  The solve must reach the oracle's
+    """16x16x4 slab: two levels, the coarsest (8x8x2, 1215 DOF, 438 of them free)
+    has a condensed half bandwidth of 287, beyond the register-set size of the
+    device inverse (its column-streaming path); the fine level itself is assembled.  The solve must reach the oracle's
     backward-error bar and match the oracle's Newton solution, in few iterations
     (an exact coarse solve on a two-level hierarchy)."""
     p = inputs.scaled_config(16, 16, 4, 2e3, seed=404)
