@@ -158,8 +158,12 @@ typedef struct {
  * geometric multigrid V-cycle (Sec. "Solving the linear systems") whose levels
  * rediscretise the operator on grids with half the elements per direction,
  * with damped block-Jacobi smoothing and a direct solve on the coarsest level.
- * FE_PC_AUTO takes multigrid when every element count halves evenly down to a
- * coarsest level of at most 2400 DOF, else block-Jacobi. */
+ * FE_PC_AUTO (the default) takes multigrid whenever the grid has at least two
+ * levels: element counts are halved while they stay even (or, where an odd
+ * count stops that early, rounded up with the coarse grid overhanging by half
+ * an element) until the coarse problem is small enough for the direct solve;
+ * grids with fewer than 4 elements along a direction before that (thin slabs)
+ * get block-Jacobi. */
 enum { FE_PC_AUTO = 0, FE_PC_BJACOBI = 1, FE_PC_MULTIGRID = 2 };
 
 typedef struct {
@@ -179,8 +183,10 @@ void fe_solve_opts_default(fe_solve_opts *opts);
 
 /* Damped Newton (Sec. "Solving the non-linear system"): each step solves
  * J delta = -R with right-preconditioned flexible GMRES (Sec. "Solving the
- * linear systems") using a nodal 5x5 block-Jacobi preconditioner, Gram-Schmidt,
- * Hessenberg and Givens in FP64; then the damping factor is the minimiser of a
+ * linear systems") with the preconditioner opts->precond selects (FE_PC_AUTO by
+ * default: the multigrid V-cycle, or nodal 5x5 block-Jacobi where the grid gives
+ * no hierarchy), Gram-Schmidt, Hessenberg and Givens in FP64; then the damping
+ * factor is the minimiser of a
  * quadratic fitted to |R|^2 at 0, 1/2 and 1 times the step.  x_inout: device
  * FP64[n_dof], the initial vector on entry (its prescribed entries hold the
  * Dirichlet values), the solution on exit.  With krylov_op_prec = FE_FP32 the
@@ -190,9 +196,11 @@ void fe_solve_opts_default(fe_solve_opts *opts);
 int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, double *x_inout,
                  const fe_solve_opts *opts, fe_solve_report *report, hipStream_t stream);
 
-/* Adjoint solve J(x)^T lambda = rhs with FGMRES on fe_adjoint_jtvp's operator
- * and the transposed block-Jacobi preconditioner; rtol_lin of opts applies.
- * All arrays device FP64. */
+/* Adjoint solve J(x)^T lambda = rhs with FGMRES on fe_adjoint_jtvp's operator,
+ * preconditioned by the transpose of the state solve's preconditioner: with
+ * FE_PC_AUTO (default) the transposed multigrid V-cycle (D^T smoothing, J^T on
+ * every level, transposed coarse solve), else transposed block-Jacobi; rtol_lin
+ * of opts applies.  All arrays device FP64. */
 int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
                      const double *rhs, double *lambda, const fe_solve_opts *opts,
                      fe_solve_report *report, hipStream_t stream);

@@ -17,4 +17,4 @@ Contents:
 """
 from .core import (build_oracle, residual, jvp, jtvp, dR_dgamma, element_jacobians,  # noqa: F401
                    element_residual, element_dR_dgamma, material, taus, gauss_points,
-                   num_threads, set_num_threads)
+                   num_threads, set_num_threads, set_frozen_tau)

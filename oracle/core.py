@@ -175,6 +175,15 @@ def set_num_threads(n: int) -> None:
     L.or_set_num_threads(int(n))
 
 
+def set_frozen_tau(on: bool) -> None:
+    """Test-only: drop the variations of tau and tauT from every derivative
+    (the comparison at the end of the appendix "Stabilisation parameters")."""
+    L = _load()
+    L.or_set_frozen_tau.argtypes = [ctypes.c_int]
+    L.or_set_frozen_tau.restype = None
+    L.or_set_frozen_tau(1 if on else 0)
+
+
 def _mask(p, mask):
     if mask is None:
         return None

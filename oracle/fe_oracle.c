@@ -47,6 +47,15 @@
 #define NEN 8
 #define NED (NEN * NF)
 
+/* Test-only switch for the comparison at the end of the appendix
+ * "Stabilisation parameters": when set, tau and tauT are treated as constants
+ * in every derivative (J v, the element Jacobians, J^T w, lambda^T dR/dgamma),
+ * i.e. their variations with the element velocity and with the design are
+ * dropped.  The residual is unaffected.  Off by default; only a test that
+ * shows the loss of finite-difference agreement of the design sensitivities
+ * turns it on. */
+static int g_frozen_tau = 0;
+
 typedef struct {
     double h, Pr, Gr, Ck, qf, amax, qa, eg[3];
     double B; /* buoyancy coefficient Gr * Pr^2 (Eq. BoussDimless-a) */
@@ -219,6 +228,7 @@ static void elem_jv(const ctx_t *c, const double xe[NEN][NF], const double ve[NE
     double h2 = c->h * c->h;
     double dtau = -tau * tau * tau * udu / (16.0 * h2);
     double dtauT = -tauT * tauT * tauT * udu / (16.0 * h2);
+    if (g_frozen_tau) dtau = dtauT = 0.0;
     memset(dRe, 0, sizeof(double) * NED);
     for (int g = 0; g < 8; ++g) {
         fields_t F, D;
@@ -303,6 +313,7 @@ static void elem_dRdgamma(const ctx_t *c, const double xe[NEN][NF], double gam, 
     double h = c->h, h4 = h * h * h * h;
     double dtau_da = -tau * tau * tau * alpha;
     double dtauT_dK = -tauT * tauT * tauT * 16.0 * K / h4;
+    if (g_frozen_tau) dtau_da = dtauT_dK = 0.0;
     memset(dRe, 0, sizeof(double) * NED);
     for (int g = 0; g < 8; ++g) {
         fields_t F;
@@ -573,6 +584,8 @@ int or_gauss_points(int nx, int ny, int nz, double h, double *xg)
             }
     return 0;
 }
+
+void or_set_frozen_tau(int on) { g_frozen_tau = on ? 1 : 0; }
 
 void or_set_num_threads(int n)
 {

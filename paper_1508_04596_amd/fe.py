@@ -174,15 +174,20 @@ def _check(rc: int, what: str, ok=(FE_OK,)) -> int:
     return rc
 
 
-def _ptr(t: Optional[torch.Tensor], dtype=None):
+def _ptr(t: Optional[torch.Tensor], dtype=None, n: Optional[int] = None, what: str = "array"):
+    """Device pointer of ``t`` after checking device, layout, dtype and (if ``n``
+    is given) the number of entries: the kernels index up to the grid's sizes,
+    so a short tensor is rejected here, before any launch."""
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("expected a GPU tensor")
+        raise ValueError(f"{what}: expected a GPU tensor")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError(f"{what}: expected a contiguous tensor")
     if dtype is not None and t.dtype != dtype:
-        raise ValueError(f"expected {dtype}, got {t.dtype}")
+        raise ValueError(f"{what}: expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: expected {n} entries, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -225,7 +230,8 @@ class Problem:
         self.phys = phys
         handle = ctypes.c_void_p()
         _check(lib().fe_problem_create(ctypes.byref(g), ctypes.byref(phys),
-                                       _ptr(mask, torch.uint8), ctypes.byref(handle)),
+                                       _ptr(mask, torch.uint8, self.n_dof, "mask"),
+                                       ctypes.byref(handle)),
                "fe_problem_create")
         self.handle = handle
 
@@ -271,8 +277,10 @@ def _prec_of(t: torch.Tensor) -> int:
 
 def fe_residual(prob: Problem, x, gamma, s, out=None, stream=None):
     out = torch.empty_like(x) if out is None else out
-    _check(lib().fe_residual(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
-                             _ptr(s, torch.float64), _ptr(out, torch.float64), _stream(stream)),
+    nd, ne = prob.n_dof, prob.n_el
+    _check(lib().fe_residual(prob.handle, _ptr(x, torch.float64, nd, "x"),
+                             _ptr(gamma, torch.float64, ne, "gamma"), _ptr(s, torch.float64, ne, "s"),
+                             _ptr(out, torch.float64, nd, "out"), _stream(stream)),
            "fe_residual")
     return out
 
@@ -280,8 +288,10 @@ def fe_residual(prob: Problem, x, gamma, s, out=None, stream=None):
 def fe_jvp(prob: Problem, x, gamma, s, v, out=None, stream=None):
     prec = _prec_of(x)
     out = torch.empty_like(v) if out is None else out
-    _check(lib().fe_jvp(prob.handle, prec, _ptr(x, x.dtype), _ptr(gamma, torch.float64),
-                        _ptr(s, torch.float64), _ptr(v, x.dtype), _ptr(out, x.dtype),
+    nd, ne = prob.n_dof, prob.n_el
+    _check(lib().fe_jvp(prob.handle, prec, _ptr(x, x.dtype, nd, "x"),
+                        _ptr(gamma, torch.float64, ne, "gamma"), _ptr(s, torch.float64, ne, "s"),
+                        _ptr(v, x.dtype, nd, "v"), _ptr(out, x.dtype, nd, "out"),
                         _stream(stream)), "fe_jvp")
     return out
 
@@ -291,8 +301,10 @@ def fe_jacobian_dense(prob: Problem, x, gamma, s, stream=None):
     import numpy as np
     n = int(lib().fe_problem_ndof(prob.handle))
     J = np.empty((n, n), dtype=np.float64)
-    _check(lib().fe_jacobian_dense(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
-                                   _ptr(s, torch.float64), J.ctypes.data_as(ctypes.c_void_p),
+    _check(lib().fe_jacobian_dense(prob.handle, _ptr(x, torch.float64, n, "x"),
+                                   _ptr(gamma, torch.float64, prob.n_el, "gamma"),
+                                   _ptr(s, torch.float64, prob.n_el, "s"),
+                                   J.ctypes.data_as(ctypes.c_void_p),
                                    _stream(stream)), "fe_jacobian_dense")
     return J
 
@@ -313,32 +325,40 @@ def fe_kernel_timer_read(prob: Problem):
 def fe_adjoint_jtvp(prob: Problem, x, gamma, s, w, out=None, stream=None):
     prec = _prec_of(x)
     out = torch.empty_like(w) if out is None else out
-    _check(lib().fe_adjoint_jtvp(prob.handle, prec, _ptr(x, x.dtype), _ptr(gamma, torch.float64),
-                                 _ptr(s, torch.float64), _ptr(w, x.dtype), _ptr(out, x.dtype),
-                                 _stream(stream)), "fe_adjoint_jtvp")
+    nd, ne = prob.n_dof, prob.n_el
+    _check(lib().fe_adjoint_jtvp(prob.handle, prec, _ptr(x, x.dtype, nd, "x"),
+                                 _ptr(gamma, torch.float64, ne, "gamma"),
+                                 _ptr(s, torch.float64, ne, "s"), _ptr(w, x.dtype, nd, "w"),
+                                 _ptr(out, x.dtype, nd, "out"), _stream(stream)), "fe_adjoint_jtvp")
     return out
 
 
 def fe_dR_dgamma(prob: Problem, x, gamma, s, lam, out=None, stream=None):
     out = torch.empty_like(gamma) if out is None else out
-    _check(lib().fe_dR_dgamma(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
-                              _ptr(s, torch.float64), _ptr(lam, torch.float64),
-                              _ptr(out, torch.float64), _stream(stream)), "fe_dR_dgamma")
+    nd, ne = prob.n_dof, prob.n_el
+    _check(lib().fe_dR_dgamma(prob.handle, _ptr(x, torch.float64, nd, "x"),
+                              _ptr(gamma, torch.float64, ne, "gamma"), _ptr(s, torch.float64, ne, "s"),
+                              _ptr(lam, torch.float64, nd, "lambda"),
+                              _ptr(out, torch.float64, ne, "out"), _stream(stream)), "fe_dR_dgamma")
     return out
 
 
 def fe_compliance(prob: Problem, x, s, dfdx=None, stream=None):
     f = ctypes.c_double()
-    _check(lib().fe_compliance(prob.handle, _ptr(x, torch.float64), _ptr(s, torch.float64),
-                               ctypes.byref(f), _ptr(dfdx, torch.float64), _stream(stream)),
+    _check(lib().fe_compliance(prob.handle, _ptr(x, torch.float64, prob.n_dof, "x"),
+                               _ptr(s, torch.float64, prob.n_el, "s"), ctypes.byref(f),
+                               _ptr(dfdx, torch.float64, prob.n_dof, "dfdx"), _stream(stream)),
            "fe_compliance")
     return f.value
 
 
 def fe_block_diagonal(prob: Problem, x, gamma, s, out=None, stream=None):
     out = torch.empty(25 * prob.n_nodes, dtype=torch.float64, device=x.device) if out is None else out
-    _check(lib().fe_block_diagonal(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
-                                   _ptr(s, torch.float64), _ptr(out, torch.float64),
+    ne = prob.n_el
+    _check(lib().fe_block_diagonal(prob.handle, _ptr(x, torch.float64, prob.n_dof, "x"),
+                                   _ptr(gamma, torch.float64, ne, "gamma"),
+                                   _ptr(s, torch.float64, ne, "s"),
+                                   _ptr(out, torch.float64, 25 * prob.n_nodes, "out"),
                                    _stream(stream)), "fe_block_diagonal")
     return out
 
@@ -347,9 +367,10 @@ def newton_solve(prob: Problem, gamma, s, x, opts: Optional[FeSolveOpts] = None,
                  allow_not_converged=False) -> dict:
     rep = FeSolveReport()
     o = solve_opts() if opts is None else opts
-    rc = lib().newton_solve(prob.handle, _ptr(gamma, torch.float64), _ptr(s, torch.float64),
-                            _ptr(x, torch.float64), ctypes.byref(o), ctypes.byref(rep),
-                            _stream(stream))
+    rc = lib().newton_solve(prob.handle, _ptr(gamma, torch.float64, prob.n_el, "gamma"),
+                            _ptr(s, torch.float64, prob.n_el, "s"),
+                            _ptr(x, torch.float64, prob.n_dof, "x"), ctypes.byref(o),
+                            ctypes.byref(rep), _stream(stream))
     _check(rc, "newton_solve", ok=(FE_OK, FE_NOT_CONVERGED) if allow_not_converged else (FE_OK,))
     return rep.as_dict()
 
@@ -359,10 +380,12 @@ def fe_adjoint_solve(prob: Problem, x, gamma, s, rhs, lam=None, opts: Optional[F
     lam = torch.empty_like(rhs) if lam is None else lam
     rep = FeSolveReport()
     o = solve_opts() if opts is None else opts
-    rc = lib().fe_adjoint_solve(prob.handle, _ptr(x, torch.float64), _ptr(gamma, torch.float64),
-                                _ptr(s, torch.float64), _ptr(rhs, torch.float64),
-                                _ptr(lam, torch.float64), ctypes.byref(o), ctypes.byref(rep),
-                                _stream(stream))
+    nd, ne = prob.n_dof, prob.n_el
+    rc = lib().fe_adjoint_solve(prob.handle, _ptr(x, torch.float64, nd, "x"),
+                                _ptr(gamma, torch.float64, ne, "gamma"),
+                                _ptr(s, torch.float64, ne, "s"), _ptr(rhs, torch.float64, nd, "rhs"),
+                                _ptr(lam, torch.float64, nd, "lambda"), ctypes.byref(o),
+                                ctypes.byref(rep), _stream(stream))
     _check(rc, "fe_adjoint_solve", ok=(FE_OK, FE_NOT_CONVERGED) if allow_not_converged else (FE_OK,))
     return lam, rep.as_dict()
 
@@ -477,6 +500,7 @@ class Filter:
     """PDE density filter on an element grid (radius R in length units)."""
 
     def __init__(self, nx, ny, nz, h, radius):
+        self.handle = None
         self.n_el = nx * ny * nz
         h_ = ctypes.c_void_p()
         _check(lib().fe_filter_create(ctypes.byref(FeGrid(nx, ny, nz, h)), radius, ctypes.byref(h_)),
@@ -485,14 +509,16 @@ class Filter:
 
     def apply(self, x, out=None, stream=None):
         out = torch.empty_like(x) if out is None else out
-        _check(lib().fe_filter_apply(self.handle, _ptr(x, torch.float64), _ptr(out, torch.float64),
-                                     _stream(stream)), "fe_filter_apply")
+        _check(lib().fe_filter_apply(self.handle, _ptr(x, torch.float64, self.n_el, "in"),
+                                     _ptr(out, torch.float64, self.n_el, "out"), _stream(stream)),
+               "fe_filter_apply")
         return out
 
     def apply_transpose(self, x, out=None, stream=None):
         out = torch.empty_like(x) if out is None else out
-        _check(lib().fe_filter_apply_transpose(self.handle, _ptr(x, torch.float64),
-                                               _ptr(out, torch.float64), _stream(stream)),
+        _check(lib().fe_filter_apply_transpose(self.handle, _ptr(x, torch.float64, self.n_el, "in"),
+                                               _ptr(out, torch.float64, self.n_el, "out"),
+                                               _stream(stream)),
                "fe_filter_apply_transpose")
         return out
 
@@ -516,14 +542,18 @@ class MMA:
     """Method of moving asymptotes, one constraint, on the device."""
 
     def __init__(self, n, xmin=0.0, xmax=1.0, move=0.2):
+        self.handle = None
+        self.n = int(n)
         h_ = ctypes.c_void_p()
         _check(lib().fe_mma_create(n, xmin, xmax, move, ctypes.byref(h_)), "fe_mma_create")
         self.handle = h_
 
     def update(self, x, df0, f1, df1, stream=None) -> float:
         lam = ctypes.c_double()
-        _check(lib().fe_mma_update(self.handle, _ptr(x, torch.float64), _ptr(df0, torch.float64),
-                                   float(f1), _ptr(df1, torch.float64), ctypes.byref(lam),
+        n = self.n
+        _check(lib().fe_mma_update(self.handle, _ptr(x, torch.float64, n, "x"),
+                                   _ptr(df0, torch.float64, n, "df0"), float(f1),
+                                   _ptr(df1, torch.float64, n, "df1"), ctypes.byref(lam),
                                    _stream(stream)), "fe_mma_update")
         return lam.value
 
@@ -563,11 +593,14 @@ class TopOpt:
     of length n_el, kept alive by this object."""
 
     def __init__(self, prob: Problem, design_mask, gamma_fixed, s, opts: Optional[FeTopoptOpts] = None):
+        self.handle = None
         self.prob = prob
         self._keep = (design_mask, gamma_fixed, s)
         h_ = ctypes.c_void_p()
-        _check(lib().fe_topopt_create(prob.handle, _ptr(design_mask, torch.uint8),
-                                      _ptr(gamma_fixed, torch.float64), _ptr(s, torch.float64),
+        ne = prob.n_el
+        _check(lib().fe_topopt_create(prob.handle, _ptr(design_mask, torch.uint8, ne, "design_mask"),
+                                      _ptr(gamma_fixed, torch.float64, ne, "gamma_fixed"),
+                                      _ptr(s, torch.float64, ne, "s"),
                                       ctypes.byref(opts) if opts is not None else None,
                                       ctypes.byref(h_)), "fe_topopt_create")
         self.handle = h_
@@ -577,22 +610,27 @@ class TopOpt:
         df = torch.zeros_like(rho) if grads else None
         dg = torch.zeros_like(rho) if grads else None
         rec = FeTopoptRecord()
-        _check(lib().fe_topopt_evaluate(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
-                                        ctypes.byref(f), ctypes.byref(g), _ptr(df, torch.float64),
-                                        _ptr(dg, torch.float64), ctypes.byref(rec), _stream(stream)),
+        nd, ne = self.prob.n_dof, self.prob.n_el
+        _check(lib().fe_topopt_evaluate(self.handle, _ptr(rho, torch.float64, ne, "rho"),
+                                        _ptr(x, torch.float64, nd, "x"), ctypes.byref(f),
+                                        ctypes.byref(g), _ptr(df, torch.float64, ne, "dfdrho"),
+                                        _ptr(dg, torch.float64, ne, "dgdrho"), ctypes.byref(rec),
+                                        _stream(stream)),
                "fe_topopt_evaluate")
         return f.value, g.value, df, dg, rec.as_dict()
 
     def step(self, rho, x, stream=None) -> dict:
         rec = FeTopoptRecord()
-        _check(lib().fe_topopt_step(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
+        _check(lib().fe_topopt_step(self.handle, _ptr(rho, torch.float64, self.prob.n_el, "rho"),
+                                    _ptr(x, torch.float64, self.prob.n_dof, "x"),
                                     ctypes.byref(rec), _stream(stream)), "fe_topopt_step")
         return rec.as_dict()
 
     def run(self, rho, x, cap=10000, stream=None):
         hist = (FeTopoptRecord * cap)()
         n = ctypes.c_int()
-        _check(lib().fe_topopt_run(self.handle, _ptr(rho, torch.float64), _ptr(x, torch.float64),
+        _check(lib().fe_topopt_run(self.handle, _ptr(rho, torch.float64, self.prob.n_el, "rho"),
+                                   _ptr(x, torch.float64, self.prob.n_dof, "x"),
                                    hist, cap, ctypes.byref(n), _stream(stream)), "fe_topopt_run")
         return [hist[i].as_dict() for i in range(min(n.value, cap))]
 

@@ -1,0 +1,52 @@
+"""The binding rejects tensors of the wrong length before any kernel launch.
+
+The kernels index x, v, w, out, lambda and rhs up to n_dof and gamma and s up
+to n_el; a short tensor (for instance a design-domain-only gamma) must raise a
+ValueError in the binding, with nothing enqueued on the stream."""
+import pytest
+import torch
+
+from paper_1508_04596_amd import autograd, fe, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    p = inputs.tiny_problem(6, 5, 4, Gr=1e3, seed=3)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    dev = torch.device("cuda:0")
+    d = lambda a: torch.from_numpy(a).to(dev)
+    yield p, prob, d(p.gamma), d(p.s), dev
+    prob.close()
+
+
+def test_short_tensors_raise_before_launch(setup):
+    p, prob, g, s, dev = setup
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device=dev)
+    short = torch.zeros(p.n_dof - 5, dtype=torch.float64, device=dev)
+    g_short = g[: p.n_el - 1].contiguous()
+    torch.cuda.synchronize()
+    cases = [
+        lambda: fe.fe_residual(prob, short, g, s),
+        lambda: fe.fe_residual(prob, x, g_short, s),
+        lambda: fe.fe_residual(prob, x, g, s, out=short),
+        lambda: fe.fe_jvp(prob, x, g, s, short),
+        lambda: fe.fe_jvp(prob, x, g, g_short, x),
+        lambda: fe.fe_adjoint_jtvp(prob, x, g, s, short),
+        lambda: fe.fe_dR_dgamma(prob, x, g, s, short),
+        lambda: fe.fe_dR_dgamma(prob, x, g, s, x, out=g_short.clone()),
+        lambda: fe.fe_compliance(prob, short, s),
+        lambda: fe.fe_block_diagonal(prob, x, g_short, s),
+        lambda: fe.newton_solve(prob, g_short, s, x.clone()),
+        lambda: fe.newton_solve(prob, g, s, short),
+        lambda: fe.fe_adjoint_solve(prob, x, g, s, short),
+        lambda: autograd.state_solve(g_short, prob, s),
+    ]
+    for i, call in enumerate(cases):
+        with pytest.raises(ValueError):
+            call()
+    torch.cuda.synchronize()
+    # the unmodified call still works after the rejected ones
+    r = fe.fe_residual(prob, x, g, s)
+    assert torch.isfinite(r).all()

@@ -3,12 +3,15 @@
 A smooth divergence-free velocity that vanishes with its gradient on the walls,
 a smooth pressure and temperature are inserted into Eqs. BoussDimless-a..c; the
 resulting forcing enters the oracle's Galerkin and stabilised residuals.  The
-discrete solution on n^3 grids must converge to the exact fields at second order
-in the L2 norm for velocity and temperature (trilinear elements).  Pressure is
-reported only.
+discrete solution on n^3 grids (n = 8, 16, 24) must converge to the exact fields
+at second order in the L2 norm for velocity and temperature (trilinear
+elements), on each refinement.  Pressure is reported only.
 """
+import os
+
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 import sympy as sy
 
 import oracle
@@ -82,10 +85,88 @@ def _l2_errors(p, x, uex, pex, Tex):
     return {k: float(np.sqrt(v)) for k, v in errs.items()}
 
 
+def nested_dissection_dofs(nx, ny, nz, leaf=4):
+    """DOF order of the structured node grid by recursive bisection along the
+    longest side, each separator plane numbered after its two halves (the
+    standard fill-reducing order for sparse LU on 3-D grids).  Only the order of
+    the unknowns changes, never the system."""
+    blocks = []
+
+    def box(lo, hi):
+        I, J, K = np.meshgrid(*(np.arange(lo[d], hi[d]) for d in range(3)), indexing="ij")
+        return (I + (nx + 1) * (J + (ny + 1) * K)).ravel()
+
+    def rec(lo, hi):
+        ext = [hi[d] - lo[d] for d in range(3)]
+        if max(ext) <= leaf:
+            blocks.append(box(lo, hi))
+            return
+        d = int(np.argmax(ext))
+        mid = (lo[d] + hi[d]) // 2
+        a_hi, b_lo, s_lo, s_hi = list(hi), list(lo), list(lo), list(hi)
+        a_hi[d], b_lo[d], s_lo[d], s_hi[d] = mid, mid + 1, mid, mid + 1
+        rec(lo, a_hi)
+        rec(b_lo, hi)
+        blocks.append(box(s_lo, s_hi))
+
+    rec([0, 0, 0], [nx + 1, ny + 1, nz + 1])
+    nodes = np.concatenate(blocks)
+    assert np.array_equal(np.sort(nodes), np.arange((nx + 1) * (ny + 1) * (nz + 1)))
+    return (5 * nodes[:, None] + np.arange(5)[None, :]).ravel()
+
+
+def discrete_solution(p, forc, x0, rtol=1e-12, max_it=40):
+    """R(x) = 0 of the oracle's residual with the manufactured forcing, by
+    simplified Newton: the oracle's assembled Jacobian at x0 is factored once
+    (sparse LU in nested-dissection order) and reused; the iteration stops on
+    the oracle's own residual norm, so the solver only has to reach the
+    discrete solution, which the residual test defines."""
+    m = p.mask_solve.astype(bool)
+    f = forc.reshape(-1)
+    x = x0.copy()
+    R = oracle.residual(p, x, mask=m.astype(np.uint8), forcing=f)
+    r0 = np.linalg.norm(R)
+    perm = nested_dissection_dofs(p.nx, p.ny, p.nz)
+    J = osolve.assemble(p, x, mask=m, forcing=f)
+    lu = spla.splu(J[perm][:, perm].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.01,
+                   options=dict(SymmetricMode=True))
+    for _ in range(max_it):
+        if np.linalg.norm(R) <= rtol * r0:
+            break
+        d = np.empty(p.n_dof)
+        d[perm] = lu.solve(-R[perm])
+        x = x + d
+        R = oracle.residual(p, x, mask=m.astype(np.uint8), forcing=f)
+    return x, float(np.linalg.norm(R) / r0)
+
+
+def _interpolant(p, uex, pex, Tex):
+    """Nodal values of the exact fields (prescribed DOFs at their wall value 0)."""
+    n = np.arange
+    I, J, K = np.meshgrid(n(p.nx + 1), n(p.ny + 1), n(p.nz + 1), indexing="ij")
+    X = np.stack([I, J, K], -1).transpose(2, 1, 0, 3).reshape(-1, 3) * p.h
+    x = np.empty((p.n_nodes, 5))
+    for f in range(3):
+        x[:, f] = uex[f](X[:, 0], X[:, 1], X[:, 2])
+    x[:, 3] = pex(X[:, 0], X[:, 1], X[:, 2])
+    x[:, 4] = Tex(X[:, 0], X[:, 1], X[:, 2])
+    x = x.reshape(-1)
+    m = p.mask_solve.astype(bool)
+    x[m] = 0.0
+    x[3] = pex(0.0, 0.0, 0.0)  # pinned pressure value
+    return x
+
+
+# 8, 16, 24 elements per side: 24^3 (78,125 DOF) is factored in about 40 s with
+# about 2 GB of LU factors; 32^3 takes about 3 minutes and 5 GB and is run on
+# request (FE_MMS_MAX=32).
+SIZES = (8, 16, 24) + ((32,) if os.environ.get("FE_MMS_MAX") == "32" else ())
+
+
 def test_manufactured_solution_converges_at_second_order():
     uex, pex, Tex, fM, fT = _exact()
     errs = []
-    for n in (4, 8, 16):
+    for n in SIZES:
         p = _problem(n)
         xg = oracle.gauss_points(p)  # [n_el, 8, 3]
         forc = np.empty((p.n_el, 8, 4))
@@ -93,13 +174,14 @@ def test_manufactured_solution_converges_at_second_order():
         for i in range(3):
             forc[..., i] = fM[i](X, Y, Z)
         forc[..., 3] = fT(X, Y, Z)
-        x0 = np.zeros(p.n_dof)
-        x0[3] = pex(0.0, 0.0, 0.0)  # pinned pressure value
-        x, it, rr = osolve.newton(p, x0=x0, rtol=1e-12, forcing=forc.reshape(-1))
+        x, rr = discrete_solution(p, forc, _interpolant(p, uex, pex, Tex))
         assert rr <= 1e-12
         errs.append(_l2_errors(p, x, uex, pex, Tex))
-    ou = [np.log2(errs[k]["u"] / errs[k + 1]["u"]) for k in range(2)]
-    oT = [np.log2(errs[k]["T"] / errs[k + 1]["T"]) for k in range(2)]
-    print("L2 errors", errs, "orders u", ou, "T", oT)
-    assert ou[-1] > 1.8 and oT[-1] > 1.8
-    assert errs[-1]["u"] < errs[0]["u"] and errs[-1]["T"] < errs[0]["T"]
+    ratio = [np.log(SIZES[k + 1] / SIZES[k]) for k in range(len(SIZES) - 1)]
+    ou = [np.log(errs[k]["u"] / errs[k + 1]["u"]) / ratio[k] for k in range(len(ratio))]
+    oT = [np.log(errs[k]["T"] / errs[k + 1]["T"]) / ratio[k] for k in range(len(ratio))]
+    print("sizes", SIZES, "L2 errors", errs, "orders u", ou, "T", oT)
+    # second order on every refinement, approaching 2 from below
+    assert min(ou) > 1.8 and min(oT) > 1.8
+    assert ou[-1] >= ou[0] - 0.02 and oT[-1] >= oT[0] - 0.02
+    assert max(ou) < 2.2 and max(oT) < 2.2

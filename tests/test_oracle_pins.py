@@ -16,6 +16,8 @@ import oracle
 from oracle import solve as osolve
 from paper_1508_04596_amd import inputs
 
+import textbook
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -147,16 +149,11 @@ def test_source_region_is_central_two_cubed_on_8x8x8():
 # ---------------------------------------------- textbook element matrices --
 
 def _1d(h):
-    M1 = h / 6 * np.array([[2.0, 1.0], [1.0, 2.0]])        # int N_a N_b
-    S1 = 1 / h * np.array([[1.0, -1.0], [-1.0, 1.0]])      # int N_a' N_b'
-    C1 = 0.5 * np.array([[-1.0, 1.0], [-1.0, 1.0]])        # int N_a N_b'
-    D1 = C1.T                                              # int N_a' N_b
-    return M1, S1, C1, D1
+    return textbook.one_d(h)
 
 
 def _tp(fx, fy, fz):
-    """8x8 tensor-product matrix, local node a = ax + 2 ay + 4 az."""
-    return np.kron(fz, np.kron(fy, fx))
+    return textbook.tp(fx, fy, fz)
 
 
 def textbook_element_jacobian_at_rest(h, Pr, B, eg, alpha, K, tau):
