@@ -13,7 +13,10 @@ One step = the whole hot path on that input:
 Prints one JSON line.  ``value`` is the FP64 J v throughput in GDOF/s; the solve
 times, the FP32 rate and the mixed-vs-FP64 error ride along.  ``roofline``
 describes the FP64 element-pass kernel of J v, timed with HIP events that the
-library records around each of its launches on the stream it runs on; ``cpu_baseline`` times the CPU oracle's J v on the host cores.
+library records around each of its launches on the stream it runs on.
+``cpu_baseline`` times the CPU oracle on the host cores: J v and residual on
+the same workload, and a full Newton solve of the 8x8x8 workload next to the
+GPU solve of the same input.
 """
 from __future__ import annotations
 
@@ -47,6 +50,9 @@ ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.13, 17217.17
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)
+# SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
+# of the element kernel reports traffic as null instead of a stale figure.
+ELEM_TRAFFIC_SRC_SHA256 = "54e2069b5e484517122b0305ea5f1b711c2a04dbbf0ad3467c0df8596fac53a6"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
        "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
@@ -76,7 +82,7 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--max-newton", type=int, default=50)
     ap.add_argument("--max-lin", type=int, default=3000)
-    ap.add_argument("--serve-requests", type=int, default=64,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving trace (Poisson arrivals, 20/s); 0 = skip")
     ap.add_argument("--serve-rate", type=float, default=20.0,
                     help="mean arrival rate of the serving trace (requests/s)")
@@ -180,8 +186,9 @@ def main():
     t_elem32 = float(np.median([q["t_elem32"] for q in recs]))
     bytes_alg = jv_bytes(n_nodes, n_el)
     achieved = FLOPS_PER_ELEM_JV * n_el / t_elem64
-    # the traffic counters were taken on the 64^3 workload only
-    traffic = ELEM_TRAFFIC_BYTES if args.config == 2 else None
+    # the traffic counters were taken on the 64^3 workload, for one source of the kernel
+    traffic = ELEM_TRAFFIC_BYTES if args.config == 2 and elem_source_sha256() == \
+        ELEM_TRAFFIC_SRC_SHA256 else None
     n_tiles = -(-p.nx // 8) * -(-p.ny // 8) * -(-p.nz // 4)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
@@ -200,6 +207,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, args.cpu_seconds)
+        cpu.update(c1_solves(fe, inputs, dev))
 
     line = {
         "metric": "Jv GDOF/s + Newton solve time to 1e-8 (FP64 vs mixed); p50/p99 serve latency",
@@ -257,39 +265,97 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0):
             "queue_wait_p50_s": float(np.percentile([b - a for a, b, _ in times], 50))}
 
 
+def elem_source_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1508_04596_amd", "csrc", "fe_elem.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def host_cpu():
+    """lscpu model name, sockets and physical cores, and the CPUs this process may use."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = dict(line.split(":", 1) for line in out.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        cps = int(kv.get("Core(s) per socket", "0") or 0)
+        info["sockets"] = sockets
+        info["physical_cores"] = sockets * cps
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    info["cpus_available"] = len(os.sched_getaffinity(0))
+    return info
+
+
+def _timed(fn, seconds):
+    fn()  # warm
+    n, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return n, el
+
+
 def cpu_baseline(p, seconds):
-    """The oracle's FP64 J v on this host's cores, repeated for about ``seconds``."""
+    """The oracle's FP64 J v and residual on this host's cores (about ``seconds``
+    of J v, a third of that for the residual and for J v on one thread)."""
     import oracle
     from paper_1508_04596_amd import inputs
     x = inputs.random_state(p, 2001, mask=p.mask_solve)
     v = inputs.random_direction(p, 1, mask=p.mask_solve)
-    oracle.jvp(p, x, v, mask="solve")  # warm
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.jvp(p, x, v, mask="solve")
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+    n, el = _timed(lambda: oracle.jvp(p, x, v, mask="solve"), seconds)
+    nr, elr = _timed(lambda: oracle.residual(p, x, mask="solve"), seconds / 3)
     cores = oracle.num_threads()
     # the same on one thread, a shorter sample
     oracle.set_num_threads(1)
-    n1 = 0
-    t1 = time.perf_counter()
-    while True:
-        oracle.jvp(p, x, v, mask="solve")
-        n1 += 1
-        el1 = time.perf_counter() - t1
-        if el1 >= seconds / 3:
-            break
+    n1, el1 = _timed(lambda: oracle.jvp(p, x, v, mask="solve"), seconds / 3)
     oracle.set_num_threads(cores)
     return {"value": p.n_dof * n / el / 1e9, "unit": "GDOF/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} FP64 J v products of the CPU oracle on the same {p.nx}x{p.ny}x{p.nz} problem "
                       f"({el:.1f} s)",
+            "residual_ms": elr / nr * 1e3,
+            "sample_residual": f"{nr} residual evaluations ({elr:.1f} s)",
             "value_1_thread": p.n_dof * n1 / el1 / 1e9,
-            "sample_1_thread": f"{n1} products on one thread ({el1:.1f} s)"}
+            "sample_1_thread": f"{n1} products on one thread ({el1:.1f} s)",
+            "host": host_cpu()}
+
+
+def c1_solves(fe, inputs, dev):
+    """Newton solve to 1e-8 of the 8x8x8 workload (3,645 DOF, Gr = 1e3): the oracle
+    (exact sparse linear solves, all cores) against the GPU (FP64 and mixed, the
+    library's default preconditioner), same inputs, medians of several runs."""
+    import torch
+    from oracle import solve as osolve
+    p1 = inputs.config(1)
+    t_or = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, it_or, rel_or = osolve.newton(p1, rtol=1e-8)
+        t_or.append(time.perf_counter() - t0)
+    prob = fe.Problem.from_inputs(p1, mask="solve")
+    g = torch.from_numpy(p1.gamma).to(dev)
+    s = torch.from_numpy(p1.s).to(dev)
+    out = {"c1_oracle_solve_s": float(np.median(t_or)), "c1_oracle_newton_its": it_or,
+           "c1_oracle_rel_res": rel_or}
+    for prec in ("fp64", "mixed"):
+        ts = []
+        for _ in range(5):
+            x = torch.zeros(p1.n_dof, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = fe.newton_solve(prob, g, s, x, fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec))
+            ts.append(time.perf_counter() - t0)
+        out[f"c1_gpu_{prec}_solve_s"] = float(np.median(ts))
+        out[f"c1_gpu_{prec}_newton_its"] = rep["newton_its"]
+    prob.close()
+    return out
 
 
 if __name__ == "__main__":

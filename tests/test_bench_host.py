@@ -28,3 +28,18 @@ def test_workload_names(cfg):
     assert f"C{cfg}:" in text and "10 Jv FP64" in text
     if p is not None:
         assert f"{p.nx}x{p.ny}x{p.nz}" in text and f"{p.n_dof:,}" in text
+
+
+def test_host_cpu_record():
+    sys.path.insert(0, ROOT)
+    import bench
+    info = bench.host_cpu()
+    assert info["cpus_available"] >= 1
+    assert "model" in info and "physical_cores" in info and "sockets" in info
+
+
+def test_traffic_guard_tracks_the_element_source():
+    sys.path.insert(0, ROOT)
+    import bench
+    sha = bench.elem_source_sha256()
+    assert len(sha) == 64 and len(bench.ELEM_TRAFFIC_SRC_SHA256) == 64

@@ -100,10 +100,11 @@ def test_fp32_jv_against_oracle(fe, name, make):
         vr = v.astype(np.float32).astype(np.float64)
         ref = oracle.jvp(p, xr, vr)
         err = rel_norm(jv32, ref)
-        print(f"[fp32] {name} jv rel err {err:.3e}")
-        assert err <= 2e-5
         jt32 = host(fe.fe_adjoint_jtvp(prob, dev(x, torch.float32), g, s, dev(v, torch.float32)))
-        assert rel_norm(jt32, oracle.jtvp(p, xr, vr)) <= 2e-5
+        errt = rel_norm(jt32, oracle.jtvp(p, xr, vr))
+        print(f"[fp32] {name} jv rel err {err:.3e}, jtv {errt:.3e}")
+        # measured at most 7.3e-8 over these cases; the bound is about 14x that
+        assert err <= 1e-6 and errt <= 1e-6
     prob.close()
 
 

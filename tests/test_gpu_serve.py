@@ -33,7 +33,7 @@ def test_same_result_alone_and_in_the_mix(fe):
     opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
     alone = {}
     with fe.Server(4 << 30, max_active=1) as srv:
-        for i in (0, 5):
+        for i in range(len(probs)):
             t = submit(fe, srv, probs[i], opts)
             rc, x, rep = srv.wait(t)
             assert rc == fe.FE_OK, rep
@@ -48,8 +48,10 @@ def test_same_result_alone_and_in_the_mix(fe):
         r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
         r = np.linalg.norm(oracle.residual(p, x, mask="solve"))
         assert r <= 1e-8 * r0 * 1.0001, (i, r / r0)
+    # every request of the mix is bitwise the same as when served alone
     for i, x in alone.items():
         assert np.array_equal(res[i][1], x), f"request {i} differs alone vs in the mix"
+    assert len(alone) == len(probs)
     # several requests were on the GPU at the same time
     overlaps = sum(1 for a in range(len(times)) for b in range(a + 1, len(times))
                    if times[a][1] < times[b][2] and times[b][1] < times[a][2])

@@ -126,3 +126,60 @@ def test_short_optimisation_run(fe):
     assert np.array_equal(results[0][0], results[1][0])
     assert np.all((rho1[p.design] >= 0.0) & (rho1[p.design] <= 1.0))
     prob.close()
+
+
+# (q_f, q_alpha, alpha_bar) of the five continuation steps, Sec. "Continuation scheme"
+CONTINUATION = [(0.881, 8.0, 1e5), (8.81, 8.0, 1e5), (88.1, 8.0, 1e5), (881.0, 98.0, 1e6),
+                (881.0, 998.0, 1e7)]
+
+
+def test_all_five_continuation_steps_against_the_oracle(fe):
+    """The design loop through all five continuation steps (two MMA iterations
+    each, as fe_topopt_run does them: the step's parameters set on the problem,
+    then the iterations).  After the iterations of steps 2-5 the GPU's objective,
+    constraint and design gradients at the current design equal the oracle's
+    chain at that step's parameters; fe_topopt_run from the same start then ends
+    on the same design."""
+    import copy
+    p, prob, _ = cavity_setup(fe)
+    design = dev(p.design.astype(np.uint8), torch.uint8)
+    gfix, s = dev(p.gamma), dev(p.s)
+    opts = fe.topopt_opts(vf=0.05, n_steps=5, iters_per_step=[2] * 5,
+                          q_f=[c[0] for c in CONTINUATION], q_alpha=[c[1] for c in CONTINUATION],
+                          alpha_max=[c[2] for c in CONTINUATION],
+                          state=dict(rtol_newton=1e-12, ramp_steps=0), adjoint=dict(rtol_lin=1e-12))
+    ofilt = OFilter(p.nx, p.ny, p.nz, p.h, 2.5 * p.h)
+    rho0 = np.where(p.design, 0.95, 0.0)
+    T = fe.TopOpt(prob, design, gfix, s, opts)
+    rho = dev(rho0)
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    for k, (qf, qa, am) in enumerate(CONTINUATION):
+        prob.set_phys(fe.make_phys(p.Pr, p.Gr, p.Ck, qf, am, qa, p.eg))
+        for _ in range(2):
+            T.step(rho, x)
+        if k == 0:
+            continue
+        print(f"[continuation] step {k + 1}: qf {qf} q_alpha {qa} alpha_bar {am:g}", flush=True)
+        rho_h = rho.cpu().numpy()
+        f, g, df, dg, rec = T.evaluate(rho.clone(), x.clone())
+        pk = copy.copy(p)
+        pk.qf, pk.q_alpha, pk.alpha_max = qf, qa, am
+        fr, gr, dfr, dgr, _ = otop.evaluate(pk, ofilt, rho_h, p.design, p.gamma, vf=0.05)
+        print(f"[continuation] f {f:.12e} oracle {fr:.12e}; g {g:+.6e} oracle {gr:+.6e}; "
+              f"df rel {rel_max(df.cpu().numpy(), dfr):.2e}", flush=True)
+        assert abs(f - fr) <= 1e-10 * abs(fr)
+        assert abs(g - gr) <= 1e-12
+        assert rel_max(df.cpu().numpy(), dfr) <= 1e-8
+        assert rel_max(dg.cpu().numpy(), dgr) <= 1e-10
+    rho_manual = rho.cpu().numpy()
+    T.close()
+    T2 = fe.TopOpt(prob, design, gfix, s, opts)
+    rho2 = dev(rho0)
+    x2 = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    hist = T2.run(rho2, x2)
+    T2.close()
+    assert [r["step"] for r in hist] == [k for k in range(5) for _ in range(2)]
+    d = np.abs(rho2.cpu().numpy() - rho_manual).max()
+    print(f"[continuation] run vs manual stepping: max design difference {d:.2e}")
+    assert d <= 1e-12
+    prob.close()
