@@ -347,6 +347,28 @@ int fe_topopt_run(fe_topopt *t, double *rho, double *x, fe_topopt_record *hist, 
                   int *n_done, hipStream_t stream);
 int fe_topopt_destroy(fe_topopt *t);
 
+/* J v without device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Computes exactly what fe_jvp computes on a problem
+ * created with the same grid, phys and dof_mask (same kernels, bitwise the
+ * same result), but takes the grid, parameters and mask directly instead of a
+ * problem handle: its two work buffers (per-node mask bits and tile-face
+ * partial sums) live in a static device array of FE_NOALLOC_SCRATCH_BYTES
+ * that every GPU the library runs on holds until the process ends.
+ *   dof_mask: device uint8[n_dof] (1 = prescribed; NULL = none), as for
+ *   fe_problem_create; x, v, jv: device FP64 or FP32 [n_dof] per prec; gamma,
+ *   s_elem: device FP64[n_el].  Stream-ordered, no synchronisation.
+ * Grids whose scratch need (fe_jvp_noalloc_scratch_bytes) exceeds
+ * FE_NOALLOC_SCRATCH_BYTES (64 MiB: FP64 grids up to about 4,000 8x8x4-element
+ * tiles, e.g. 96^3) are refused with FE_EINVAL.  Every call on one GPU uses
+ * the same array: calls that overlap on one GPU (different streams or host
+ * threads without ordering between them) race and give wrong results. */
+#define FE_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int64_t fe_jvp_noalloc_scratch_bytes(const fe_grid *grid, fe_prec prec);
+int fe_jvp_noalloc(const fe_grid *grid, const fe_phys *phys, fe_prec prec, const uint8_t *dof_mask,
+                   const void *x, const double *gamma, const double *s_elem, const void *v,
+                   void *jv, hipStream_t stream);
+
 const char *fe_last_error(void);
 const char *fe_version(void);
 

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe_hip.so")
-SOURCES = ["fe_elem.hip", "fe_vec.hip", "fe_mg.hip", "fe_filter.hip", "fe_mma.hip", "fe_api.cpp",
+SOURCES = ["fe_elem.hip", "fe_vec.hip", "fe_mg.hip", "fe_filter.hip", "fe_mma.hip", "fe_noalloc.hip",
+           "fe_api.cpp",
            "fe_solver.cpp", "fe_mg.cpp", "fe_topopt.cpp",
            "fe_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -142,6 +142,9 @@ def lib() -> ctypes.CDLL:
         L.fe_kernel_timer.argtypes = [vp, i32]
         L.fe_kernel_timer_read.argtypes = [vp, P(dbl), P(ctypes.c_int64)]
         L.fe_dR_dgamma.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fe_jvp_noalloc.argtypes = [P(FeGrid), P(FePhys), i32, vp, vp, vp, vp, vp, vp, vp]
+        L.fe_jvp_noalloc_scratch_bytes.argtypes = [P(FeGrid), i32]
+        L.fe_jvp_noalloc_scratch_bytes.restype = i64
         L.fe_compliance.argtypes = [vp, vp, vp, P(dbl), vp, vp]
         L.fe_block_diagonal.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fe_solve_opts_default.argtypes = [P(FeSolveOpts)]
@@ -293,6 +296,28 @@ def fe_jvp(prob: Problem, x, gamma, s, v, out=None, stream=None):
                         _ptr(gamma, torch.float64, ne, "gamma"), _ptr(s, torch.float64, ne, "s"),
                         _ptr(v, x.dtype, nd, "v"), _ptr(out, x.dtype, nd, "out"),
                         _stream(stream)), "fe_jvp")
+    return out
+
+
+FE_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fe_jvp_noalloc_scratch_bytes(nx, ny, nz, prec=FE_FP64) -> int:
+    return int(lib().fe_jvp_noalloc_scratch_bytes(ctypes.byref(FeGrid(nx, ny, nz, 1.0)), prec))
+
+
+def fe_jvp_noalloc(nx, ny, nz, h, phys: FePhys, mask, x, gamma, s, v, out=None, stream=None):
+    """J v through the allocation-free entry point (no problem handle); ``mask``
+    is a device uint8 tensor of n_dof entries or None."""
+    prec = _prec_of(x)
+    nd = 5 * (nx + 1) * (ny + 1) * (nz + 1)
+    ne = nx * ny * nz
+    out = torch.empty_like(v) if out is None else out
+    _check(lib().fe_jvp_noalloc(ctypes.byref(FeGrid(nx, ny, nz, h)), ctypes.byref(phys), prec,
+                                _ptr(mask, torch.uint8, nd, "mask"), _ptr(x, x.dtype, nd, "x"),
+                                _ptr(gamma, torch.float64, ne, "gamma"),
+                                _ptr(s, torch.float64, ne, "s"), _ptr(v, x.dtype, nd, "v"),
+                                _ptr(out, x.dtype, nd, "out"), _stream(stream)), "fe_jvp_noalloc")
     return out
 
 
