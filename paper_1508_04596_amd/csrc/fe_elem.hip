@@ -430,8 +430,6 @@ __device__ __forceinline__ int64_t gnode(const Geo &g, int I, int J, int K)
     return (int64_t)I + (int64_t)(g.nx + 1) * ((int64_t)J + (int64_t)(g.ny + 1) * K);
 }
 
-// Stage the node box of x (and of the masked direction v) in LDS; zero the
-// output accumulator.
 // threadIdx.x hidden from the optimiser (an empty asm statement that claims to
 // change it), so that index arithmetic derived from it is not specialised on
 // its range.  Used for the FP32 staging loop, where the code generated this way
@@ -444,22 +442,70 @@ __device__ __forceinline__ int opaque_tid()
     return t;
 }
 
-template <typename T, int NVO, bool HASV>
-__device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
-                                      const T *__restrict__ v, const uint8_t *__restrict__ nmask,
-                                      T (*sx)[BOXN], T (*sv)[BOXN], T *so)
+// Stage one node per thread and iteration (its five values of x and of v,
+// and its mask byte): the box position and the global node index are worked
+// out once for five values.  Fixed trip count, branch-free loads (nodes
+// outside the box or the grid load node 0 and are replaced by 0), all issued
+// before the first wait.
+template <typename T, bool HASV>
+__device__ __forceinline__ void stage_by_node(const Geo &g, const TileIdx &t,
+                                              const T *__restrict__ x, const T *__restrict__ v,
+                                              const uint8_t *__restrict__ nmask, T (*sx)[BOXN],
+                                              T (*sv)[BOXN], int tid)
 {
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
-    const int tid = sizeof(T) == 4 ? opaque_tid() : (int)threadIdx.x;
-    // fixed trip count, unrolled: every thread issues all of its global loads
-    // before the first one is waited for
+    constexpr int NIT = (BOXN + NTHR - 1) / NTHR;
+    T xv[NIT][NF], vv[NIT][NF];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int nb = tid + it * NTHR;
+        const int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        const int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+        const bool in = nb < BOXN && I <= g.nx && J <= g.ny && K <= g.nz;
+        const int64_t gn = in ? gnode(g, I, J, K) : 0;
+        const T *xp = x + NF * gn;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const T xl = xp[f];
+            xv[it][f] = in ? xl : T(0);
+        }
+        if (HASV) {
+            const T *vp = v + NF * gn;
+            const int m = in ? (int)nmask[gn] : 0x1f;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const T vl = vp[f];
+                vv[it][f] = ((m >> f) & 1) ? T(0) : vl;
+            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int nb = tid + it * NTHR;
+        if (nb < BOXN) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                sx[f][nb] = xv[it][f];
+                if (HASV) sv[f][nb] = vv[it][f];
+            }
+        }
+    }
+}
+
+// Stage one value (node and field) per thread and iteration, fixed trip count,
+// branch-free as above.
+template <typename T, bool HASV>
+__device__ __forceinline__ void stage_by_value(const Geo &g, const TileIdx &t,
+                                               const T *__restrict__ x, const T *__restrict__ v,
+                                               const uint8_t *__restrict__ nmask, T (*sx)[BOXN],
+                                               T (*sv)[BOXN], int tid)
+{
+    const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
     constexpr int NIT = (BOXN * NF + NTHR - 1) / NTHR;
     T xv[NIT], vv[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = tid + it * NTHR;
-        // branch-free: entries outside the box or the grid load node 0 and
-        // are replaced by 0, so no load waits on a branch
         const int nb = idx / NF, f = idx - nb * NF;
         const int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
         const int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
@@ -484,6 +530,23 @@ __device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *_
             if (HASV) sv[f][nb] = vv[it];
         }
     }
+}
+
+// Stage the node box of x (and of the masked direction v) in LDS; zero the
+// output accumulator.  The FP32 kernels stage by node: that measured 4-5 %
+// faster for the FP32 J v element pass (64^3: 31.2 -> 29.9 us, 160x160x320:
+// 709 -> 675 us).  The FP64 kernels stage by value: by node, J v and J^T w did
+// not change and the residual, whose body then no longer fits two waves per
+// SIMD, ran 18-23 % slower.
+template <typename T, int NVO, bool HASV>
+__device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
+                                      const T *__restrict__ v, const uint8_t *__restrict__ nmask,
+                                      T (*sx)[BOXN], T (*sv)[BOXN], T *so)
+{
+    if constexpr (sizeof(T) == 4)
+        stage_by_node<T, HASV>(g, t, x, v, nmask, sx, sv, opaque_tid());
+    else
+        stage_by_value<T, HASV>(g, t, x, v, nmask, sx, sv, (int)threadIdx.x);
     if (NVO > 0)
         for (int idx = threadIdx.x; idx < BOXN * NVO; idx += NTHR) so[idx] = T(0);
 }
@@ -1175,6 +1238,73 @@ __device__ __forceinline__ void shape_at(const SGT &SG, int a, double h, double 
     dN[2] = (sgn[2] / h) * f[0] * f[1];
 }
 
+// Corners per group of the block kernel: 2 measured 1.5x faster than the
+// per-corner evaluation of the directional derivatives (64^3: 400 -> 265 us,
+// 160x160x320: 10.3 -> 6.7 ms, with the shared-node pass); 1 corner per group
+// (fewest registers) 280 us / 7.0 ms; 4 corners 261 us / 6.6 ms but spills.
+#ifndef FE_BD_GROUP
+#define FE_BD_GROUP 2
+#endif
+
+// State at one Gauss point: velocity, its gradient G[i][j] = d u_i / d x_j,
+// the strong momentum residual and the temperature gradient and residual.
+struct BdState {
+    double u[3], G[3][3], rM[3], gT[3], rT;
+};
+
+// Unscaled (without the Gauss weight W) contribution of one Gauss point to the
+// nodal 5x5 block of corner a: row f, column k of
+// sum_g W d R_{f,a} / d x_{k,a}, the directional derivative of the element
+// residual (Galerkin + SUPG/PSPG with tau and tauT, and their variation with
+// the element velocity) along the unit vector of DOF (a, k).  With N = N_a and
+// d = grad N_a at the point, udN = u . d, and dtau_k = -tau^3 u_{a,k}/(16 h^2)
+// (likewise dtauT_k), the terms are those of J v with v = N e_k:
+//   velocity columns k < 3:
+//     [i][k] = N (N + tau udN) G_ik + delta_ik ((udN + alpha N)(N + tau udN) + Pr |d|^2)
+//              + Pr d_i d_k + rM_i (udN dtau_k + tau N d_k)
+//     [3][k] = N d_k + dtau_k (d . rM) + tau (N (d . G_{.k}) + d_k (udN + alpha N))
+//     [4][k] = N gT_k (N + tauT udN) + rT (udN dtauT_k + tauT N d_k)
+//   pressure column: [i][3] = d_i (tau udN - N), [3][3] = tau |d|^2, [4][3] = 0
+//   temperature column: [i][4] = B eg_i N (N + tau udN), [3][4] = tau B N (eg . d),
+//     [4][4] = N udN + K |d|^2 + tauT udN^2.
+template <typename T>
+__device__ __forceinline__ void bd_corner(const EC<T> &c, const BdState &st, T N, const T dN[3],
+                                          const T ua[3], T alpha, T Kc, T tau, T tauT, T blk[25])
+{
+    const T udN = st.u[0] * dN[0] + st.u[1] * dN[1] + st.u[2] * dN[2];
+    const T dd = dN[0] * dN[0] + dN[1] * dN[1] + dN[2] * dN[2];
+    const T Nt = N + tau * udN, NtT = N + tauT * udN;
+    const T uaN = udN + alpha * N;
+    const T c1 = N * Nt;
+    const T c2 = uaN * Nt + c.Pr * dd;
+    const T t3 = tau * tau * tau * c.inv16h2, t3T = tauT * tauT * tauT * c.inv16h2;
+    const T drM = dN[0] * st.rM[0] + dN[1] * st.rM[1] + dN[2] * st.rM[2];
+    const T egv[3] = {c.eg0, c.eg1, c.eg2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T dtk = -t3 * ua[k], dtTk = -t3T * ua[k];
+        const T ek = udN * dtk + tau * N * dN[k];
+        const T dGk = dN[0] * st.G[0][k] + dN[1] * st.G[1][k] + dN[2] * st.G[2][k];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            T v = c1 * st.G[i][k] + c.Pr * dN[i] * dN[k] + st.rM[i] * ek;
+            if (i == k) v += c2;
+            blk[i * NF + k] += v;
+        }
+        blk[3 * NF + k] += N * dN[k] + dtk * drM + tau * (N * dGk + dN[k] * uaN);
+        blk[4 * NF + k] += N * st.gT[k] * NtT + st.rT * (udN * dtTk + tauT * N * dN[k]);
+    }
+    const T pq = tau * udN - N, bN = c.B * N * Nt;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        blk[i * NF + 3] += dN[i] * pq;
+        blk[i * NF + 4] += egv[i] * bN;
+    }
+    blk[3 * NF + 3] += tau * dd;
+    blk[3 * NF + 4] += tau * c.B * N * (egv[0] * dN[0] + egv[1] * dN[1] + egv[2] * dN[2]);
+    blk[4 * NF + 4] += N * udN + Kc * dd + tauT * udN * udN;
+}
+
 __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restrict__ x,
                                                     const double *__restrict__ gamma,
                                                     const double *__restrict__ src,
@@ -1219,76 +1349,55 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
         tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
     }
     const double h = g.h;
-    for (int a = 0; a < 8; ++a) {
+    // Corners in groups of BDG: the state at each Gauss point is evaluated once
+    // per group (8 / BDG times per element instead of once per corner), and
+    // each corner's block is the closed form of the directional derivatives
+    // along the five unit vectors of that node (see bd_corner).  The
+    // accumulation keeps the corner order of the sub-steps.
+    constexpr int BDG = FE_BD_GROUP;
+#pragma unroll 1
+    for (int grp = 0; grp < 8 / BDG; ++grp) {
+        T blk[BDG][25];
+#pragma unroll
+        for (int cc = 0; cc < BDG; ++cc)
+#pragma unroll
+            for (int q = 0; q < 25; ++q) blk[cc][q] = T(0);
         if (t.valid) {
-            T blk[25];
+            T ua[BDG][3];
 #pragma unroll
-            for (int q = 0; q < 25; ++q) blk[q] = 0;
-            T ua[3];
+            for (int cc = 0; cc < BDG; ++cc)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) ua[i] = sx[i][t.nb[a]];
-#define FE_BD_GP(SG)                                                                          \
+                for (int k = 0; k < 3; ++k) ua[cc][k] = sx[k][t.nb[BDG * grp + cc]];
+#define FE_BD2_GP(SG)                                                                         \
     {                                                                                        \
-        T u[3], Gd[3][3], gp[3], Tv, gT[3];                                                  \
+        BdState st;                                                                          \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
-            eval_vg(SG, mu[i], c.gs, u[i], Gd[i][0], Gd[i][1], Gd[i][2]);                     \
+            eval_vg(SG, mu[i], c.gs, st.u[i], st.G[i][0], st.G[i][1], st.G[i][2]);           \
+        T gp[3], Tv;                                                                         \
         eval_g(SG, mp, c.gs, gp[0], gp[1], gp[2]);                                            \
-        eval_vg(SG, mT, c.gs, Tv, gT[0], gT[1], gT[2]);                                       \
-        T N, dN[3];                                                                          \
-        shape_at(SG, a, h, N, dN);                                                            \
+        eval_vg(SG, mT, c.gs, Tv, st.gT[0], st.gT[1], st.gT[2]);                              \
         const T egv[3] = {c.eg0, c.eg1, c.eg2};                                              \
-        T rM[3];                                                                             \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
-            rM[i] = u[0] * Gd[i][0] + u[1] * Gd[i][1] + u[2] * Gd[i][2] + gp[i]             \
-                  + alpha * u[i] + c.B * egv[i] * Tv;                                        \
-        T rT = u[0] * gT[0] + u[1] * gT[1] + u[2] * gT[2] - s;                               \
-        T udN = u[0] * dN[0] + u[1] * dN[1] + u[2] * dN[2];                                  \
-        _Pragma("unroll") for (int fc = 0; fc < NF; ++fc) {                                  \
-            /* direction: unit vector on (node a, field fc) */                               \
-            T du[3] = {0, 0, 0}, dG[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};               \
-            T dpv = 0, gdp[3] = {0, 0, 0}, dTv = 0, gdT[3] = {0, 0, 0};                      \
-            T dtau = 0, dtauT = 0;                                                           \
-            if (fc < 3) {                                                                    \
-                du[fc] = N;                                                                  \
-                dG[fc][0] = dN[0]; dG[fc][1] = dN[1]; dG[fc][2] = dN[2];                     \
-                dtau = -(tau * tau * tau) * ua[fc] * c.inv16h2;                              \
-                dtauT = -(tauT * tauT * tauT) * ua[fc] * c.inv16h2;                          \
-            } else if (fc == 3) {                                                            \
-                dpv = N; gdp[0] = dN[0]; gdp[1] = dN[1]; gdp[2] = dN[2];                     \
-            } else {                                                                         \
-                dTv = N; gdT[0] = dN[0]; gdT[1] = dN[1]; gdT[2] = dN[2];                     \
-            }                                                                                \
-            T A[3], Bm[3], dgal[3];                                                          \
-            _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                  \
-                T dconv = du[0] * Gd[i][0] + du[1] * Gd[i][1] + du[2] * Gd[i][2]             \
-                        + u[0] * dG[i][0] + u[1] * dG[i][1] + u[2] * dG[i][2];               \
-                dgal[i] = dconv + alpha * du[i] + c.B * egv[i] * dTv;                        \
-                A[i] = dtau * rM[i] + tau * (dgal[i] + gdp[i]);                              \
-                Bm[i] = tau * rM[i];                                                         \
-            }                                                                                \
-            T dudN = du[0] * dN[0] + du[1] * dN[1] + du[2] * dN[2];                          \
-            _Pragma("unroll") for (int i = 0; i < 3; ++i) {                                  \
-                T visc = c.Pr * ((dG[i][0] + dG[0][i]) * dN[0] + (dG[i][1] + dG[1][i]) * dN[1] \
-                                 + (dG[i][2] + dG[2][i]) * dN[2]);                           \
-                blk[i * NF + fc] += c.W * (N * dgal[i] + visc - dN[i] * dpv + udN * A[i]     \
-                                           + dudN * Bm[i]);                                  \
-            }                                                                                \
-            blk[3 * NF + fc] += c.W * (N * (dG[0][0] + dG[1][1] + dG[2][2])                  \
-                                       + dN[0] * A[0] + dN[1] * A[1] + dN[2] * A[2]);        \
-            T drT = du[0] * gT[0] + du[1] * gT[1] + du[2] * gT[2]                            \
-                  + u[0] * gdT[0] + u[1] * gdT[1] + u[2] * gdT[2];                           \
-            T AT = dtauT * rT + tauT * drT, BT = tauT * rT;                                  \
-            blk[4 * NF + fc] += c.W * (N * drT + Kc * (dN[0] * gdT[0] + dN[1] * gdT[1]       \
-                                                       + dN[2] * gdT[2])                     \
-                                       + udN * AT + dudN * BT);                              \
+            st.rM[i] = st.u[0] * st.G[i][0] + st.u[1] * st.G[i][1] + st.u[2] * st.G[i][2]   \
+                     + gp[i] + alpha * st.u[i] + c.B * egv[i] * Tv;                          \
+        st.rT = st.u[0] * st.gT[0] + st.u[1] * st.gT[1] + st.u[2] * st.gT[2] - s;            \
+        _Pragma("unroll") for (int cc = 0; cc < BDG; ++cc) {                                 \
+            T N, dN[3];                                                                      \
+            shape_at(SG, BDG * grp + cc, h, N, dN);                                          \
+            bd_corner(c, st, N, dN, ua[cc], alpha, Kc, tau, tauT, blk[cc]);                   \
         }                                                                                    \
     }
-            FE_GAUSS_LOOP(false, T, FE_BD_GP)
-#undef FE_BD_GP
-#pragma unroll
-            for (int q = 0; q < 25; ++q) so[q * BOXN + t.nb[a]] += blk[q];
+            FE_GAUSS_LOOP(false, T, FE_BD2_GP)
+#undef FE_BD2_GP
         }
-        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < BDG; ++cc) {
+            if (t.valid) {
+#pragma unroll
+                for (int q = 0; q < 25; ++q) so[q * BOXN + t.nb[BDG * grp + cc]] += c.W * blk[cc][q];
+            }
+            __syncthreads();
+        }
     }
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
     for (int nb = threadIdx.x; nb < BOXN; nb += NTHR) {
