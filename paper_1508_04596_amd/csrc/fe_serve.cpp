@@ -8,9 +8,12 @@
 // each other's memory, and no device allocation or free (and no implicit device
 // synchronisation) happens while requests run.  max_active worker threads, each
 // with its own HIP stream, take requests from the queue in arrival order as
-// soon as the arena has a free block for the head request; a request therefore
-// starts while others are still on the GPU, and the kernels of all running
-// requests overlap on the device.  A finished request returns its block and
+// soon as the arena has a free block for them; a request therefore starts
+// while others are still on the GPU, and the kernels of all running requests
+// overlap on the device.  When the head request does not fit the largest free
+// block, the first later request that fits is admitted instead, until the head
+// has been passed over max_active times; then admission waits for the head, so
+// a large request is delayed by at most that many smaller ones.  A finished request returns its block and
 // wakes the admission of the next.  Each request runs the same deterministic
 // kernels as a standalone newton_solve, so its result does not depend on what
 // else is running.
@@ -167,6 +170,7 @@ struct Request {
     int status = FE_PENDING;
     fe_solve_report rep;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    int bypassed = 0;  // later requests admitted while this one waited at the head
     std::string error;
 };
 
@@ -241,6 +245,22 @@ int run_request(fe_server *S, Request *r, hipStream_t st)
     return rc;
 }
 
+// The queued request to admit next (under S->mu): the head if it fits the
+// largest free block of the arena, else the first later one that fits, as
+// long as the head has been passed over fewer than max_active times; queue end
+// if none.
+std::deque<Request *>::iterator admissible(fe_server *S)
+{
+    if (S->queue.empty()) return S->queue.end();
+    const size_t room = S->arena.largest_free();
+    auto head = S->queue.begin();
+    if ((*head)->footprint <= room) return head;
+    if ((*head)->bypassed >= S->max_active) return S->queue.end();
+    for (auto it = std::next(head); it != S->queue.end(); ++it)
+        if ((*it)->footprint <= room) return it;
+    return S->queue.end();
+}
+
 void worker_main(fe_server *S)
 {
     (void)hipSetDevice(S->device);
@@ -250,13 +270,16 @@ void worker_main(fe_server *S)
         Request *r = nullptr;
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            std::deque<Request *>::iterator pick;
             S->cv.wait(lk, [&] {
-                return S->stop ||
-                       (!S->queue.empty() && S->arena.largest_free() >= S->queue.front()->footprint);
+                if (S->stop) return true;
+                pick = admissible(S);
+                return pick != S->queue.end();
             });
             if (S->stop) break;
-            r = S->queue.front();
-            S->queue.pop_front();
+            r = *pick;
+            if (pick != S->queue.begin()) S->queue.front()->bypassed++;
+            S->queue.erase(pick);
             // the arena changes only here and at a request's end, both under S->mu,
             // so the block found free above is still free
             if (S->arena.dev_alloc(&r->block, r->footprint) != hipSuccess) {

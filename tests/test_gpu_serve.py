@@ -183,3 +183,36 @@ def test_request_with_ramping_fits_its_block(fe):
         rc, x, rep = srv.wait(t)
         err = srv.error(t)
     assert rc == fe.FE_OK, err
+
+
+def test_smaller_requests_pass_a_blocked_head_a_bounded_number_of_times(fe):
+    """A 32^3 request at the head of the queue that does not fit next to the
+    16^3 request already running: later 16^3 requests that fit are admitted
+    past it, at most max_active of them, then the head is admitted; every
+    result is the same as when solved alone."""
+    small = inputs.scaled_config(16, 16, 16, 1e4, seed=21)
+    big = inputs.scaled_config(32, 32, 32, 1e4, seed=22)
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    fs = fe.fe_solve_footprint_bytes(16, 16, 16, small.h, opts)
+    fb = fe.fe_solve_footprint_bytes(32, 32, 32, big.h, opts)
+    # the big one fits only with no small one running (blocks carry about 1 %
+    # plus 1 MiB of margin over the footprint), two small ones fit together
+    budget = int(fb + 0.5 * fs) + (8 << 20)
+    assert budget < fb + fs and budget > 2 * fs
+    max_active = 3
+    with fe.Server(4 << 30, max_active=1) as srv:
+        alone_small = srv.wait(submit(fe, srv, small, opts))[1]
+        alone_big = srv.wait(submit(fe, srv, big, opts))[1]
+    with fe.Server(budget, max_active=max_active) as srv:
+        t0 = submit(fe, srv, small, opts)
+        tb = submit(fe, srv, big, opts)
+        later = [submit(fe, srv, small, opts) for _ in range(8)]
+        res = {t: srv.wait(t) for t in [t0, tb] + later}
+        times = {t: srv.times(t) for t in res}
+    assert all(r[0] == fe.FE_OK for r in res.values())
+    passed = [t for t in later if times[t][1] < times[tb][1]]
+    print(f"[serve] later requests admitted before the blocked head: {len(passed)}")
+    assert 1 <= len(passed) <= max_active
+    assert np.array_equal(res[tb][1], alone_big)
+    for t in [t0] + later:
+        assert np.array_equal(res[t][1], alone_small)
