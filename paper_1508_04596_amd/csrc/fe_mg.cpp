@@ -37,6 +37,10 @@ template <typename T>
 hipError_t mg_restrict(const fe_grid &c, const fe_grid &f, const T *b, const T *t,
                        const uint8_t *cmask, T *bc, hipStream_t st);
 template <typename T>
+hipError_t mg_restrict_smooth(const fe_grid &c, const fe_grid &f, const T *b, const T *t,
+                              const uint8_t *cmask, T *bc, const T *Dc, T *xc, T omega,
+                              bool transpose, hipStream_t st);
+template <typename T>
 hipError_t mg_prolong_add(const fe_grid &f, const fe_grid &c, const T *xc, const uint8_t *fmask,
                           T *x, hipStream_t st);
 template <typename T>
@@ -574,8 +578,11 @@ static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
     return FE_OK;
 }
 
+// V-cycle from level l on b; x receives the result.  first_done: the first
+// pre-smoothing sweep from x = 0 (x = omega D^{-1} b) has already been applied
+// to x, by the restriction kernel of the level above.
 template <typename T>
-static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
+static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st, bool first_done = false)
 {
     MgLevel &L = mg->lev[l];
     const int nl = (int)mg->lev.size();
@@ -583,13 +590,20 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st)
     const T om = (T)mg->omega;
     const T *D = blocksT<T>(L);
     T *t = vecT<T>(L, 2);
-    FE_CHECK_HIP(mg_smooth<T>(D, b, nullptr, x, L.nn, om, tr, false, st));
+    if (!first_done) FE_CHECK_HIP(mg_smooth<T>(D, b, nullptr, x, L.nn, om, tr, false, st));
     for (int it = 1; it < mg->nu1; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
     MgLevel &C = mg->lev[l + 1];
     FE_CHECK_HIP(op<T>(L, x, t, tr, st));
     T *bc = vecT<T>(C, 0), *xc = vecT<T>(C, 1);
-    FE_CHECK_HIP(mg_restrict<T>(C.grid, L.grid, b, t, C.nmask, bc, st));
-    int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st);
+    // below the coarse level's first sweep is fused into the restriction,
+    // except where that level is the directly solved coarsest one
+    const bool fuse = l + 1 < nl - 1;
+    if (fuse)
+        FE_CHECK_HIP(mg_restrict_smooth<T>(C.grid, L.grid, b, t, C.nmask, bc, blocksT<T>(C), xc, om,
+                                           tr, st));
+    else
+        FE_CHECK_HIP(mg_restrict<T>(C.grid, L.grid, b, t, C.nmask, bc, st));
+    int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st, fuse);
     if (rc) return rc;
     FE_CHECK_HIP(mg_prolong_add<T>(L.grid, C.grid, xc, L.nmask, x, st));
     for (int it = 0; it < mg->nu2; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));

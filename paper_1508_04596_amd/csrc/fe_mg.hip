@@ -106,6 +106,69 @@ __global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, int
     bc[q] = ((cmask[n] >> f) & 1) ? T(0) : acc;
 }
 
+// The restriction above fused with the first smoothing sweep of the coarse
+// level, which starts from x_c = 0: x_c = omega D_c^{-1} b_c (D_c^{-T} when
+// TR).  A workgroup of 255 threads covers the 5 DOFs of 51 coarse nodes; b_c
+// of a node reaches its other four threads through LDS.  Both results are
+// bitwise those of k_restrict followed by k_smooth (same terms, same order).
+template <typename T, bool TR>
+__global__ __launch_bounds__(255) void k_restrict_smooth(int ncx, int ncy, int ncz, int nfx,
+                                                         int nfy, int nfz, const T *__restrict__ b,
+                                                         const T *__restrict__ t,
+                                                         const uint8_t *__restrict__ cmask,
+                                                         T *__restrict__ bc,
+                                                         const T *__restrict__ Dc,
+                                                         T *__restrict__ xc, T omega)
+{
+    __shared__ T sb[255];
+    const int64_t nn = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
+    const int lq = (int)threadIdx.x;
+    const int ln = lq / NF, f = lq - NF * ln;
+    const int64_t n = (int64_t)blockIdx.x * 51 + ln;
+    const bool valid = n < nn;
+    T val = T(0);
+    if (valid) {
+        const int I = (int)(n % (ncx + 1));
+        const int64_t r = n / (ncx + 1);
+        const int J = (int)(r % (ncy + 1)), K = (int)(r / (ncy + 1));
+        T acc = T(0);
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int k = 2 * K + dz;
+            const bool inz = k >= 0 && k <= nfz;
+            const int kc = k < 0 ? 0 : (k > nfz ? nfz : k);
+            const T wz = dz == 0 ? T(1) : T(0.5);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int j = 2 * J + dy;
+                const bool iny = j >= 0 && j <= nfy;
+                const int jc = j < 0 ? 0 : (j > nfy ? nfy : j);
+                const T wy = dy == 0 ? T(1) : T(0.5);
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int i = 2 * I + dx;
+                    const bool in = inz && iny && i >= 0 && i <= nfx;
+                    const int ic = i < 0 ? 0 : (i > nfx ? nfx : i);
+                    const T w = (dx == 0 ? T(1) : T(0.5)) * wy * wz;
+                    const int64_t fn = ic + (int64_t)(nfx + 1) * (jc + (int64_t)(nfy + 1) * kc);
+                    const T v = w * (b[NF * fn + f] - (t ? t[NF * fn + f] : T(0)));
+                    acc += in ? v : T(0);
+                }
+            }
+        }
+        val = ((cmask[n] >> f) & 1) ? T(0) : acc;
+        bc[NF * n + f] = val;
+    }
+    sb[lq] = val;
+    __syncthreads();
+    if (!valid) return;
+    const T *Dn = Dc + n * 25;
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) acc += (TR ? Dn[c * NF + f] : Dn[f * NF + c]) * sb[NF * ln + c];
+    xc[NF * n + f] = omega * acc;
+}
+
 // x += P xc on unprescribed fine DOFs (trilinear interpolation); one thread
 // per fine DOF.  The up to 8 coarse parents are unrolled (along an even index
 // the parent repeats with its term dropped) so that their loads issue together.
@@ -517,6 +580,22 @@ hipError_t mg_restrict(const fe_grid &c, const fe_grid &f, const T *b, const T *
 }
 
 template <typename T>
+hipError_t mg_restrict_smooth(const fe_grid &c, const fe_grid &f, const T *b, const T *t,
+                              const uint8_t *cmask, T *bc, const T *Dc, T *xc, T omega,
+                              bool transpose, hipStream_t st)
+{
+    const int64_t n = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+    const dim3 g((unsigned)((n + 50) / 51)), bl(255);
+    if (transpose)
+        hipLaunchKernelGGL((k_restrict_smooth<T, true>), g, bl, 0, st, c.nx, c.ny, c.nz, f.nx, f.ny,
+                           f.nz, b, t, cmask, bc, Dc, xc, omega);
+    else
+        hipLaunchKernelGGL((k_restrict_smooth<T, false>), g, bl, 0, st, c.nx, c.ny, c.nz, f.nx, f.ny,
+                           f.nz, b, t, cmask, bc, Dc, xc, omega);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t mg_prolong_add(const fe_grid &f, const fe_grid &c, const T *xc, const uint8_t *fmask,
                           T *x, hipStream_t st)
 {
@@ -598,6 +677,9 @@ hipError_t mg_coarse_apply(int nfull, int m, const double *X, const int *fidx, c
     template hipError_t mg_restrict<T>(const fe_grid &, const fe_grid &, const T *, const T *,      \
                                        const uint8_t *, T *,                                      \
                                        hipStream_t);                                           \
+    template hipError_t mg_restrict_smooth<T>(const fe_grid &, const fe_grid &, const T *,       \
+                                              const T *, const uint8_t *, T *, const T *, T *, T,  \
+                                              bool, hipStream_t);                                 \
     template hipError_t mg_prolong_add<T>(const fe_grid &, const fe_grid &, const T *,           \
                                           const uint8_t *, T *,                                   \
                                           hipStream_t);                                        \
