@@ -46,13 +46,13 @@ PEAK_HBM = 8.0e12
 # torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
 # 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
 # whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.13, 17217.17
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.88, 17217.19
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
-ELEM_TRAFFIC_SRC_SHA256 = "54e2069b5e484517122b0305ea5f1b711c2a04dbbf0ad3467c0df8596fac53a6"
+ELEM_TRAFFIC_SRC_SHA256 = "de63c7919908f8b5895116119979412e0bbb0d005a640343f16cdee546d8bcc1"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
        "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
