@@ -72,6 +72,33 @@ def test_mma_parity(fe):
     m.close()
 
 
+def test_mma_parity_at_the_papers_design_size(fe):
+    """3,456,000 design variables (the design domain of the paper's 160x320x160
+    mesh, Sec. "Varying Grashof number"), three updates: the third moves the
+    asymptotes by the sign history of the last two steps."""
+    n = 3456000
+    rng = np.random.default_rng(13)
+    x = rng.uniform(0.1, 0.9, n)
+    ref = OMMA(n, move=0.2)
+    m = fe.MMA(n, move=0.2)
+    xg = dev(x)
+    xr = x.copy()
+    for k in range(3):
+        df0 = rng.uniform(-2.0, 0.5, n)
+        df1 = np.full(n, 1.0 / n) + 1e-3 * rng.standard_normal(n) / n
+        f1 = [0.05, -0.01, 0.02][k]
+        xr, lr = ref.update(xr, 1.0, df0, f1, df1)
+        lg = m.update(xg, dev(df0), f1, dev(df1))
+        xa = xg.cpu().numpy()
+        err = np.abs(xa - xr).max()
+        print(f"[mma] n={n} update {k}: lambda gpu {lg:.15e} oracle {lr:.15e}; max |x_gpu - x_oracle| {err:.2e}",
+              flush=True)
+        assert abs(lg - lr) <= 1e-10 * max(abs(lr), 1e-300) or lr == lg == 0.0
+        assert err <= 1e-10
+        xg = dev(xr)  # continue both from the oracle's iterate
+    m.close()
+
+
 def cavity_setup(fe, N=20, Gr=1e3, s0=10.0, seed=4):
     p = inputs.cavity_problem(N, Gr, s0=s0)
     rng = np.random.default_rng(seed)
