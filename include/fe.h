@@ -96,6 +96,25 @@ int fe_residual(fe_problem *p, const double *x, const double *gamma, const doubl
 int fe_jvp(fe_problem *p, fe_prec prec, const void *x, const double *gamma, const double *s_elem,
            const void *v, void *jv, hipStream_t stream);
 
+/* Batched J v over a table of problems (Sec. "Finite element formulation", as
+ * fe_jvp).  fe_jvp_batch_create copies to device memory a table with, for
+ * each of the n problems probs[i], its geometry, parameters and the device
+ * pointers x[i], gamma[i], s_elem[i], v[i], jv[i] (host arrays of n pointers;
+ * x, v, jv of precision prec, gamma and s_elem FP64), plus the workgroup
+ * offsets of the problems' concatenated tile and node index spaces.
+ * fe_jvp_batch_run then computes jv_i = J_i(x_i) v_i for all i with ONE launch
+ * of the element pass and ONE of the shared-node pass.  Per problem the
+ * arithmetic is fe_jvp's, so jv_i is bitwise what fe_jvp(probs[i], ...) gives.
+ * The problems must be distinct (each owns its tile-face work buffer) and
+ * outlive the batch; the vectors are read and written when run executes.
+ * FE_EINVAL for n < 1, a NULL or repeated problem or a NULL pointer. */
+typedef struct fe_batch fe_batch;
+int fe_jvp_batch_create(int n, fe_problem *const *probs, fe_prec prec, const void *const *x,
+                        const double *const *gamma, const double *const *s_elem,
+                        const void *const *v, void *const *jv, fe_batch **out);
+int fe_jvp_batch_run(fe_batch *b, hipStream_t stream);
+int fe_jvp_batch_destroy(fe_batch *b);
+
 /* Element-pass timer of fe_jvp (instrumentation; it changes no result).
  * fe_kernel_timer(p, 1) clears the record and starts timing: every later
  * fe_jvp on p records a pair of HIP events on its stream, right before and
@@ -250,6 +269,21 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
  * given (serve_submit_x0). */
 typedef struct fe_server fe_server;
 int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
+/* flags = FE_SERVE_BATCHED: the same server, but the requests' linear solves
+ * (one per Newton step: FGMRES with the multigrid V-cycle) run in lockstep on
+ * one engine thread -- each FGMRES step launches every kernel once over a
+ * device table of all running requests (concatenated element and DOF index
+ * spaces, per-request segmented reductions) -- while the workers keep the
+ * set-up and line search of their requests.  max_active may then be up to 256.
+ * A request's result is the same alone and in any mix (its arithmetic does not
+ * depend on the batch); it can differ from the default mode's in the last bits
+ * (the batched Gram-Schmidt step always takes its second pass).  Requests whose
+ * grid has no multigrid hierarchy use their worker's one-problem FGMRES. */
+#define FE_SERVE_BATCHED 1
+int serve_create_ex(size_t hbm_budget_bytes, int max_active, int flags, fe_server **out);
+/* Batched mode: lockstep steps run and batched launches issued so far (0 in
+ * the default mode). */
+int serve_engine_stats(fe_server *s, uint64_t *steps, uint64_t *launches);
 /* gamma_host, s_host: host FP64[n_el]; copied.  Returns at once with a ticket. */
 int serve_submit(fe_server *s, const fe_grid *grid, const fe_phys *phys, const double *gamma_host,
                  const double *s_host, const fe_solve_opts *opts, uint64_t *ticket);

@@ -16,10 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfe_hip.so")
-SOURCES = ["fe_elem.hip", "fe_vec.hip", "fe_mg.hip", "fe_filter.hip", "fe_mma.hip", "fe_noalloc.hip",
+SOURCES = ["fe_elem.hip", "fe_vec.hip", "fe_mg.hip", "fe_filter.hip", "fe_mma.hip", "fe_noalloc.hip", "fe_batch.hip",
            "fe_api.cpp",
            "fe_solver.cpp", "fe_mg.cpp", "fe_topopt.cpp",
-           "fe_serve.cpp"]
+           "fe_serve.cpp", "fe_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,216 @@
+// Batched launches over a table of problems (internal).
+//
+// A batched launch runs one kernel over several problems at once: entry i of a
+// device table holds problem i's arguments, and workgroups off[i] .. off[i+1]-1
+// of the launch work on it, each with its local workgroup index
+// blockIdx.x - off[i].  The element and multigrid kernels run the same device
+// bodies as their one-problem launches, so a problem's result does not depend
+// on which other problems share the launch, and equals that of the
+// one-problem kernels.
+#pragma once
+
+#include "fe_internal.h"
+
+namespace fe {
+
+// One batched launch: device pointers to its argument table and to the n + 1
+// workgroup offsets; blocks = off[n].
+struct BLaunch {
+    const void *tab = nullptr;
+    const int *off = nullptr;
+    int n = 0;
+    int blocks = 0;
+};
+
+// Table entry that owns this workgroup (off[0] = 0 <= blockIdx.x < off[n]).
+__device__ __forceinline__ int batch_entry(const int *__restrict__ off, int n)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---- element passes (fe_elem.hip) ------------------------------------------
+// J v: the element pass writes out (and the tile-face slots), the shared-node
+// pass completes out; both launches take the same table.
+template <typename Tin, typename Tout>
+struct BElem {
+    Geo g;
+    const Tin *x, *v;
+    const double *gamma, *s;
+    const uint8_t *nmask;
+    Tout *out, *slots;
+};
+// One smoothing sweep x += omega D^{-1} (b - J x) of a matrix-free level
+// (element pass into t and the slots, then the fused shared-node/smoothing pass).
+template <typename T>
+struct BElemSmooth {
+    Geo g;
+    const T *xs;
+    T *x;
+    const double *gamma, *s;
+    const uint8_t *nmask;
+    T *t, *slots;
+    const T *D, *b;
+    T omega;
+};
+inline int belem_blocks(const Geo &g) { return (int)n_tiles(g); }
+inline int bnode_blocks(const Geo &g) { return (int)((n_nodes(g) + 255) / 256); }
+template <typename Tin, typename Tout>
+hipError_t blaunch_elem_jv(const BLaunch &L, hipStream_t st);
+template <typename Tin, typename Tout>
+hipError_t blaunch_combine_jv(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_elem_smooth_pass(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_combine_smooth(const BLaunch &L, hipStream_t st);
+
+// ---- multigrid (fe_mg.hip) -------------------------------------------------
+template <typename T>
+struct BStencil {
+    int nx, ny, nz;
+    const T *S, *v;
+    T *out;
+};
+template <typename T>
+struct BSmooth {  // x (+)= omega D^{-1} (b - t); t may be NULL
+    const T *D, *b, *t;
+    T *x;
+    int64_t nn;
+    T omega;
+};
+template <typename T>
+struct BRestrict {  // b_c = R (b - t); with Dc: also x_c = omega D_c^{-1} b_c
+    int ncx, ncy, ncz, nfx, nfy, nfz;
+    const T *b, *t;
+    const uint8_t *cmask;
+    T *bc;
+    const T *Dc;
+    T *xc;
+    T omega;
+};
+template <typename T>
+struct BProlong {  // x += P x_c
+    int nfx, nfy, nfz, ncx, ncy;
+    const T *xc;
+    const uint8_t *fmask;
+    T *x;
+};
+template <typename T>
+struct BCoarse {  // x = A_c^{-1} b through the explicit inverse of the free DOFs
+    int nfull, n, nt;  // DOFs, free DOFs, 64-row tiles per dimension
+    const double *X;
+    const int *fidx, *pos;
+    const T *b;
+    T *x;
+    double *P;
+};
+inline int bstencil_blocks(int64_t nn) { return (int)((NF * nn + 63) / 64); }
+inline int bsmooth_blocks(int64_t nn) { return (int)((nn + 255) / 256); }
+inline int brestrict_blocks(int64_t nn_c) { return (int)((NF * nn_c + 255) / 256); }
+inline int brestrict_smooth_blocks(int64_t nn_c) { return (int)((nn_c + 50) / 51); }
+inline int bprolong_blocks(int64_t nn_f) { return (int)((NF * nn_f + 255) / 256); }
+inline int bcoarse_part_blocks(int n) { return n > 0 ? ((n + 63) / 64) * ((n + 63) / 64) : 0; }
+inline int bcoarse_sum_blocks(int nfull) { return (nfull + 255) / 256; }
+template <typename T>
+hipError_t blaunch_stencil(const BLaunch &L, hipStream_t st);
+template <typename T, bool ACC>
+hipError_t blaunch_smooth(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_restrict(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_restrict_smooth(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_prolong(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_coarse_part(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_coarse_sum(const BLaunch &L, hipStream_t st);
+
+// ---- vectors and reductions (fe_batch.hip) ---------------------------------
+// Reductions split a problem's vector of n entries into nchunk chunks of
+// 256 * ept consecutive entries (ept >= 8, nchunk <= BRED_MAX_CHUNKS); the
+// chunking depends on n only, and partials are added in a fixed order, so a
+// problem's sums are the same in every batch.
+constexpr int BRED_MAX_CHUNKS = 1024;
+constexpr int BDOT_GROUP = 8;  // basis vectors per workgroup of a multi-dot
+inline void bred_chunks(int64_t n, int *nchunk, int *ept)
+{
+    int64_t e = 8;
+    while ((n + 256 * e - 1) / (256 * e) > BRED_MAX_CHUNKS) e *= 2;
+    *ept = (int)e;
+    *nchunk = (int)std::max<int64_t>(1, (n + 256 * e - 1) / (256 * e));
+}
+struct BFill {
+    double *p;
+    int64_t n;
+};
+struct BCast {
+    const double *a;
+    float *b;
+    int64_t n;
+};
+struct BAxpby {  // y = a x + b y
+    int64_t n;
+    double a;
+    const double *x;
+    double b;
+    double *y;
+};
+struct BScale {  // y = x / s[0]
+    int64_t n;
+    const double *x, *s;
+    double *y;
+};
+constexpr int BCOMB_MAX = 64;
+template <typename Tz>
+struct BComb {  // x += sum_{j<k} y_j Z_j
+    const Tz *Z;
+    int64_t ld;
+    int k;
+    int64_t n;
+    double *x;
+    double y[BCOMB_MAX];
+};
+struct BDots {  // partial[c nchunk + chunk] of <V_c, w> for c < k, and <w, w> as column k if norm
+    const double *w, *V;
+    int64_t ld;
+    int k, norm;
+    int64_t n;
+    int nchunk, ept, ngrp;
+    double *partial;
+};
+struct BReduce {  // out[c] = sum of the nchunk partials of column c < ncol; beta = sqrt(out[ncol-1])
+    const double *partial;
+    int ncol, nchunk;
+    double *out, *beta;
+};
+struct BUpdate {  // w -= sum_{c<k} h_c V_c; partial[chunk] of <w, w> after it (if partial)
+    double *w;
+    const double *V;
+    int64_t ld;
+    int k;
+    int64_t n;
+    int nchunk, ept;
+    const double *h;
+    double *partial;
+};
+inline int belt_blocks(int64_t n) { return (int)((n + 255) / 256); }
+hipError_t blaunch_fill(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_cast(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_axpby(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_scale(const BLaunch &L, hipStream_t st);
+template <typename Tz>
+hipError_t blaunch_comb(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_dots(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_reduce(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_update(const BLaunch &L, hipStream_t st);
+
+}  // namespace fe

@@ -22,6 +22,7 @@
 // Brinkman limits; its variation with the element velocity vector enters the
 // consistent Jacobian).  The viscous second derivative is left out of the
 // strong residual used by SUPG/PSPG.
+#include "fe_batch.h"
 #include "fe_internal.h"
 
 namespace fe {
@@ -399,13 +400,17 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return (b & 7) * q + (b >> 3);
 }
 
-__device__ __forceinline__ TileIdx tile_index(const Geo &g)
+// blk / nblk: this workgroup's index among the nblk workgroups that cover the
+// grid's tiles (blockIdx.x / gridDim.x, or the local index within one problem
+// of a batched launch)
+__device__ __forceinline__ TileIdx tile_index(const Geo &g, int blk, int nblk)
 {
     TileIdx t;
 #if FE_XCD_REMAP
-    t.tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    t.tile = xcd_tile(blk, nblk);
 #else
-    t.tile = blockIdx.x;
+    (void)nblk;
+    t.tile = blk;
 #endif
     t.btx = t.tile % g.ntx;
     int r = t.tile / g.ntx;
@@ -423,6 +428,11 @@ __device__ __forceinline__ TileIdx tile_index(const Geo &g)
     for (int a = 0; a < 8; ++a)
         t.nb[a] = (t.li + (a & 1)) + BX * ((t.lj + ((a >> 1) & 1)) + BY * (t.lk + ((a >> 2) & 1)));
     return t;
+}
+
+__device__ __forceinline__ TileIdx tile_index(const Geo &g)
+{
+    return tile_index(g, (int)blockIdx.x, (int)gridDim.x);
 }
 
 __device__ __forceinline__ int64_t gnode(const Geo &g, int I, int J, int K)
@@ -900,16 +910,17 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
 // ---- tile kernel: element loop + ordered LDS accumulation + face slots ---------
 
 template <typename Tin, typename Tout, int OP>
-__global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
-                                               const Tin *__restrict__ v,
-                                               const double *__restrict__ gamma,
-                                               const double *__restrict__ src,
-                                               const uint8_t *__restrict__ nmask,
-                                               Tout *__restrict__ out, Tout *__restrict__ slots)
+__device__ __forceinline__ void elem_tile(const Geo &g, const Tin *__restrict__ x,
+                                          const Tin *__restrict__ v,
+                                          const double *__restrict__ gamma,
+                                          const double *__restrict__ src,
+                                          const uint8_t *__restrict__ nmask,
+                                          Tout *__restrict__ out, Tout *__restrict__ slots, int blk,
+                                          int nblk)
 {
     using T = Tin;
     __shared__ TileSmem<T> S;
-    const TileIdx t = tile_index(g);
+    const TileIdx t = tile_index(g, blk, nblk);
     stage<T, NF, OP != OP_RES>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
                  (OP == OP_RES) ? nullptr : S.v, &S.o[0][0]);
     __syncthreads();
@@ -980,6 +991,18 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
     }
 }
 
+template <typename Tin, typename Tout, int OP>
+__global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
+                                               const Tin *__restrict__ v,
+                                               const double *__restrict__ gamma,
+                                               const double *__restrict__ src,
+                                               const uint8_t *__restrict__ nmask,
+                                               Tout *__restrict__ out, Tout *__restrict__ slots)
+{
+    elem_tile<Tin, Tout, OP>(g, x, v, gamma, src, nmask, out, slots, (int)blockIdx.x,
+                             (int)gridDim.x);
+}
+
 // Tiles containing node coordinate I along one direction, in increasing order.
 // With one tile, the second entry repeats the first (a valid address for
 // unrolled loads whose term is dropped).
@@ -1033,12 +1056,13 @@ __device__ __forceinline__ void sum_slots5(const Geo &g, const T *__restrict__ s
 
 // Sum the slot partials of nodes shared between tiles, in a fixed tile order.
 template <typename Tv, typename Tout, int NV, int OP>
-__global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__ slots,
-                                                 const uint8_t *__restrict__ nmask,
-                                                 const Tv *__restrict__ v, Tout *__restrict__ out)
+__device__ __forceinline__ void combine_nodes(const Geo &g, const Tout *__restrict__ slots,
+                                              const uint8_t *__restrict__ nmask,
+                                              const Tv *__restrict__ v, Tout *__restrict__ out,
+                                              unsigned blk)
 {
     const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-    const int64_t gn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gn = (int64_t)blk * blockDim.x + threadIdx.x;
     if (gn >= nn) return;
     const int I = (int)(gn % (g.nx + 1));
     const int64_t r = gn / (g.nx + 1);
@@ -1085,6 +1109,14 @@ __global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__
     }
 }
 
+template <typename Tv, typename Tout, int NV, int OP>
+__global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__ slots,
+                                                 const uint8_t *__restrict__ nmask,
+                                                 const Tv *__restrict__ v, Tout *__restrict__ out)
+{
+    combine_nodes<Tv, Tout, NV, OP>(g, slots, nmask, v, out, blockIdx.x);
+}
+
 // The shared-node pass fused with one damped block-Jacobi sweep of the
 // multigrid smoother: t = J x is completed per node exactly as k_combine does
 // (rows of a node inside one tile were written to t by the element pass), and
@@ -1092,15 +1124,16 @@ __global__ __launch_bounds__(256) void k_combine(Geo g, const Tout *__restrict__
 // once, so t is never written for shared nodes nor read back.  Each thread
 // reads and writes only its own node of x.
 template <typename T, int OP>
-__global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restrict__ slots,
-                                                        const uint8_t *__restrict__ nmask,
-                                                        const T *__restrict__ t,
-                                                        const T *__restrict__ D,
-                                                        const T *__restrict__ b, T *x, T omega)
+__device__ __forceinline__ void combine_smooth_nodes(const Geo &g, const T *__restrict__ slots,
+                                                     const uint8_t *__restrict__ nmask,
+                                                     const T *__restrict__ t,
+                                                     const T *__restrict__ D,
+                                                     const T *__restrict__ b, T *x, T omega,
+                                                     unsigned blk)
 {
     const int64_t nn = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     __shared__ T sD[256 * 25];
-    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const int64_t n0 = (int64_t)blk * 256;
     const T *Dn = stage_blocks256(D, n0, nn, sD);
     const int64_t gn = n0 + threadIdx.x;
     if (gn >= nn) return;
@@ -1134,6 +1167,16 @@ __global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restri
             acc += (OP == OP_JTV ? Dn[c * NF + a] : Dn[a * NF + c]) * rr[c];
         x[NF * gn + a] += omega * acc;
     }
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_combine_smooth(Geo g, const T *__restrict__ slots,
+                                                        const uint8_t *__restrict__ nmask,
+                                                        const T *__restrict__ t,
+                                                        const T *__restrict__ D,
+                                                        const T *__restrict__ b, T *x, T omega)
+{
+    combine_smooth_nodes<T, OP>(g, slots, nmask, t, D, b, x, omega, blockIdx.x);
 }
 
 // ---- design derivative: one output per element, no scatter ---------------------
@@ -1422,6 +1465,50 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
     }
 }
 
+// ---- batched launches: the kernels above over a table of problems -------------
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(NTHR) void kb_elem_jv(const BElem<Tin, Tout> *__restrict__ tab,
+                                                   const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BElem<Tin, Tout> &a = tab[e];
+    const int b0 = off[e];
+    elem_tile<Tin, Tout, OP_JV>(a.g, a.x, a.v, a.gamma, a.s, a.nmask, a.out, a.slots,
+                                (int)blockIdx.x - b0, off[e + 1] - b0);
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void kb_combine_jv(const BElem<Tin, Tout> *__restrict__ tab,
+                                                     const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BElem<Tin, Tout> &a = tab[e];
+    combine_nodes<Tin, Tout, NF, OP_JV>(a.g, a.slots, a.nmask, a.v, a.out,
+                                        blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHR) void kb_elem_smooth(const BElemSmooth<T> *__restrict__ tab,
+                                                       const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BElemSmooth<T> &a = tab[e];
+    const int b0 = off[e];
+    elem_tile<T, T, OP_JV>(a.g, a.xs, (const T *)a.x, a.gamma, a.s, a.nmask, a.t, a.slots,
+                           (int)blockIdx.x - b0, off[e + 1] - b0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_combine_smooth(const BElemSmooth<T> *__restrict__ tab,
+                                                         const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BElemSmooth<T> &a = tab[e];
+    combine_smooth_nodes<T, OP_JV>(a.g, a.slots, a.nmask, a.t, a.D, a.b, a.x, a.omega,
+                                   blockIdx.x - (unsigned)off[e]);
+}
+
 }  // namespace
 
 // ---- assembled operator of a small grid (coarsest multigrid level) -----------------
@@ -1666,5 +1753,54 @@ hipError_t launch_probe_products(const Geo &g, const double *x, const double *ga
                        st, g, (const double *)Je, nmask, probe_out);
     return hipGetLastError();
 }
+
+// ---- batched launchers ---------------------------------------------------------------
+
+template <typename Tin, typename Tout>
+hipError_t blaunch_elem_jv(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_elem_jv<Tin, Tout>), dim3((unsigned)L.blocks), dim3(NTHR), 0, st,
+                       (const BElem<Tin, Tout> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Tout>
+hipError_t blaunch_combine_jv(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_combine_jv<Tin, Tout>), dim3((unsigned)L.blocks), dim3(256), 0, st,
+                       (const BElem<Tin, Tout> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t blaunch_elem_smooth_pass(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_elem_smooth<T>), dim3((unsigned)L.blocks), dim3(NTHR), 0, st,
+                       (const BElemSmooth<T> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t blaunch_combine_smooth(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_combine_smooth<T>), dim3((unsigned)L.blocks), dim3(256), 0, st,
+                       (const BElemSmooth<T> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+
+template hipError_t blaunch_elem_jv<double, double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_elem_jv<float, double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_elem_jv<float, float>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_combine_jv<double, double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_combine_jv<float, double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_combine_jv<float, float>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_elem_smooth_pass<double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_elem_smooth_pass<float>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_combine_smooth<double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_combine_smooth<float>(const BLaunch &, hipStream_t);
 
 }  // namespace fe

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -169,6 +170,39 @@ void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
 struct SolverWs;
+struct Mg;
+struct BatchEngine;
+
+// One FGMRES solve A x = b handed to the batch engine (lockstep Krylov
+// iterations over all solves in flight; fe_batch.cpp).  The caller fills the
+// inputs, keeps every buffer alive and untouched until batch_fgmres returns.
+struct BJob {
+    fe_problem *p = nullptr;
+    Mg *mg = nullptr;                 // multigrid hierarchy, set up for this Newton step
+    bool mixed = false;               // FP32 V-cycle and J z (GMRES-IR), FP64 otherwise
+    const double *b = nullptr;        // right-hand side
+    double *x = nullptr;              // solution (set to 0 first)
+    const double *xlin = nullptr;     // linearisation state
+    const float *x32 = nullptr;       // its FP32 copy (mixed)
+    const double *gamma = nullptr, *s = nullptr;
+    double *V = nullptr, *Z = nullptr, *tmp = nullptr, *partial = nullptr;
+    float *Z32 = nullptr;
+    int64_t n = 0;
+    int m = 0, max_its = 0, n_refine = 0;
+    double rtol = 0.0;
+    hipEvent_t ready = nullptr;       // recorded on the caller's stream at submission
+    // results
+    int rc = 0, its = 0;
+    bool converged = false, done = false;
+    double res_true = 0.0;
+    std::string error;
+};
+int batch_engine_create(int device, BatchEngine **out);
+void batch_engine_destroy(BatchEngine *E);
+// Solve job on the engine; blocks until it is finished (its work on the device
+// complete).  st: the caller's stream, on which the inputs were produced.
+int batch_fgmres(BatchEngine *E, BJob *job, hipStream_t st);
+void batch_engine_stats(const BatchEngine *E, uint64_t *steps, uint64_t *launches);
 
 // Device / host memory source of a problem: hipMalloc by default, or a
 // sub-allocator over a pre-allocated HBM arena (the solve server).
@@ -205,6 +239,7 @@ struct fe_problem {
     double *partial = nullptr;    // reduction partials, 66 * RED_BLOCKS
     double *scal = nullptr;       // device scalars
     fe::SolverWs *ws = nullptr;    // Newton/FGMRES workspace (allocated on first solve)
+    fe::BatchEngine *batch = nullptr; // if set, Newton's multigrid FGMRES solves run on it
     fe::Allocator *alloc = nullptr; // memory source of this problem's buffers
     // Element-pass timer of fe_jvp (instrumentation, off by default): start/stop
     // event pairs, timer_n of them recorded since the last read.

@@ -9,6 +9,7 @@
 // Coarse grids halve the element count in every direction; coarse node
 // (I,J,K) coincides with fine node (2I,2J,2K).  Prolongation is trilinear
 // interpolation, restriction its transpose (weights 1, 1/2, 1/4, 1/8).
+#include "fe_batch.h"
 #include "fe_internal.h"
 
 namespace fe {
@@ -64,14 +65,13 @@ __global__ void k_inject(int ncx, int ncy, int ncz, int nfx, int nfy, int nfz,
 // in flight together (a loop that skips them issues one neighbour at a time);
 // the sum keeps the dz, dy, dx order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, int nfx, int nfy,
-                                                  int nfz, const T *__restrict__ b,
-                                                  const T *__restrict__ t,
-                                                  const uint8_t *__restrict__ cmask,
-                                                  T *__restrict__ bc)
+__device__ __forceinline__ void restrict_dofs(int ncx, int ncy, int ncz, int nfx, int nfy, int nfz,
+                                              const T *__restrict__ b, const T *__restrict__ t,
+                                              const uint8_t *__restrict__ cmask, T *__restrict__ bc,
+                                              unsigned blk)
 {
     const int64_t nn = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blk * blockDim.x + threadIdx.x;
     if (q >= NF * nn) return;
     const int64_t n = q / NF;
     const int f = (int)(q - NF * n);
@@ -106,25 +106,34 @@ __global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, int
     bc[q] = ((cmask[n] >> f) & 1) ? T(0) : acc;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(int ncx, int ncy, int ncz, int nfx, int nfy,
+                                                  int nfz, const T *__restrict__ b,
+                                                  const T *__restrict__ t,
+                                                  const uint8_t *__restrict__ cmask,
+                                                  T *__restrict__ bc)
+{
+    restrict_dofs<T>(ncx, ncy, ncz, nfx, nfy, nfz, b, t, cmask, bc, blockIdx.x);
+}
+
 // The restriction above fused with the first smoothing sweep of the coarse
 // level, which starts from x_c = 0: x_c = omega D_c^{-1} b_c (D_c^{-T} when
 // TR).  A workgroup of 255 threads covers the 5 DOFs of 51 coarse nodes; b_c
 // of a node reaches its other four threads through LDS.  Both results are
 // bitwise those of k_restrict followed by k_smooth (same terms, same order).
 template <typename T, bool TR>
-__global__ __launch_bounds__(255) void k_restrict_smooth(int ncx, int ncy, int ncz, int nfx,
-                                                         int nfy, int nfz, const T *__restrict__ b,
-                                                         const T *__restrict__ t,
-                                                         const uint8_t *__restrict__ cmask,
-                                                         T *__restrict__ bc,
-                                                         const T *__restrict__ Dc,
-                                                         T *__restrict__ xc, T omega)
+__device__ __forceinline__ void restrict_smooth_nodes(int ncx, int ncy, int ncz, int nfx, int nfy,
+                                                      int nfz, const T *__restrict__ b,
+                                                      const T *__restrict__ t,
+                                                      const uint8_t *__restrict__ cmask,
+                                                      T *__restrict__ bc, const T *__restrict__ Dc,
+                                                      T *__restrict__ xc, T omega, unsigned blk)
 {
     __shared__ T sb[255];
     const int64_t nn = (int64_t)(ncx + 1) * (ncy + 1) * (ncz + 1);
     const int lq = (int)threadIdx.x;
     const int ln = lq / NF, f = lq - NF * ln;
-    const int64_t n = (int64_t)blockIdx.x * 51 + ln;
+    const int64_t n = (int64_t)blk * 51 + ln;
     const bool valid = n < nn;
     T val = T(0);
     if (valid) {
@@ -169,16 +178,30 @@ __global__ __launch_bounds__(255) void k_restrict_smooth(int ncx, int ncy, int n
     xc[NF * n + f] = omega * acc;
 }
 
+template <typename T, bool TR>
+__global__ __launch_bounds__(255) void k_restrict_smooth(int ncx, int ncy, int ncz, int nfx,
+                                                         int nfy, int nfz, const T *__restrict__ b,
+                                                         const T *__restrict__ t,
+                                                         const uint8_t *__restrict__ cmask,
+                                                         T *__restrict__ bc,
+                                                         const T *__restrict__ Dc,
+                                                         T *__restrict__ xc, T omega)
+{
+    restrict_smooth_nodes<T, TR>(ncx, ncy, ncz, nfx, nfy, nfz, b, t, cmask, bc, Dc, xc, omega,
+                                 blockIdx.x);
+}
+
 // x += P xc on unprescribed fine DOFs (trilinear interpolation); one thread
 // per fine DOF.  The up to 8 coarse parents are unrolled (along an even index
 // the parent repeats with its term dropped) so that their loads issue together.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy,
-                                                     const T *__restrict__ xc,
-                                                     const uint8_t *__restrict__ fmask, T *__restrict__ x)
+__device__ __forceinline__ void prolong_add_dofs(int nfx, int nfy, int nfz, int ncx, int ncy,
+                                                 const T *__restrict__ xc,
+                                                 const uint8_t *__restrict__ fmask,
+                                                 T *__restrict__ x, unsigned blk)
 {
     const int64_t nn = (int64_t)(nfx + 1) * (nfy + 1) * (nfz + 1);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)blk * blockDim.x + threadIdx.x;
     if (q >= NF * nn) return;
     const int64_t n = q / NF;
     const int f = (int)(q - NF * n);
@@ -206,6 +229,14 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, 
     x[q] = ((m >> f) & 1) ? xq : xq + wi * wj * wk * acc;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, int ncx, int ncy,
+                                                     const T *__restrict__ xc,
+                                                     const uint8_t *__restrict__ fmask, T *__restrict__ x)
+{
+    prolong_add_dofs<T>(nfx, nfy, nfz, ncx, ncy, xc, fmask, x, blockIdx.x);
+}
+
 // out = A v (A^T v when TR) for an assembled 27-point block stencil
 // S[((d 5 + g) 5 + f) nn + N] (entry (N g, N + offset(d) f)).  A block of 9
 // waves computes 64 output DOFs (node index fastest, so that stencil loads
@@ -215,13 +246,14 @@ __global__ __launch_bounds__(256) void k_prolong_add(int nfx, int nfy, int nfz, 
 // (M f, N g) sits in row M at the opposite offset 26 - d.  Neighbours outside
 // the grid load a clamped node and drop the term.
 template <typename T, bool TR>
-__global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, const T *__restrict__ S,
-                                                       const T *__restrict__ v, T *__restrict__ out)
+__device__ __forceinline__ void stencil_apply_dofs(int nx, int ny, int nz, const T *__restrict__ S,
+                                                   const T *__restrict__ v, T *__restrict__ out,
+                                                   unsigned blk)
 {
     __shared__ T part[9][64];
     const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t q = (int64_t)blk * 64 + lane;
     const bool live = q < NF * nn;
     const int g = live ? (int)(q / nn) : 0;
     const int64_t N = live ? q - (int64_t)g * nn : 0;
@@ -251,6 +283,13 @@ __global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, c
         for (int w = 1; w < 9; ++w) sum += part[w][lane];
         out[NF * N + g] = sum;
     }
+}
+
+template <typename T, bool TR>
+__global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, const T *__restrict__ S,
+                                                       const T *__restrict__ v, T *__restrict__ out)
+{
+    stencil_apply_dofs<T, TR>(nx, ny, nz, S, v, out, blockIdx.x);
 }
 
 // ---- coarsest level: explicit inverse from the band LU factors ---------------
@@ -436,14 +475,15 @@ __global__ __launch_bounds__(CI_T) void k_coarse_inverse(int n, int kl, int w, c
 constexpr int CA_B = 64;
 
 template <typename T, bool TR>
-__global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *__restrict__ X,
-                                                           const int *__restrict__ fidx,
-                                                           const T *__restrict__ b, double *__restrict__ P)
+__device__ __forceinline__ void coarse_apply_tile(int n, const double *__restrict__ X,
+                                                  const int *__restrict__ fidx,
+                                                  const T *__restrict__ b, double *__restrict__ P,
+                                                  unsigned bx, unsigned by)
 {
     __shared__ double tile[4][CA_B + 1];
     __shared__ double prod[CA_B][CA_B + 1];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i0 = blockIdx.x * CA_B, j0 = blockIdx.y * CA_B;
+    const int i0 = bx * CA_B, j0 = by * CA_B;
     if (!TR) {
         const int i = i0 + lane;
         const int ic = i < n ? i : n - 1;
@@ -458,7 +498,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *
         tile[q][lane] = acc;
         __syncthreads();
         if (q == 0 && i < n)
-            P[(int64_t)blockIdx.y * n + i] = ((tile[0][lane] + tile[1][lane]) + tile[2][lane]) + tile[3][lane];
+            P[(int64_t)by * n + i] = ((tile[0][lane] + tile[1][lane]) + tile[2][lane]) + tile[3][lane];
     } else {
         const int j = j0 + lane;
         const int jc = j < n ? j : n - 1;
@@ -475,18 +515,27 @@ __global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *
             const int i = i0 + threadIdx.x;
             double acc = 0.0;
             for (int l = 0; l < CA_B; ++l) acc += prod[threadIdx.x][l];
-            if (i < n) P[(int64_t)blockIdx.y * n + i] = acc;
+            if (i < n) P[(int64_t)by * n + i] = acc;
         }
     }
 }
 
+template <typename T, bool TR>
+__global__ __launch_bounds__(256) void k_coarse_apply_part(int n, const double *__restrict__ X,
+                                                           const int *__restrict__ fidx,
+                                                           const T *__restrict__ b, double *__restrict__ P)
+{
+    coarse_apply_tile<T, TR>(n, X, fidx, b, P, blockIdx.x, blockIdx.y);
+}
+
 // Pass 2 over the full vector (nfull DOFs; pos: full -> free index, -1 when prescribed).
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_sum(int nfull, int n, int nc, const int *__restrict__ pos,
-                                                          const double *__restrict__ P,
-                                                          const T *__restrict__ b, T *__restrict__ x)
+__device__ __forceinline__ void coarse_apply_rows(int nfull, int n, int nc, const int *__restrict__ pos,
+                                                  const double *__restrict__ P,
+                                                  const T *__restrict__ b, T *__restrict__ x,
+                                                  unsigned blk)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blk * blockDim.x + threadIdx.x;
     if (i >= nfull) return;
     const int r = pos[i];
     if (r < 0) {
@@ -497,6 +546,14 @@ __global__ __launch_bounds__(256) void k_coarse_apply_sum(int nfull, int n, int 
 #pragma unroll 8
     for (int c = 0; c < nc; ++c) acc += P[(int64_t)c * n + r];
     x[i] = (T)acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_sum(int nfull, int n, int nc, const int *__restrict__ pos,
+                                                          const double *__restrict__ P,
+                                                          const T *__restrict__ b, T *__restrict__ x)
+{
+    coarse_apply_rows<T>(nfull, n, nc, pos, P, b, x, blockIdx.x);
 }
 
 // Nodal diagonal blocks of an assembled level from its stencil: D[n 25 + g 5 + f]
@@ -516,12 +573,12 @@ __global__ __launch_bounds__(256) void k_stencil_diag(int64_t nn, const double *
 // ACC = false overwrites x.
 // Launched with 256 threads per workgroup (the block staging assumes it).
 template <typename T, bool TR, bool ACC>
-__global__ __launch_bounds__(256) void k_smooth(const T *__restrict__ D, const T *__restrict__ b,
-                                                const T *__restrict__ t, T *__restrict__ x,
-                                                int64_t nn, T omega)
+__device__ __forceinline__ void smooth_nodes(const T *__restrict__ D, const T *__restrict__ b,
+                                             const T *__restrict__ t, T *__restrict__ x, int64_t nn,
+                                             T omega, unsigned blk)
 {
     __shared__ T sD[256 * 25];
-    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const int64_t n0 = (int64_t)blk * 256;
     const T *Dn = stage_blocks256(D, n0, nn, sD);
     const int64_t n = n0 + threadIdx.x;
     if (n >= nn) return;
@@ -538,6 +595,84 @@ __global__ __launch_bounds__(256) void k_smooth(const T *__restrict__ D, const T
         else
             x[NF * n + a] = omega * acc;
     }
+}
+
+template <typename T, bool TR, bool ACC>
+__global__ __launch_bounds__(256) void k_smooth(const T *__restrict__ D, const T *__restrict__ b,
+                                                const T *__restrict__ t, T *__restrict__ x,
+                                                int64_t nn, T omega)
+{
+    smooth_nodes<T, TR, ACC>(D, b, t, x, nn, omega, blockIdx.x);
+}
+
+// ---- batched launches: the kernels above over a table of problems -------------
+
+template <typename T>
+__global__ __launch_bounds__(576) void kb_stencil(const BStencil<T> *__restrict__ tab,
+                                                  const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BStencil<T> &a = tab[e];
+    stencil_apply_dofs<T, false>(a.nx, a.ny, a.nz, a.S, a.v, a.out, blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T, bool ACC>
+__global__ __launch_bounds__(256) void kb_smooth(const BSmooth<T> *__restrict__ tab,
+                                                 const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BSmooth<T> &a = tab[e];
+    smooth_nodes<T, false, ACC>(a.D, a.b, a.t, a.x, a.nn, a.omega, blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_restrict(const BRestrict<T> *__restrict__ tab,
+                                                   const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BRestrict<T> &a = tab[e];
+    restrict_dofs<T>(a.ncx, a.ncy, a.ncz, a.nfx, a.nfy, a.nfz, a.b, a.t, a.cmask, a.bc,
+                     blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(255) void kb_restrict_smooth(const BRestrict<T> *__restrict__ tab,
+                                                          const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BRestrict<T> &a = tab[e];
+    restrict_smooth_nodes<T, false>(a.ncx, a.ncy, a.ncz, a.nfx, a.nfy, a.nfz, a.b, a.t, a.cmask,
+                                    a.bc, a.Dc, a.xc, a.omega, blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_prolong(const BProlong<T> *__restrict__ tab,
+                                                  const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BProlong<T> &a = tab[e];
+    prolong_add_dofs<T>(a.nfx, a.nfy, a.nfz, a.ncx, a.ncy, a.xc, a.fmask, a.x,
+                        blockIdx.x - (unsigned)off[e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_coarse_part(const BCoarse<T> *__restrict__ tab,
+                                                      const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BCoarse<T> &a = tab[e];
+    const unsigned lb = blockIdx.x - (unsigned)off[e];
+    coarse_apply_tile<T, false>(a.n, a.X, a.fidx, a.b, a.P, lb % (unsigned)a.nt,
+                                lb / (unsigned)a.nt);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_coarse_sum(const BCoarse<T> *__restrict__ tab,
+                                                     const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BCoarse<T> &a = tab[e];
+    coarse_apply_rows<T>(a.nfull, a.n, a.nt, a.pos, a.P, a.b, a.x, blockIdx.x - (unsigned)off[e]);
 }
 
 }  // namespace
@@ -692,5 +827,46 @@ hipError_t mg_coarse_apply(int nfull, int m, const double *X, const int *fidx, c
 FE_MG_INST(double)
 FE_MG_INST(float)
 #undef FE_MG_INST
+
+// ---- batched launchers ---------------------------------------------------------------
+
+#define FE_BLAUNCH(NAME, KERNEL, ARGS, THREADS)                                                  \
+    template <typename T>                                                                      \
+    hipError_t NAME(const BLaunch &L, hipStream_t st)                                          \
+    {                                                                                          \
+        if (L.blocks <= 0) return hipSuccess;                                                  \
+        hipLaunchKernelGGL(KERNEL, dim3((unsigned)L.blocks), dim3(THREADS), 0, st,             \
+                           (const ARGS *)L.tab, L.off, L.n);                                    \
+        return hipGetLastError();                                                              \
+    }
+FE_BLAUNCH(blaunch_stencil, kb_stencil<T>, BStencil<T>, 576)
+FE_BLAUNCH(blaunch_restrict, kb_restrict<T>, BRestrict<T>, 256)
+FE_BLAUNCH(blaunch_restrict_smooth, kb_restrict_smooth<T>, BRestrict<T>, 255)
+FE_BLAUNCH(blaunch_prolong, kb_prolong<T>, BProlong<T>, 256)
+FE_BLAUNCH(blaunch_coarse_part, kb_coarse_part<T>, BCoarse<T>, 256)
+FE_BLAUNCH(blaunch_coarse_sum, kb_coarse_sum<T>, BCoarse<T>, 256)
+#undef FE_BLAUNCH
+
+template <typename T, bool ACC>
+hipError_t blaunch_smooth(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((kb_smooth<T, ACC>), dim3((unsigned)L.blocks), dim3(256), 0, st,
+                       (const BSmooth<T> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+
+#define FE_BMG_INST(T)                                                                         \
+    template hipError_t blaunch_stencil<T>(const BLaunch &, hipStream_t);                      \
+    template hipError_t blaunch_restrict<T>(const BLaunch &, hipStream_t);                     \
+    template hipError_t blaunch_restrict_smooth<T>(const BLaunch &, hipStream_t);              \
+    template hipError_t blaunch_prolong<T>(const BLaunch &, hipStream_t);                      \
+    template hipError_t blaunch_coarse_part<T>(const BLaunch &, hipStream_t);                  \
+    template hipError_t blaunch_coarse_sum<T>(const BLaunch &, hipStream_t);                   \
+    template hipError_t blaunch_smooth<T, false>(const BLaunch &, hipStream_t);                \
+    template hipError_t blaunch_smooth<T, true>(const BLaunch &, hipStream_t);
+FE_BMG_INST(double)
+FE_BMG_INST(float)
+#undef FE_BMG_INST
 
 }  // namespace fe

@@ -1,5 +1,10 @@
 // Continuous-batching solve server.
 //
+// Two modes.  Default: each running request's whole Newton solve runs on its
+// worker's stream.  Batched (FE_SERVE_BATCHED): the workers run set-up and line
+// searches, and hand every linear solve to one lockstep engine (fe_batch.cpp)
+// whose FGMRES steps launch each kernel once over all running requests.
+//
 // One device arena of hbm_budget_bytes is allocated at creation.  An admitted
 // request takes one contiguous block of the arena, sized by its predicted
 // footprint, and its whole working set (problem handle, solver workspace,
@@ -190,6 +195,7 @@ struct fe_server {
     uint64_t next_ticket = 1;
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point t0;
+    fe::BatchEngine *engine = nullptr;  // batched mode: lockstep FGMRES of all requests
 
     double now() const
     {
@@ -216,6 +222,7 @@ int run_request(fe_server *S, Request *r, hipStream_t st)
     fe_problem *p = nullptr;
     int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &mem, st, &p);
     if (rc) return rc;
+    p->batch = S->engine;
     const int64_t ne = p->ne, ndof = p->ndof;
     double *g = nullptr, *s = nullptr, *x = nullptr;
     hipError_t e = dalloc(p, &g, sizeof(double) * ne);
@@ -320,8 +327,17 @@ extern "C" {
 
 int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out)
 {
-    if (!out || max_active < 1 || max_active > 64 || hbm_budget_bytes < ((size_t)1 << 20)) {
-        set_error("serve_create: need out != NULL, 1 <= max_active <= 64, budget >= 1 MiB");
+    return serve_create_ex(hbm_budget_bytes, max_active, 0, out);
+}
+
+int serve_create_ex(size_t hbm_budget_bytes, int max_active, int flags, fe_server **out)
+{
+    const bool batched = (flags & FE_SERVE_BATCHED) != 0;
+    const int cap = batched ? 256 : 64;
+    if (!out || max_active < 1 || max_active > cap || hbm_budget_bytes < ((size_t)1 << 20) ||
+        (flags & ~FE_SERVE_BATCHED)) {
+        set_error("serve_create: need out != NULL, 1 <= max_active <= 64 (256 batched), "
+                  "budget >= 1 MiB, known flags");
         return FE_EINVAL;
     }
     *out = nullptr;
@@ -339,6 +355,13 @@ int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out)
     }
     S->budget = S->arena.size();
     S->max_active = max_active;
+    if (batched) {
+        const int rc = batch_engine_create(S->device, &S->engine);
+        if (rc) {
+            delete S;
+            return rc;
+        }
+    }
     S->t0 = std::chrono::steady_clock::now();
     for (int i = 0; i < max_active; ++i) S->workers.emplace_back(worker_main, S);
     *out = S;
@@ -454,7 +477,18 @@ int serve_destroy(fe_server *S)
     }
     S->cv.notify_all();
     for (auto &t : S->workers) t.join();
+    batch_engine_destroy(S->engine);
     delete S;
+    return FE_OK;
+}
+
+int serve_engine_stats(fe_server *S, uint64_t *steps, uint64_t *launches)
+{
+    if (!S) {
+        set_error("serve_engine_stats: NULL server");
+        return FE_EINVAL;
+    }
+    batch_engine_stats(S->engine, steps, launches);
     return FE_OK;
 }
 

@@ -467,8 +467,36 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         FE_CHECK_HIP(launch_axpby(n, -1.0, R, 0.0, w->rhs, st));
         FE_CHECK_HIP(hipEventRecord(e1, st));
         LinStats ls;
-        rc = fgmres(p, L, w->rhs, w->delta, opts.rtol_lin, opts.restart, opts.max_lin,
-                    mixed ? opts.n_refine : 0, st, &ls, opts.verbose);
+        if (p->batch && pc == FE_PC_MULTIGRID && opts.restart <= 64) {
+            BJob job;
+            job.p = p;
+            job.mg = w->mg;
+            job.mixed = mixed;
+            job.b = w->rhs;
+            job.x = w->delta;
+            job.xlin = x;
+            job.x32 = w->x32;
+            job.gamma = gamma;
+            job.s = s_elem;
+            job.V = w->V;
+            job.Z = w->Z;
+            job.Z32 = w->Z32;
+            job.tmp = w->tmp;
+            job.partial = p->partial;
+            job.n = n;
+            job.m = opts.restart;
+            job.max_its = opts.max_lin;
+            job.n_refine = mixed ? opts.n_refine : 0;
+            job.rtol = opts.rtol_lin;
+            job.ready = w->ev[6];
+            rc = batch_fgmres(p->batch, &job, st);
+            ls.its = job.its;
+            ls.converged = job.converged;
+            ls.res_true = job.res_true;
+        } else {
+            rc = fgmres(p, L, w->rhs, w->delta, opts.rtol_lin, opts.restart, opts.max_lin,
+                        mixed ? opts.n_refine : 0, st, &ls, opts.verbose);
+        }
         if (rc) {
             rep.status = rc;
             fill_report(report, rep);

@@ -27,7 +27,10 @@ EXPORTS = [
     "fe_solve_opts_default", "newton_solve", "fe_adjoint_solve", "fe_block_diagonal",
     "fe_line_search_lambda", "fe_solve_footprint_bytes", "serve_create", "serve_submit",
     "serve_poll", "serve_times", "serve_error", "serve_destroy", "fe_last_error", "fe_version",
+    "serve_create_ex", "serve_engine_stats", "fe_jvp_batch_create", "fe_jvp_batch_run",
+    "fe_jvp_batch_destroy",
 ]
+FE_SERVE_BATCHED = 1
 
 
 class FeGrid(ctypes.Structure):
@@ -156,6 +159,11 @@ def lib() -> ctypes.CDLL:
         L.fe_solve_footprint_bytes.argtypes = [P(FeGrid), P(FeSolveOpts)]
         L.fe_solve_footprint_bytes.restype = i64
         L.serve_create.argtypes = [ctypes.c_size_t, i32, P(vp)]
+        L.serve_create_ex.argtypes = [ctypes.c_size_t, i32, i32, P(vp)]
+        L.serve_engine_stats.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
+        L.fe_jvp_batch_create.argtypes = [i32, P(vp), i32, P(vp), P(vp), P(vp), P(vp), P(vp), P(vp)]
+        L.fe_jvp_batch_run.argtypes = [vp, vp]
+        L.fe_jvp_batch_destroy.argtypes = [vp]
         L.serve_submit.argtypes = [vp, P(FeGrid), P(FePhys), vp, vp, P(FeSolveOpts),
                                    P(ctypes.c_uint64)]
         L.serve_submit_x0.argtypes = [vp, P(FeGrid), P(FePhys), vp, vp, vp, P(FeSolveOpts),
@@ -424,6 +432,52 @@ def fe_solve_footprint_bytes(nx, ny, nz, h=1.0, opts: Optional[FeSolveOpts] = No
     return int(lib().fe_solve_footprint_bytes(ctypes.byref(g), ctypes.byref(opts) if opts else None))
 
 
+class JvpBatch:
+    """J v of several problems in one batched launch (``fe_jvp_batch_*``).
+
+    ``probs``: distinct :class:`Problem` objects; ``x``, ``v``, ``out``: lists
+    of device tensors of one precision (float64 or float32); ``gamma``, ``s``:
+    lists of float64 device tensors.  The table holds the tensors' addresses:
+    keep them alive (and in place) while the batch is used."""
+
+    def __init__(self, probs, x, gamma, s, v, out):
+        n = len(probs)
+        if not (len(x) == len(gamma) == len(s) == len(v) == len(out) == n) or n < 1:
+            raise ValueError("JvpBatch: lists of equal length >= 1 expected")
+        self.handle = None
+        prec = _prec_of(x[0])
+        dt = x[0].dtype
+        arr = ctypes.c_void_p * n
+        ptrs = {}
+        for name, lst, dty, size in (("x", x, dt, "n_dof"), ("v", v, dt, "n_dof"),
+                                     ("out", out, dt, "n_dof"),
+                                     ("gamma", gamma, torch.float64, "n_el"),
+                                     ("s", s, torch.float64, "n_el")):
+            ptrs[name] = arr(*[_ptr(t, dty, getattr(pr, size), f"{name}[{i}]").value
+                               for i, (t, pr) in enumerate(zip(lst, probs))])
+        ph = arr(*[pr.handle.value for pr in probs])
+        h = ctypes.c_void_p()
+        _check(lib().fe_jvp_batch_create(n, ph, prec, ptrs["x"], ptrs["gamma"], ptrs["s"],
+                                         ptrs["v"], ptrs["out"], ctypes.byref(h)),
+               "fe_jvp_batch_create")
+        self.handle = h
+        self._keep = (list(x), list(gamma), list(s), list(v), list(out))
+
+    def run(self, stream=None):
+        _check(lib().fe_jvp_batch_run(self.handle, _stream(stream)), "fe_jvp_batch_run")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().fe_jvp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def fe_version() -> str:
     return lib().fe_version().decode()
 
@@ -435,12 +489,24 @@ class Server:
     arrays, copied at submit); walls and the pressure pin are applied by the
     library and every solve starts from x = 0."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 4):
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 4, batched: bool = False):
+        """``batched``: run the requests' linear solves in lockstep, one launch
+        per kernel over all running requests (``FE_SERVE_BATCHED``)."""
+        self.handle = None
         h = ctypes.c_void_p()
-        _check(lib().serve_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_active),
-                                  ctypes.byref(h)), "serve_create")
+        _check(lib().serve_create_ex(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_active),
+                                     FE_SERVE_BATCHED if batched else 0, ctypes.byref(h)),
+               "serve_create_ex")
         self.handle = h
+        self.batched = batched
         self.n_dof = {}
+
+    def engine_stats(self):
+        """(lockstep steps, batched launches) of the batched engine so far."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().serve_engine_stats(self.handle, ctypes.byref(a), ctypes.byref(b)),
+               "serve_engine_stats")
+        return a.value, b.value
 
     def submit(self, nx, ny, nz, h, phys: FePhys, gamma, s, opts: Optional[FeSolveOpts] = None,
                allow_enomem=False, x0=None) -> int:
