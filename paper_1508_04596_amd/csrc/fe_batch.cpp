@@ -43,7 +43,7 @@ constexpr int MAXD = 64;         // depth bound of the V-cycle phase keys
 
 // launch kinds
 enum Kind {
-    K_FILL, K_CAST, K_AXPBY, K_SCALE, K_COMB64, K_COMB32, K_DOTS, K_REDUCE, K_UPDATE,
+    K_FILL, K_CAST, K_AXPBY, K_SCALE, K_COMB64, K_COMB32, K_DOTS, K_REDUCE, K_UPDATE, K_SCNORM,
     K_EJV_DD, K_CJV_DD, K_EJV_FD, K_CJV_FD, K_EJV_FF, K_CJV_FF,
     K_ESM_D, K_CSM_D, K_ESM_F, K_CSM_F,
     K_ST_D, K_ST_F, K_SM0_D, K_SM0_F, K_SM1_D, K_SM1_F,
@@ -54,7 +54,7 @@ enum Kind {
 using LaunchFn = hipError_t (*)(const BLaunch &, hipStream_t);
 const LaunchFn kLaunch[K_COUNT] = {
     blaunch_fill, blaunch_cast, blaunch_axpby, blaunch_scale, blaunch_comb<double>,
-    blaunch_comb<float>, blaunch_dots, blaunch_reduce, blaunch_update,
+    blaunch_comb<float>, blaunch_dots, blaunch_reduce, blaunch_update, blaunch_scale_norm,
     blaunch_elem_jv<double, double>, blaunch_combine_jv<double, double>,
     blaunch_elem_jv<float, double>, blaunch_combine_jv<float, double>,
     blaunch_elem_jv<float, float>, blaunch_combine_jv<float, float>,
@@ -263,8 +263,8 @@ void emit_norm_scale(Planner &P, int stage, const BJob &J, double *res, const do
     int nch, ept;
     bred_chunks(J.n, &nch, &ept);
     P.add(key(0, 0, stage), K_DOTS, BDots{w, nullptr, J.n, 0, 1, J.n, nch, ept, 1, J.partial}, nch);
-    P.add(key(0, 0, stage + 1), K_REDUCE, BReduce{J.partial, 1, nch, res + R_NRM2, res + R_BETA}, 1);
-    P.add(key(0, 0, stage + 2), K_SCALE, BScale{J.n, w, res + R_BETA, v}, belt_blocks(J.n));
+    P.add(key(0, 0, stage + 1), K_SCNORM,
+          BScaleNorm{J.partial, nch, J.n, w, v, res + R_NRM2, res + R_BETA}, belt_blocks(J.n));
 }
 
 }  // namespace
@@ -364,14 +364,14 @@ void BatchEngine::plan(Solve &S)
         const int ngrp = (k + BDOT_GROUP - 1) / BDOT_GROUP;
         const BDots d{vn, J.V, n, k, 0, n, nch, ept, ngrp, J.partial};
         P.add(key(3, 0, 10), K_DOTS, d, nch * ngrp);
-        P.add(key(3, 0, 11), K_REDUCE, BReduce{J.partial, k, nch, res + R_H1, nullptr}, 1);
+        P.add(key(3, 0, 11), K_REDUCE, BReduce{J.partial, k, nch, res + R_H1, nullptr}, k);
         P.add(key(3, 0, 12), K_UPDATE, BUpdate{vn, J.V, n, k, n, nch, ept, res + R_H1, nullptr}, nch);
         P.add(key(3, 0, 13), K_DOTS, d, nch * ngrp);
-        P.add(key(3, 0, 14), K_REDUCE, BReduce{J.partial, k, nch, res + R_H2, nullptr}, 1);
+        P.add(key(3, 0, 14), K_REDUCE, BReduce{J.partial, k, nch, res + R_H2, nullptr}, k);
         P.add(key(3, 0, 15), K_UPDATE, BUpdate{vn, J.V, n, k, n, nch, ept, res + R_H2, J.partial},
               nch);
-        P.add(key(3, 0, 16), K_REDUCE, BReduce{J.partial, 1, nch, res + R_NRM2, res + R_BETA}, 1);
-        P.add(key(3, 0, 17), K_SCALE, BScale{n, vn, res + R_BETA, vn}, belt_blocks(n));
+        P.add(key(3, 0, 16), K_SCNORM,
+              BScaleNorm{J.partial, nch, n, vn, vn, res + R_NRM2, res + R_BETA}, belt_blocks(n));
         break;
     }
     }

@@ -136,14 +136,15 @@ hipError_t blaunch_coarse_sum(const BLaunch &L, hipStream_t st);
 
 // ---- vectors and reductions (fe_batch.hip) ---------------------------------
 // Reductions split a problem's vector of n entries into nchunk chunks of
-// 256 * ept consecutive entries (ept >= 8, nchunk <= BRED_MAX_CHUNKS); the
-// chunking depends on n only, and partials are added in a fixed order, so a
-// problem's sums are the same in every batch.
+// 256 * ept consecutive entries (ept the smallest power of two that keeps
+// nchunk <= BRED_MAX_CHUNKS, so that small vectors still spread over many
+// workgroups); the chunking depends on n only, and partials are added in a
+// fixed order, so a problem's sums are the same in every batch.
 constexpr int BRED_MAX_CHUNKS = 1024;
 constexpr int BDOT_GROUP = 8;  // basis vectors per workgroup of a multi-dot
 inline void bred_chunks(int64_t n, int *nchunk, int *ept)
 {
-    int64_t e = 8;
+    int64_t e = 1;
     while ((n + 256 * e - 1) / (256 * e) > BRED_MAX_CHUNKS) e *= 2;
     *ept = (int)e;
     *nchunk = (int)std::max<int64_t>(1, (n + 256 * e - 1) / (256 * e));
@@ -187,7 +188,15 @@ struct BDots {  // partial[c nchunk + chunk] of <V_c, w> for c < k, and <w, w> a
     int nchunk, ept, ngrp;
     double *partial;
 };
-struct BReduce {  // out[c] = sum of the nchunk partials of column c < ncol; beta = sqrt(out[ncol-1])
+struct BScaleNorm {  // y = x / |x| with |x|^2 the sum of nchunk partials; nrm2, beta = |x|^2, |x|
+    const double *partial;
+    int nchunk;
+    int64_t n;
+    const double *x;
+    double *y, *nrm2, *beta;
+};
+struct BReduce {  // out[c] = sum of the nchunk partials of column c < ncol (one workgroup
+                  // per column); beta = sqrt(out[ncol-1])
     const double *partial;
     int ncol, nchunk;
     double *out, *beta;
@@ -212,5 +221,6 @@ hipError_t blaunch_comb(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_dots(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_reduce(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_update(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_scale_norm(const BLaunch &L, hipStream_t st);
 
 }  // namespace fe

@@ -124,22 +124,43 @@ __global__ __launch_bounds__(256) void kb_dots(const BDots *__restrict__ tab,
     }
 }
 
-// One workgroup per problem: the columns' sums over their chunks.
+// One workgroup per column: the column's sum over its chunks (chunk order
+// within each thread, then the fixed block order).
 __global__ __launch_bounds__(256) void kb_reduce(const BReduce *__restrict__ tab,
                                                  const int *__restrict__ off, int n)
 {
     __shared__ double red[4];
     const int e = batch_entry(off, n);
     const BReduce &a = tab[e];
-    for (int c = 0; c < a.ncol; ++c) {
-        double v = 0.0;
-        for (int i = threadIdx.x; i < a.nchunk; i += 256) v += a.partial[(int64_t)c * a.nchunk + i];
-        const double s = bblock_sum(v, red);
-        if (threadIdx.x == 0) {
-            a.out[c] = s;
-            if (a.beta && c == a.ncol - 1) a.beta[0] = sqrt(s);
-        }
+    const int c = (int)blockIdx.x - off[e];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < a.nchunk; i += 256) v += a.partial[(int64_t)c * a.nchunk + i];
+    const double s = bblock_sum(v, red);
+    if (threadIdx.x == 0) {
+        a.out[c] = s;
+        if (a.beta && c == a.ncol - 1) a.beta[0] = sqrt(s);
     }
+}
+
+// y = x / |x|: every workgroup adds the nchunk partials of |x|^2 in the same
+// fixed order (so all see the same norm); workgroup 0 also stores |x|^2 and |x|.
+__global__ __launch_bounds__(256) void kb_scale_norm(const BScaleNorm *__restrict__ tab,
+                                                     const int *__restrict__ off, int n)
+{
+    __shared__ double red[4];
+    const int e = batch_entry(off, n);
+    const BScaleNorm &a = tab[e];
+    const int lb = (int)blockIdx.x - off[e];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < a.nchunk; i += 256) v += a.partial[i];
+    const double s = bblock_sum(v, red);
+    const double beta = sqrt(s);
+    if (lb == 0 && threadIdx.x == 0) {
+        a.nrm2[0] = s;
+        a.beta[0] = beta;
+    }
+    const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+    if (i < a.n) a.y[i] = a.x[i] / beta;
 }
 
 // w -= sum_{c<k} h_c V_c over one chunk, then (optionally) the chunk's <w, w>.
@@ -186,6 +207,7 @@ FE_BVLAUNCH(blaunch_scale, kb_scale, BScale)
 FE_BVLAUNCH(blaunch_dots, kb_dots, BDots)
 FE_BVLAUNCH(blaunch_reduce, kb_reduce, BReduce)
 FE_BVLAUNCH(blaunch_update, kb_update, BUpdate)
+FE_BVLAUNCH(blaunch_scale_norm, kb_scale_norm, BScaleNorm)
 #undef FE_BVLAUNCH
 
 template <typename Tz>
