@@ -46,13 +46,13 @@ PEAK_HBM = 8.0e12
 # torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
 # 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
 # whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.88, 17217.19
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.56, 17217.13
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
-ELEM_TRAFFIC_SRC_SHA256 = "de63c7919908f8b5895116119979412e0bbb0d005a640343f16cdee546d8bcc1"
+ELEM_TRAFFIC_SRC_SHA256 = "b06d00ff2bb7f5cb58e56714e4709d240cb3a9439729e817ee654f723fe40e13"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
        "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
@@ -88,6 +88,11 @@ def main():
                     help="mean arrival rate of the serving trace (requests/s)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-max-active", type=int, default=8)
+    ap.add_argument("--serve-batched-max-active", type=int, default=256,
+                    help="worker slots of the batched (lockstep) server")
+    ap.add_argument("--serve-burst-rate", type=float, default=1000.0,
+                    help="arrival rate of the burst comparison (default vs batched server); 0 = skip")
+    ap.add_argument("--serve-burst-budget-gb", type=float, default=16.0)
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
                     help="workload: 2 = 64^3 (the reported line), 3 = 160x160x320 (the "
                          "paper's 41.6 M DOF mesh), 4 = 96^3")
@@ -201,8 +206,22 @@ def main():
 
     serve = None
     if args.serve_requests > 0:
+        # the configured trace on the default server (each request's solve on its
+        # worker's stream) and on the batched one (lockstep FGMRES, one launch per
+        # kernel over all running requests); then a burst that keeps many
+        # requests in flight, on both
         serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
                             args.serve_max_active, args.serve_rate)
+        serve["batched"] = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
+                                       args.serve_batched_max_active, args.serve_rate,
+                                       batched=True)
+        if args.serve_burst_rate > 0:
+            serve["burst"] = {
+                "default": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
+                                       args.serve_max_active, args.serve_burst_rate),
+                "batched": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
+                                       args.serve_batched_max_active, args.serve_burst_rate,
+                                       batched=True)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -236,16 +255,24 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0):
+_SERVE_PROBS = {}
+
+
+def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
     """Serving workload: n requests with Poisson arrivals (20/s by default), grids uniform
     over {16,24,32,48}^3, log10 Gr uniform in [3,5], 40 %-solid smoothed random
-    designs, mixed precision to 1e-8; latency = completion - arrival."""
+    designs, mixed precision to 1e-8; latency = completion - arrival.  ``batched``:
+    the lockstep server (one launch per kernel over all running requests)."""
     import time as _t
     reqs = inputs.serving_trace(n_requests=n, rate_per_s=rate, seed=4000)
-    probs = [inputs.request_problem(r) for r in reqs]
+    # the requests' grids, designs and Grashof numbers do not depend on the
+    # arrival rate (the arrival gaps are drawn first): build them once
+    if n not in _SERVE_PROBS:
+        _SERVE_PROBS[n] = [inputs.request_problem(r) for r in reqs]
+    probs = _SERVE_PROBS[n]
     opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
     lat, tickets, statuses = [], [], []
-    with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active) as srv:
+    with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active, batched=batched) as srv:
         t0 = _t.perf_counter()
         for r, pr in zip(reqs, probs):
             wait = t0 + r.arrival_s - _t.perf_counter()
@@ -257,11 +284,14 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0):
             rc, _, _ = srv.wait(t)
             statuses.append(rc)
         times = [srv.times(t) for t in tickets]
+        steps, launches = srv.engine_stats()
     lat = np.array([d - a for a, _, d in times])
     makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
     return {"requests": n, "rate_per_s": rate, "budget_gb": budget_gb, "max_active": max_active,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "solves_per_s": n / makespan, "all_converged": all(s == 0 for s in statuses),
+            "mode": "batched" if batched else "default",
+            "engine_steps": steps, "engine_launches": launches,
             "queue_wait_p50_s": float(np.percentile([b - a for a, b, _ in times], 50))}
 
 

@@ -294,12 +294,14 @@ void worker_main(fe_server *S)
                 r->error = "serve: no arena block for the request";
                 r->state = Q_DONE;
                 r->t_admit = r->t_done = S->now();
-                S->cv.notify_all();
                 continue;
             }
             S->reserved += r->footprint;
             r->state = Q_RUNNING;
             r->t_admit = S->now();
+            // idle workers all wait for the same condition, so one is woken per
+            // event; it passes the wake-up on while more requests are admissible
+            if (admissible(S) != S->queue.end()) S->cv.notify_one();
         }
         int rc = run_request(S, r, st);
         // the request's kernels and copies have finished (run_request ends with a
@@ -316,7 +318,7 @@ void worker_main(fe_server *S)
             r->state = Q_DONE;
             r->t_done = S->now();
         }
-        S->cv.notify_all();
+        S->cv.notify_one();
     }
     if (st) (void)hipStreamDestroy(st);
 }
@@ -417,7 +419,7 @@ int serve_submit_x0(fe_server *S, const fe_grid *grid, const fe_phys *phys,
     }
     S->reqs[raw->ticket] = std::move(r);
     S->queue.push_back(raw);
-    S->cv.notify_all();
+    S->cv.notify_one();
     return FE_OK;
 }
 
