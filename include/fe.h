@@ -229,6 +229,13 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
  * the identity in place of prescribed rows and columns.  D: device FP64[25*n_nodes]. */
 int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const double *s_elem,
                       double *D, hipStream_t stream);
+/* The same blocks evaluated in FP32 arithmetic from an FP32 state x (device
+ * float[n_dof]) into D (device float[25*n_nodes]): the blocks that a
+ * mixed-precision Newton step inverts in FP32 for its FP32 smoother (Sec.
+ * "Solving the linear systems"; the preconditioner's precision does not enter
+ * the FP64 residual that decides convergence). */
+int fe_block_diagonal_fp32(fe_problem *p, const float *x, const double *gamma,
+                           const double *s_elem, float *D, hipStream_t stream);
 
 /* The assembled Jacobian J(x) of a small problem, dense and row-major:
  * J_host[i * n_dof + j] = dR_i/dx_j (host FP64[n_dof * n_dof], written in

@@ -312,7 +312,23 @@ int fe_block_diagonal(fe_problem *p, const double *x, const double *gamma, const
         const size_t b = (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double);
         FE_CHECK_HIP(dalloc(p, &p->slots25, b));
     }
-    FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, D, p->slots25, stream));
+    FE_CHECK_HIP((launch_blockdiag<double>(p->geo, x, gamma, s_elem, p->nmask, D, p->slots25, stream)));
+    return FE_OK;
+}
+
+int fe_block_diagonal_fp32(fe_problem *p, const float *x, const double *gamma,
+                           const double *s_elem, float *D, hipStream_t stream)
+{
+    if (!p || !x || !gamma || !s_elem || !D) {
+        set_error("fe_block_diagonal_fp32: NULL argument");
+        return FE_EINVAL;
+    }
+    if (!p->slots25) {
+        const size_t b = (size_t)n_tiles(p->geo) * BOXN * 25 * sizeof(double);
+        FE_CHECK_HIP(dalloc(p, &p->slots25, b));
+    }
+    FE_CHECK_HIP((launch_blockdiag<float>(p->geo, x, gamma, s_elem, p->nmask, D,
+                                          reinterpret_cast<float *>(p->slots25), stream)));
     return FE_OK;
 }
 

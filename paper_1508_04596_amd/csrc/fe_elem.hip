@@ -1263,17 +1263,17 @@ __global__ __launch_bounds__(NTHR) void k_dRdgamma(Geo g, const double *__restri
 // ---- nodal 5x5 diagonal blocks of J -----------------------------------------------
 
 // Shape function of local node a and its physical gradient at Gauss point G.
-template <typename SGT>
-__device__ __forceinline__ void shape_at(const SGT &SG, int a, double h, double &N, double dN[3])
+template <typename T, typename SGT>
+__device__ __forceinline__ void shape_at(const SGT &SG, int a, T h, T &N, T dN[3])
 {
-    const double q = QG;
-    const double sgv[3] = {double(SG.sx), double(SG.sy), double(SG.sz)};
-    double f[3], sgn[3];
+    const T q = (T)QG;
+    const T sgv[3] = {T(SG.sx), T(SG.sy), T(SG.sz)};
+    T f[3], sgn[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double sg = sgv[d] * q;
-        sgn[d] = ((a >> d) & 1) ? 1.0 : -1.0;
-        f[d] = 0.5 * (1.0 + sgn[d] * sg);
+        const T sg = sgv[d] * q;
+        sgn[d] = ((a >> d) & 1) ? T(1) : T(-1);
+        f[d] = T(0.5) * (T(1) + sgn[d] * sg);
     }
     N = f[0] * f[1] * f[2];
     dN[0] = (sgn[0] / h) * f[1] * f[2];
@@ -1281,18 +1281,34 @@ __device__ __forceinline__ void shape_at(const SGT &SG, int a, double h, double 
     dN[2] = (sgn[2] / h) * f[0] * f[1];
 }
 
-// Corners per group of the block kernel: 2 measured 1.5x faster than the
-// per-corner evaluation of the directional derivatives (64^3: 400 -> 265 us,
-// 160x160x320: 10.3 -> 6.7 ms, with the shared-node pass); 1 corner per group
-// (fewest registers) 280 us / 7.0 ms; 4 corners 261 us / 6.6 ms but spills.
+// Corners per group of the block kernel, FP64 and FP32.  With the node box in
+// the accumulators' LDS, one FP64 corner per group (252 registers) lets two
+// waves share a SIMD; with 2 (322 registers, 1.5x faster than evaluating each
+// corner's derivatives separately) only one fits (64^3 / 160x160x320, blocks
+// and shared-node pass: 243 us / 6.15 ms with 1 corner, 297 us / 8.29 ms with 2,
+// 285 us / 7.89 ms with 4).
 #ifndef FE_BD_GROUP
-#define FE_BD_GROUP 2
+#define FE_BD_GROUP 1
 #endif
+#ifndef FE_BD_GROUP32
+#define FE_BD_GROUP32 2
+#endif
+template <typename T>
+struct BdCfg;
+template <>
+struct BdCfg<double> {
+    static constexpr int G = FE_BD_GROUP, WAVES = FE_BD_GROUP == 1 ? 2 : 1;
+};
+template <>
+struct BdCfg<float> {
+    static constexpr int G = FE_BD_GROUP32, WAVES = 2;
+};
 
 // State at one Gauss point: velocity, its gradient G[i][j] = d u_i / d x_j,
 // the strong momentum residual and the temperature gradient and residual.
+template <typename T>
 struct BdState {
-    double u[3], G[3][3], rM[3], gT[3], rT;
+    T u[3], G[3][3], rM[3], gT[3], rT;
 };
 
 // Unscaled (without the Gauss weight W) contribution of one Gauss point to the
@@ -1311,7 +1327,7 @@ struct BdState {
 //   temperature column: [i][4] = B eg_i N (N + tau udN), [3][4] = tau B N (eg . d),
 //     [4][4] = N udN + K |d|^2 + tauT udN^2.
 template <typename T>
-__device__ __forceinline__ void bd_corner(const EC<T> &c, const BdState &st, T N, const T dN[3],
+__device__ __forceinline__ void bd_corner(const EC<T> &c, const BdState<T> &st, T N, const T dN[3],
                                           const T ua[3], T alpha, T Kc, T tau, T tauT, T blk[25])
 {
     const T udN = st.u[0] * dN[0] + st.u[1] * dN[1] + st.u[2] * dN[2];
@@ -1348,18 +1364,23 @@ __device__ __forceinline__ void bd_corner(const EC<T> &c, const BdState &st, T N
     blk[4 * NF + 4] += N * udN + Kc * dd + tauT * udN * udN;
 }
 
-__global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restrict__ x,
+// Nodal 5x5 diagonal blocks of J at state x in the arithmetic of T (FP32 for
+// the mixed-precision preconditioner, whose smoother only uses FP32 blocks).
+template <typename T>
+__global__ __launch_bounds__(NTHR, BdCfg<T>::WAVES) void k_blockdiag(Geo g, const T *__restrict__ x,
                                                     const double *__restrict__ gamma,
                                                     const double *__restrict__ src,
                                                     const uint8_t *__restrict__ nmask,
-                                                    double *__restrict__ D,
-                                                    double *__restrict__ slots)
+                                                    T *__restrict__ D,
+                                                    T *__restrict__ slots)
 {
-    using T = double;
-    __shared__ T sx[NF][BOXN];
+    // 25 accumulators per box node (81,000 B); the staged node box lives in the
+    // same array until the element state is in registers, so that two
+    // workgroups fit in a CU's LDS
     __shared__ T so[25 * BOXN];
+    T(*sx)[BOXN] = reinterpret_cast<T(*)[BOXN]>(so);
     const TileIdx t = tile_index(g);
-    stage<T, 25, false>(g, t, x, (const double *)nullptr, nmask, sx, nullptr, so);
+    stage<T, 0, false>(g, t, x, (const T *)nullptr, nmask, sx, nullptr, nullptr);
     __syncthreads();
     const EC<T> c = make_ec<T>(g);
     T alpha = 0, Kc = 1, s = 0, tau = 0, tauT = 0;
@@ -1367,9 +1388,9 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
     if (t.valid) {
         const int64_t e = (int64_t)t.i + (int64_t)g.nx * ((int64_t)t.j + (int64_t)g.ny * t.k);
         const double y = gamma[e];
-        alpha = alpha_of(g, y);
-        Kc = K_of(g, y);
-        s = src[e];
+        alpha = (T)alpha_of(g, y);
+        Kc = (T)K_of(g, y);
+        s = (T)src[e];
         T U2 = 0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -1391,13 +1412,27 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
         tau = rsqrt_t(U2 * c.inv16h2 + c.cvisc + alpha * alpha);
         tauT = rsqrt_t(U2 * c.inv16h2 + Kc * Kc * c.c16h4);
     }
-    const double h = g.h;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 25 * BOXN; idx += NTHR) so[idx] = T(0);
+    __syncthreads();
+    const T h = (T)g.h;
     // Corners in groups of BDG: the state at each Gauss point is evaluated once
     // per group (8 / BDG times per element instead of once per corner), and
     // each corner's block is the closed form of the directional derivatives
-    // along the five unit vectors of that node (see bd_corner).  The
-    // accumulation keeps the corner order of the sub-steps.
-    constexpr int BDG = FE_BD_GROUP;
+    // along the five unit vectors of that node (see bd_corner).  The corners'
+    // nodal velocities are read from x (the staged copy is overwritten), one
+    // group ahead.  The accumulation keeps the corner order of the sub-steps.
+    constexpr int BDG = BdCfg<T>::G;
+    auto corner_u = [&](int a, T u[3]) {
+        const int64_t n = gnode(g, t.i + (a & 1), t.j + ((a >> 1) & 1), t.k + (a >> 2));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) u[k] = x[NF * n + k];
+    };
+    T un[BDG][3];
+    if (t.valid) {
+#pragma unroll
+        for (int cc = 0; cc < BDG; ++cc) corner_u(cc, un[cc]);
+    }
 #pragma unroll 1
     for (int grp = 0; grp < 8 / BDG; ++grp) {
         T blk[BDG][25];
@@ -1410,10 +1445,14 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
 #pragma unroll
             for (int cc = 0; cc < BDG; ++cc)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) ua[cc][k] = sx[k][t.nb[BDG * grp + cc]];
+                for (int k = 0; k < 3; ++k) ua[cc][k] = un[cc][k];
+            if (grp + 1 < 8 / BDG) {
+#pragma unroll
+                for (int cc = 0; cc < BDG; ++cc) corner_u(BDG * (grp + 1) + cc, un[cc]);
+            }
 #define FE_BD2_GP(SG)                                                                         \
     {                                                                                        \
-        BdState st;                                                                          \
+        BdState<T> st;                                                                       \
         _Pragma("unroll") for (int i = 0; i < 3; ++i)                                        \
             eval_vg(SG, mu[i], c.gs, st.u[i], st.G[i][0], st.G[i][1], st.G[i][2]);           \
         T gp[3], Tv;                                                                         \
@@ -1442,25 +1481,25 @@ __global__ __launch_bounds__(NTHR) void k_blockdiag(Geo g, const double *__restr
             __syncthreads();
         }
     }
+    // write-out, one thread per (node, entry): consecutive threads store
+    // consecutive entries of a node, and consecutive nodes of a box row are
+    // consecutive in D and in the slots
     const int tx0 = t.btx * TX, ty0 = t.bty * TY, tz0 = t.btz * TZ;
-    for (int nb = threadIdx.x; nb < BOXN; nb += NTHR) {
-        int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
-        int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
+    for (int idx = threadIdx.x; idx < 25 * BOXN; idx += NTHR) {
+        const int nb = idx / 25, q = idx - 25 * nb;
+        const int lx = nb % BX, r = nb / BX, ly = r % BY, lz = r / BY;
+        const int I = tx0 + lx, J = ty0 + ly, K = tz0 + lz;
         if (I > g.nx || J > g.ny || K > g.nz) continue;
-        bool sh = shared_dir(lx, I, g.nx, TX) || shared_dir(ly, J, g.ny, TY) ||
-                  shared_dir(lz, K, g.nz, TZ);
+        const bool sh = shared_dir(lx, I, g.nx, TX) || shared_dir(ly, J, g.ny, TY) ||
+                        shared_dir(lz, K, g.nz, TZ);
+        const T val = so[q * BOXN + nb];
         if (sh) {
-            double *sl = slots + ((int64_t)t.tile * BOXN + nb) * 25;
-            for (int q = 0; q < 25; ++q) sl[q] = so[q * BOXN + nb];
+            slots[((int64_t)t.tile * BOXN + nb) * 25 + q] = val;
         } else {
-            int64_t gn = gnode(g, I, J, K);
-            uint8_t m = nmask[gn];
-            for (int f = 0; f < NF; ++f)
-                for (int f2 = 0; f2 < NF; ++f2) {
-                    double val = so[(f * NF + f2) * BOXN + nb];
-                    if (((m >> f) & 1) || ((m >> f2) & 1)) val = (f == f2) ? 1.0 : 0.0;
-                    D[gn * 25 + f * NF + f2] = val;
-                }
+            const int64_t gn = gnode(g, I, J, K);
+            const uint8_t m = nmask[gn];
+            const int f = q / NF, f2 = q - NF * f;
+            D[gn * 25 + q] = (((m >> f) & 1) || ((m >> f2) & 1)) ? ((f == f2) ? T(1) : T(0)) : val;
         }
     }
 }
@@ -1688,17 +1727,23 @@ hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, con
     return hipGetLastError();
 }
 
-hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, const double *s,
-                            const uint8_t *nmask, double *D, double *slots, hipStream_t st)
+template <typename T>
+hipError_t launch_blockdiag(const Geo &g, const T *x, const double *gamma, const double *s,
+                            const uint8_t *nmask, T *D, T *slots, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_blockdiag, dim3((unsigned)n_tiles(g)), dim3(NTHR), 0, st, g, x, gamma, s,
-                       nmask, D, slots);
+    hipLaunchKernelGGL(k_blockdiag<T>, dim3((unsigned)n_tiles(g)), dim3(NTHR), 0, st, g, x, gamma,
+                       s, nmask, D, slots);
     const int64_t nn = n_nodes(g);
-    hipLaunchKernelGGL((k_combine<double, double, 25, OP_RES>), dim3((unsigned)((nn + 255) / 256)),
-                       dim3(256), 0, st, g, (const double *)slots, nmask, (const double *)nullptr,
-                       D);
+    hipLaunchKernelGGL((k_combine<T, T, 25, OP_RES>), dim3((unsigned)((nn + 255) / 256)),
+                       dim3(256), 0, st, g, (const T *)slots, nmask, (const T *)nullptr, D);
     return hipGetLastError();
 }
+template hipError_t launch_blockdiag<double>(const Geo &, const double *, const double *,
+                                             const double *, const uint8_t *, double *, double *,
+                                             hipStream_t);
+template hipError_t launch_blockdiag<float>(const Geo &, const float *, const double *,
+                                            const double *, const uint8_t *, float *, float *,
+                                            hipStream_t);
 
 template <typename T>
 hipError_t launch_elem_smooth(bool tr, const Geo &g, const T *xs, T *x, const double *gamma,

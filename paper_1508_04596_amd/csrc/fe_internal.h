@@ -95,8 +95,6 @@ hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, cons
                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
-// Raw nodal 5x5 diagonal blocks of J (row-major [n][25]), masked rows/cols set
-// to the identity; slots must hold n_tiles * BOXN * 25 doubles.
 // One smoother sweep with the operator fused: x += omega D^{-1} (b - J x) (J^T
 // and D^{-T} when tr), J at state xs; t (node vector) and slots are work space.
 template <typename T>
@@ -114,8 +112,11 @@ hipError_t launch_stencil_assemble(const Geo &g, const double *x, const double *
 hipError_t launch_probe_products(const Geo &g, const double *x, const double *gamma,
                                  const double *s, const uint8_t *nmask, double *Je,
                                  double *probe_out, hipStream_t st);
-hipError_t launch_blockdiag(const Geo &g, const double *x, const double *gamma, const double *s,
-                            const uint8_t *nmask, double *D, double *slots, hipStream_t st);
+// Raw nodal 5x5 diagonal blocks of J (row-major [n][25]) in the arithmetic of T,
+// masked rows/cols set to the identity; slots must hold n_tiles * BOXN * 25 T.
+template <typename T>
+hipError_t launch_blockdiag(const Geo &g, const T *x, const double *gamma, const double *s,
+                            const uint8_t *nmask, T *D, T *slots, hipStream_t st);
 
 // ---- vector kernels (fe_vec.hip) ------------------------------------------
 constexpr int RED_BLOCKS = 1024;  // partial sums per reduction (fixed => deterministic)
@@ -124,6 +125,8 @@ constexpr int RED_THREADS = 256;
 hipError_t launch_node_mask(const uint8_t *dof_mask, uint8_t *nmask, int64_t nn, hipStream_t st);
 // Invert 5x5 blocks in place (FP64) and optionally write an FP32 copy.
 hipError_t launch_invert_blocks(double *D, float *D32, int64_t nn, hipStream_t st);
+// In-place FP32 inverse of FP32 blocks (mixed-precision preconditioner set-up).
+hipError_t launch_invert_blocks32(float *D32, int64_t nn, hipStream_t st);
 // z = D v per node (D row-major 5x5); Tin/Tout/Tm = vector, output, matrix types;
 // the transposed variant applies D^T.
 template <typename Tm, typename Tin, typename Tout>

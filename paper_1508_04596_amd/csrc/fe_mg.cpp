@@ -452,13 +452,23 @@ int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, 
     L0.x32 = const_cast<float *>(x032);
     const int nl = (int)mg->lev.size();
     MgLevel &C = mg->lev.back();
+    // a mixed-precision Newton step (FP32 state given) smooths with FP32 blocks
+    // only, formed and inverted in FP32; otherwise (FP64 solves, the adjoint)
+    // the blocks are FP64, with an FP32 copy in a mixed hierarchy
+    const bool blocks32 = x032 != nullptr;
     for (int l = 1; l < nl - 1; ++l) {
         MgLevel &L = mg->lev[l];
-        if (!L.assembled) {
-            FE_CHECK_HIP(launch_blockdiag(L.geo, L.x, L.gamma, L.s, L.nmask, L.D, L.slots25, st));
+        if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.x, L.x32, L.ndof, st)));
+        if (L.assembled) continue;
+        if (blocks32) {
+            FE_CHECK_HIP((launch_blockdiag<float>(L.geo, L.x32, L.gamma, L.s, L.nmask, L.D32,
+                                                  reinterpret_cast<float *>(L.slots25), st)));
+            FE_CHECK_HIP(launch_invert_blocks32(L.D32, L.nn, st));
+        } else {
+            FE_CHECK_HIP((launch_blockdiag<double>(L.geo, L.x, L.gamma, L.s, L.nmask, L.D,
+                                                   L.slots25, st)));
             FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
         }
-        if (mg->mixed) FE_CHECK_HIP((launch_cast<double, float>(L.x, L.x32, L.ndof, st)));
     }
     // assembled levels: element Jacobians, then the 27-point block stencil, whose
     // centre blocks are the smoother's diagonal blocks (below the finest level,

@@ -74,6 +74,10 @@ void mg_free(Mg *mg);
 int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, hipStream_t st);
 // Per Newton step: mg_setup_begin before the caller's fine-level block diagonal
 // (it starts the coarsest level's probing products), mg_setup_finish after it.
+// D0 / D032, x032: the finest level's inverted blocks and FP32 state.  A
+// mixed-precision step passes D032 and x032 (its V-cycles run in FP32, and the
+// blocks of the other matrix-free levels are then formed in FP32 only); an FP64
+// step (or the adjoint) passes NULL for both and gets FP64 blocks.
 int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st);
 int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, const float *x032,
                     hipStream_t st);

@@ -453,11 +453,21 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
                 return rc;
             }
         }
-        FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
-        FE_CHECK_HIP(launch_invert_blocks(w->D, mixed ? w->D32 : nullptr, p->nn, st));
-        if (mixed) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+        if (mixed) {
+            // the mixed-precision preconditioner uses FP32 blocks only: they are
+            // formed and inverted in FP32 from the FP32 state
+            FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+            FE_CHECK_HIP((launch_blockdiag<float>(p->geo, w->x32, gamma, s_elem, p->nmask, w->D32,
+                                                  reinterpret_cast<float *>(p->slots25), st)));
+            FE_CHECK_HIP(launch_invert_blocks32(w->D32, p->nn, st));
+        } else {
+            FE_CHECK_HIP((launch_blockdiag<double>(p->geo, x, gamma, s_elem, p->nmask, w->D,
+                                                   p->slots25, st)));
+            FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
+        }
         if (pc == FE_PC_MULTIGRID) {
-            rc = mg_setup_finish(w->mg, p, w->D, w->D32, w->x32, st);
+            rc = mg_setup_finish(w->mg, p, w->D, mixed ? w->D32 : nullptr,
+                                 mixed ? w->x32 : nullptr, st);
             if (rc) {
                 rep.status = rc;
                 fill_report(report, rep);

@@ -248,22 +248,30 @@ __global__ void k_node_mask(const uint8_t *__restrict__ dm, uint8_t *__restrict_
 }
 
 // In-place inverse of each 5x5 block by Gauss-Jordan with partial pivoting.
-__global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32, int64_t nn)
+// The workgroup's 256 blocks pass through LDS both ways, so that global loads
+// and stores are contiguous (a thread's block is 25 consecutive doubles; read
+// and written directly, neighbouring lanes would touch addresses 200 B apart).
+// Launched with 256 threads per workgroup.  T: the blocks' type and the
+// arithmetic (D32, if given, receives an FP32 copy of FP64 inverses).
+template <typename T>
+__global__ __launch_bounds__(256) void k_invert_blocks(T *__restrict__ D, float *__restrict__ D32,
+                                                       int64_t nn)
 {
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    double a[5][5], b[5][5];
+    __shared__ T sD[256 * 25];
+    const int64_t n0 = (int64_t)blockIdx.x * 256;
+    const T *Dn = stage_blocks256(D, n0, nn, sD);  // entries past nn: copies of the last
+    T a[5][5], b[5][5];
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            a[r][c] = D[n * 25 + r * 5 + c];
-            b[r][c] = (r == c) ? 1.0 : 0.0;
+            a[r][c] = Dn[r * 5 + c];
+            b[r][c] = (r == c) ? T(1) : T(0);
         }
 #pragma unroll
     for (int col = 0; col < 5; ++col) {
         int p = col;
-        double best = fabs(a[col][col]);
+        T best = fabs(a[col][col]);
 #pragma unroll
         for (int r = col + 1; r < 5; ++r)
             if (fabs(a[r][col]) > best) {
@@ -275,11 +283,11 @@ __global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32,
             if (r == p) {
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
-                    double t = a[col][c]; a[col][c] = a[r][c]; a[r][c] = t;
+                    T t = a[col][c]; a[col][c] = a[r][c]; a[r][c] = t;
                     t = b[col][c]; b[col][c] = b[r][c]; b[r][c] = t;
                 }
             }
-        const double inv = 1.0 / a[col][col];
+        const T inv = T(1) / a[col][col];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             a[col][c] *= inv;
@@ -288,7 +296,7 @@ __global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32,
 #pragma unroll
         for (int r = 0; r < 5; ++r)
             if (r != col) {
-                const double f = a[r][col];
+                const T f = a[r][col];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     a[r][c] -= f * a[col][c];
@@ -296,13 +304,25 @@ __global__ void k_invert_blocks(double *__restrict__ D, float *__restrict__ D32,
                 }
             }
     }
+    // (every thread has read its own block above; it now overwrites only that)
+    T *own = sD + threadIdx.x * 25;
 #pragma unroll
     for (int r = 0; r < 5; ++r)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            D[n * 25 + r * 5 + c] = b[r][c];
-            if (D32) D32[n * 25 + r * 5 + c] = (float)b[r][c];
+        for (int c = 0; c < 5; ++c) own[r * 5 + c] = b[r][c];
+    __syncthreads();
+    const int64_t left = nn - n0;
+    const int cnt = (int)(left < 256 ? left : 256) * 25;
+    T *dst = D + n0 * 25;
+    float *dst32 = D32 ? D32 + n0 * 25 : nullptr;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        if (q < cnt) {
+            dst[q] = sD[q];
+            if (dst32) dst32[q] = (float)sD[q];
         }
+    }
 }
 
 // Launched with 256 threads per workgroup (the block staging assumes it).
@@ -419,7 +439,14 @@ hipError_t launch_node_mask(const uint8_t *dof_mask, uint8_t *nmask, int64_t nn,
 
 hipError_t launch_invert_blocks(double *D, float *D32, int64_t nn, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_invert_blocks, dim3(nblk(nn, 128)), dim3(128), 0, st, D, D32, nn);
+    hipLaunchKernelGGL(k_invert_blocks<double>, dim3(nblk(nn, 256)), dim3(256), 0, st, D, D32, nn);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_blocks32(float *D32, int64_t nn, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_invert_blocks<float>, dim3(nblk(nn, 256)), dim3(256), 0, st, D32,
+                       (float *)nullptr, nn);
     return hipGetLastError();
 }
 

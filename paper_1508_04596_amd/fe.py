@@ -28,7 +28,7 @@ EXPORTS = [
     "fe_line_search_lambda", "fe_solve_footprint_bytes", "serve_create", "serve_submit",
     "serve_poll", "serve_times", "serve_error", "serve_destroy", "fe_last_error", "fe_version",
     "serve_create_ex", "serve_engine_stats", "fe_jvp_batch_create", "fe_jvp_batch_run",
-    "fe_jvp_batch_destroy",
+    "fe_jvp_batch_destroy", "fe_block_diagonal_fp32",
 ]
 FE_SERVE_BATCHED = 1
 
@@ -150,6 +150,7 @@ def lib() -> ctypes.CDLL:
         L.fe_jvp_noalloc_scratch_bytes.restype = i64
         L.fe_compliance.argtypes = [vp, vp, vp, P(dbl), vp, vp]
         L.fe_block_diagonal.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fe_block_diagonal_fp32.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fe_solve_opts_default.argtypes = [P(FeSolveOpts)]
         L.fe_solve_opts_default.restype = None
         L.newton_solve.argtypes = [vp, vp, vp, vp, P(FeSolveOpts), P(FeSolveReport), vp]
@@ -383,6 +384,18 @@ def fe_compliance(prob: Problem, x, s, dfdx=None, stream=None):
                                _ptr(dfdx, torch.float64, prob.n_dof, "dfdx"), _stream(stream)),
            "fe_compliance")
     return f.value
+
+
+def fe_block_diagonal_fp32(prob: Problem, x32, gamma, s, out=None, stream=None):
+    """Nodal 5x5 blocks in FP32 arithmetic from an FP32 state (mixed-precision set-up)."""
+    out = torch.empty(25 * prob.n_nodes, dtype=torch.float32, device=x32.device) if out is None else out
+    ne = prob.n_el
+    _check(lib().fe_block_diagonal_fp32(prob.handle, _ptr(x32, torch.float32, prob.n_dof, "x"),
+                                        _ptr(gamma, torch.float64, ne, "gamma"),
+                                        _ptr(s, torch.float64, ne, "s"),
+                                        _ptr(out, torch.float32, 25 * prob.n_nodes, "out"),
+                                        _stream(stream)), "fe_block_diagonal_fp32")
+    return out
 
 
 def fe_block_diagonal(prob: Problem, x, gamma, s, out=None, stream=None):

@@ -128,6 +128,36 @@ def test_block_diagonal_parity(fe):
     prob.close()
 
 
+def _oracle_blocks(p, x):
+    Ke = oracle.element_jacobians(p, x)
+    dofs = osolve.element_dofs(p)
+    ref = np.zeros((p.n_nodes, 5, 5))
+    for a in range(8):
+        nodes = dofs[:, 5 * a] // 5
+        np.add.at(ref, nodes, Ke[:, 5 * a:5 * a + 5, 5 * a:5 * a + 5])
+    m = p.mask_solve.reshape(-1, 5).astype(bool)
+    for f in range(5):
+        for f2 in range(5):
+            sel = m[:, f] | m[:, f2]
+            ref[sel, f, f2] = 1.0 if f == f2 else 0.0
+    return ref
+
+
+@pytest.mark.parametrize("grid", [(11, 9, 6), (8, 8, 4), (17, 3, 5)])
+def test_block_diagonal_fp32_parity(fe, grid):
+    """FP32 blocks (the mixed-precision set-up) against the oracle's blocks at the
+    FP32-rounded state, relative to the largest block entry."""
+    p = inputs.scaled_config(*grid, 5e3, seed=22)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = inputs.random_state(p, 32, mask=p.mask_solve).astype(np.float32)
+    D = host(fe.fe_block_diagonal_fp32(prob, dev(x).float(), dev(p.gamma), dev(p.s)))
+    ref = _oracle_blocks(p, x.astype(np.float64)).reshape(-1)
+    err = np.abs(D.astype(np.float64) - ref).max() / np.abs(ref).max()
+    print(f"[fp32] blocks {grid}: rel err {err:.3e}")
+    assert err <= 1e-6
+    prob.close()
+
+
 def test_compliance_parity(fe):
     p = inputs.scaled_config(12, 9, 10, 1e3, seed=3)
     prob = fe.Problem.from_inputs(p, mask="solve")
