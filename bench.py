@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--serve-burst-rate", type=float, default=1000.0,
                     help="arrival rate of the burst comparison (default vs batched server); 0 = skip")
     ap.add_argument("--serve-burst-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="diagnostic: run only the serving legs and print their JSON")
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
                     help="workload: 2 = 64^3 (the reported line), 3 = 160x160x320 (the "
                          "paper's 41.6 M DOF mesh), 4 = 96^3")
@@ -108,6 +110,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serve_only:
+        print(json.dumps({"serving": serving_legs(fe, inputs, args)}), flush=True)
+        return
     p = inputs.config(args.config)
     prob = fe.Problem.from_inputs(p, mask="solve")
     g = torch.from_numpy(p.gamma).to(dev)
@@ -204,24 +209,7 @@ def main():
             "jv_alg_bytes": bytes_alg,
             "jv_op_alg_GBps": bytes_alg / t_jv64 / 1e9}
 
-    serve = None
-    if args.serve_requests > 0:
-        # the configured trace on the default server (each request's solve on its
-        # worker's stream) and on the batched one (lockstep FGMRES, one launch per
-        # kernel over all running requests); then a burst that keeps many
-        # requests in flight, on both
-        serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                            args.serve_max_active, args.serve_rate)
-        serve["batched"] = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                                       args.serve_batched_max_active, args.serve_rate,
-                                       batched=True)
-        if args.serve_burst_rate > 0:
-            serve["burst"] = {
-                "default": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
-                                       args.serve_max_active, args.serve_burst_rate),
-                "batched": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
-                                       args.serve_batched_max_active, args.serve_burst_rate,
-                                       batched=True)}
+    serve = serving_legs(fe, inputs, args) if args.serve_requests > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -258,6 +246,25 @@ def main():
 _SERVE_PROBS = {}
 
 
+def serving_legs(fe, inputs, args):
+    """The configured trace on the default server (each request's solve on its
+    worker's stream) and on the batched one (lockstep FGMRES, one launch per
+    kernel over all running requests); then a burst that keeps many requests
+    in flight, on both."""
+    serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
+                        args.serve_max_active, args.serve_rate)
+    serve["batched"] = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
+                                   args.serve_batched_max_active, args.serve_rate, batched=True)
+    if args.serve_burst_rate > 0:
+        serve["burst"] = {
+            "default": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
+                                   args.serve_max_active, args.serve_burst_rate),
+            "batched": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
+                                   args.serve_batched_max_active, args.serve_burst_rate,
+                                   batched=True)}
+    return serve
+
+
 def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
     """Serving workload: n requests with Poisson arrivals (20/s by default), grids uniform
     over {16,24,32,48}^3, log10 Gr uniform in [3,5], 40 %-solid smoothed random
@@ -273,6 +280,15 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
     opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
     lat, tickets, statuses = [], [], []
     with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active, batched=batched) as srv:
+        # warm-up, not timed: one request of each grid size (first use of the
+        # kernels and of the server's worker threads and streams)
+        seen = {}
+        for pr in probs:
+            seen.setdefault(pr.nx, pr)
+        for pr in seen.values():
+            ph = fe.make_phys(pr.Pr, pr.Gr, pr.Ck, pr.qf, pr.alpha_max, pr.q_alpha, pr.eg)
+            srv.wait(srv.submit(pr.nx, pr.ny, pr.nz, pr.h, ph, pr.gamma, pr.s, opts))
+        steps0, launches0 = srv.engine_stats()
         t0 = _t.perf_counter()
         for r, pr in zip(reqs, probs):
             wait = t0 + r.arrival_s - _t.perf_counter()
@@ -285,6 +301,7 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
             statuses.append(rc)
         times = [srv.times(t) for t in tickets]
         steps, launches = srv.engine_stats()
+        steps, launches = steps - steps0, launches - launches0
     lat = np.array([d - a for a, _, d in times])
     makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
     return {"requests": n, "rate_per_s": rate, "budget_gb": budget_gb, "max_active": max_active,

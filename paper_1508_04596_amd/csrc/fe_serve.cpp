@@ -42,42 +42,34 @@ using namespace fe;
 
 namespace {
 
-class Arena final : public Allocator {
+// First-fit free list over [0, size) with coalescing of neighbouring free ranges.
+class FreeList {
   public:
-    hipError_t init(size_t bytes)
+    void reset(size_t size)
     {
-        size_ = bytes / 256 * 256;
-        const char *pz = std::getenv("FE_ARENA_POISON");
-        poison_ = pz && pz[0] == '1';
-        hipError_t e = hipMalloc(&base_, size_);
-        if (e == hipSuccess) free_[0] = size_;
-        return e;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.clear();
+        used_.clear();
+        if (size) free_[0] = size;
     }
-    ~Arena() override
+    // offset of a range of n bytes (n a multiple of 256), or false if none is free
+    bool take(size_t n, size_t *off)
     {
-        if (base_) (void)hipFree(base_);
-    }
-    hipError_t dev_alloc(void **p, size_t n) override
-    {
-        n = std::max<size_t>(256, (n + 255) / 256 * 256);
         std::lock_guard<std::mutex> lk(mu_);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second < n) continue;
-            const size_t off = it->first, sz = it->second;
+            const size_t o = it->first, sz = it->second;
             free_.erase(it);
-            if (sz > n) free_[off + n] = sz - n;
-            used_[off] = n;
-            *p = static_cast<char *>(base_) + off;
-            return hipSuccess;
+            if (sz > n) free_[o + n] = sz - n;
+            used_[o] = n;
+            *off = o;
+            return true;
         }
-        *p = nullptr;
-        return hipErrorOutOfMemory;
+        return false;
     }
-    void dev_free(void *p) override
+    void give(size_t off)
     {
-        if (!p) return;
         std::lock_guard<std::mutex> lk(mu_);
-        const size_t off = static_cast<char *>(p) - static_cast<char *>(base_);
         auto u = used_.find(off);
         if (u == used_.end()) return;
         size_t start = off, n = u->second;
@@ -98,16 +90,7 @@ class Arena final : public Allocator {
         }
         free_[start] = n;
     }
-    // host staging memory: plain pageable memory (freeing it never synchronises)
-    hipError_t host_alloc(void **p, size_t n) override
-    {
-        *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
-        return *p ? hipSuccess : hipErrorOutOfMemory;
-    }
-    void host_free(void *p) override { std::free(p); }
-    size_t size() const { return size_; }
-    bool poison() const { return poison_; }
-    size_t largest_free()
+    size_t largest()
     {
         std::lock_guard<std::mutex> lk(mu_);
         size_t m = 0;
@@ -116,12 +99,98 @@ class Arena final : public Allocator {
     }
 
   private:
+    std::mutex mu_;
+    std::map<size_t, size_t> free_;            // offset -> size of free ranges
+    std::unordered_map<size_t, size_t> used_;  // offset -> size of live ranges
+};
+
+// Pinned host memory for the requests' host staging (Krylov scalars, coarse
+// factorisation buffers): copies to and from it are direct DMA, where pageable
+// memory goes through the runtime's staging copy.  Allocated once; a request
+// whose staging does not fit takes pageable memory instead.
+class HostPool {
+  public:
+    hipError_t init(size_t bytes)
+    {
+        size_ = bytes / 256 * 256;
+        if (!size_) return hipSuccess;
+        hipError_t e = hipHostMalloc(&base_, size_);
+        if (e != hipSuccess) {
+            base_ = nullptr;
+            size_ = 0;
+        }
+        fl_.reset(size_);
+        return e;
+    }
+    ~HostPool()
+    {
+        if (base_) (void)hipHostFree(base_);
+    }
+    void *alloc(size_t n)
+    {
+        n = std::max<size_t>(256, (n + 255) / 256 * 256);
+        size_t off = 0;
+        if (!base_ || !fl_.take(n, &off)) return nullptr;
+        return static_cast<char *>(base_) + off;
+    }
+    bool owns(const void *p) const
+    {
+        const char *c = static_cast<const char *>(p), *b = static_cast<const char *>(base_);
+        return base_ && c >= b && c < b + size_;
+    }
+    void release(void *p) { fl_.give(static_cast<char *>(p) - static_cast<char *>(base_)); }
+
+  private:
+    void *base_ = nullptr;
+    size_t size_ = 0;
+    FreeList fl_;
+};
+
+class Arena final : public Allocator {
+  public:
+    hipError_t init(size_t bytes)
+    {
+        size_ = bytes / 256 * 256;
+        const char *pz = std::getenv("FE_ARENA_POISON");
+        poison_ = pz && pz[0] == '1';
+        hipError_t e = hipMalloc(&base_, size_);
+        if (e == hipSuccess) fl_.reset(size_);
+        return e;
+    }
+    ~Arena() override
+    {
+        if (base_) (void)hipFree(base_);
+    }
+    hipError_t dev_alloc(void **p, size_t n) override
+    {
+        n = std::max<size_t>(256, (n + 255) / 256 * 256);
+        size_t off = 0;
+        if (!fl_.take(n, &off)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        *p = static_cast<char *>(base_) + off;
+        return hipSuccess;
+    }
+    void dev_free(void *p) override
+    {
+        if (p) fl_.give(static_cast<char *>(p) - static_cast<char *>(base_));
+    }
+    hipError_t host_alloc(void **p, size_t n) override
+    {
+        *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void host_free(void *p) override { std::free(p); }
+    size_t size() const { return size_; }
+    bool poison() const { return poison_; }
+    size_t largest_free() { return fl_.largest(); }
+
+  private:
     void *base_ = nullptr;
     size_t size_ = 0;
     bool poison_ = false;
-    std::mutex mu_;
-    std::map<size_t, size_t> free_;            // offset -> size of free blocks
-    std::unordered_map<size_t, size_t> used_;  // offset -> size of live blocks
+    FreeList fl_;
 };
 
 // One request's block of the arena: allocations are carved from it in order
@@ -129,8 +198,8 @@ class Arena final : public Allocator {
 // the request ends.
 class Block final : public Allocator {
   public:
-    Block(void *base, size_t size, bool poison)
-        : base_(static_cast<char *>(base)), size_(size), poison_(poison)
+    Block(void *base, size_t size, bool poison, HostPool *pool)
+        : base_(static_cast<char *>(base)), size_(size), poison_(poison), pool_(pool)
     {
     }
     hipError_t dev_alloc(void **p, size_t n) override
@@ -148,17 +217,27 @@ class Block final : public Allocator {
         return hipSuccess;
     }
     void dev_free(void *) override {}
+    // host staging: the server's pinned pool, pageable memory when it is full
+    // (neither allocating nor freeing synchronises the device)
     hipError_t host_alloc(void **p, size_t n) override
     {
-        *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
+        *p = pool_ ? pool_->alloc(n) : nullptr;
+        if (!*p) *p = std::aligned_alloc(64, (n + 63) / 64 * 64);
         return *p ? hipSuccess : hipErrorOutOfMemory;
     }
-    void host_free(void *p) override { std::free(p); }
+    void host_free(void *p) override
+    {
+        if (pool_ && pool_->owns(p))
+            pool_->release(p);
+        else
+            std::free(p);
+    }
 
   private:
     char *base_;
     size_t size_, used_ = 0;
     bool poison_;
+    HostPool *pool_;
 };
 
 enum ReqState { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2 };
@@ -183,6 +262,7 @@ struct Request {
 
 struct fe_server {
     Arena arena;
+    HostPool host_pool;
     size_t budget = 0;
     int max_active = 1;
     int device = 0;
@@ -218,7 +298,7 @@ size_t request_footprint(const fe_grid &g, const fe_solve_opts &o)
 
 int run_request(fe_server *S, Request *r, hipStream_t st)
 {
-    Block mem(r->block, r->footprint, S->arena.poison());
+    Block mem(r->block, r->footprint, S->arena.poison(), &S->host_pool);
     fe_problem *p = nullptr;
     int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &mem, st, &p);
     if (rc) return rc;
@@ -357,6 +437,12 @@ int serve_create_ex(size_t hbm_budget_bytes, int max_active, int flags, fe_serve
     }
     S->budget = S->arena.size();
     S->max_active = max_active;
+    // pinned host staging: 4 MiB per worker slot within [64 MiB, 512 MiB]
+    // (requests of 16^3 to 48^3 take 1.1 to 2.9 MiB, mostly the coarsest
+    // level's probing products and band factors; past the pool, pageable memory)
+    const size_t pool = std::min<size_t>(std::max<size_t>((size_t)max_active << 22, (size_t)64 << 20),
+                                         (size_t)512 << 20);
+    if (S->host_pool.init(pool) != hipSuccess) (void)hipGetLastError();  // pageable only
     if (batched) {
         const int rc = batch_engine_create(S->device, &S->engine);
         if (rc) {

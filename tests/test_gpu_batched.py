@@ -112,3 +112,31 @@ def test_batched_server_alone_and_in_the_mix(fe, prec, n_req):
         assert np.array_equal(x, alone[i]), f"request {i} differs alone vs in the mix"
     # the requests' linear solves shared engine steps
     assert steps_mix < 0.8 * steps_alone
+
+
+def test_batched_server_with_requests_that_have_no_multigrid(fe):
+    """Grids without a multigrid hierarchy (a three-element-thick slab, a 3^3
+    cube) run their block-Jacobi FGMRES on their worker while the others share
+    engine steps."""
+    probs = [inputs.scaled_config(16, 16, 16, 1e4, seed=61),
+             inputs.scaled_config(20, 20, 3, 1e3, seed=62),
+             inputs.scaled_config(3, 3, 3, 1e3, seed=63),
+             inputs.scaled_config(24, 24, 24, 3e3, seed=64)]
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    alone = []
+    with fe.Server(2 << 30, max_active=1, batched=True) as srv:
+        for p in probs:
+            rc, x, rep = srv.wait(_submit(fe, srv, p, opts))
+            assert rc == fe.FE_OK, rep
+            alone.append((x, rep))
+    with fe.Server(4 << 30, max_active=4, batched=True) as srv:
+        res = [srv.wait(t) for t in [_submit(fe, srv, p, opts) for p in probs]]
+    for i, ((rc, x, rep), p) in enumerate(zip(res, probs)):
+        assert rc == fe.FE_OK, (i, rep)
+        assert (rep["mg_levels"] >= 2) == (i in (0, 3)), (i, rep["mg_levels"])
+        r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+        assert r0 > 0.0
+        r = np.linalg.norm(oracle.residual(p, x, mask="solve"))
+        print(f"[batched] {p.nx}x{p.ny}x{p.nz}: levels {rep['mg_levels']}, oracle |R|/|R0| = {r / r0:.3e}")
+        assert r <= 1e-8 * r0 * 1.0001, (i, r / r0)
+        assert np.array_equal(x, alone[i][0]), f"request {i} differs alone vs in the mix"
