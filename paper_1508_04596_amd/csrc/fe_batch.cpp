@@ -49,6 +49,7 @@ enum Kind {
     K_ST_D, K_ST_F, K_SM0_D, K_SM0_F, K_SM1_D, K_SM1_F,
     K_RS_D, K_RS_F, K_RSS_D, K_RSS_F, K_PR_D, K_PR_F,
     K_CP_D, K_CP_F, K_CS_D, K_CS_F,
+    K_SS_D, K_SS_F, K_SM0C, K_CPY_D, K_CPY_F,
     K_COUNT
 };
 using LaunchFn = hipError_t (*)(const BLaunch &, hipStream_t);
@@ -68,6 +69,8 @@ const LaunchFn kLaunch[K_COUNT] = {
     blaunch_prolong<double>, blaunch_prolong<float>,
     blaunch_coarse_part<double>, blaunch_coarse_part<float>,
     blaunch_coarse_sum<double>, blaunch_coarse_sum<float>,
+    blaunch_stencil_smooth<double>, blaunch_stencil_smooth<float>, blaunch_smooth0_cast,
+    blaunch_copy<double>, blaunch_copy<float>,
 };
 
 // Kind of a templated kernel for T = double / float.
@@ -177,19 +180,31 @@ void emit_op(Planner &P, uint64_t k, MgLevel &L, const T *x, T *t)
     P.add(k + 1, kd<T>(K_CJV_DD, K_CJV_FF), a, bnode_blocks(L.geo));
 }
 
-// x += omega D^{-1} (b - A x) on level L
 template <typename T>
-void emit_sweep(Planner &P, uint64_t k, MgLevel &L, const T *D, const T *b, T *x, T *t, T om)
+T *alt_of(MgLevel &L)
+{
+    if constexpr (sizeof(T) == 8)
+        return L.xa;
+    else
+        return L.xa32;
+}
+
+// x += omega D^{-1} (b - A x) on level L: the element pass and the fused
+// shared-node/smoothing pass in place on matrix-free levels; one kernel on
+// assembled ones, writing the other of the level's two iterate buffers (x, the
+// level's own, and its second buffer); cur tracks where the iterate is.
+template <typename T>
+void emit_sweep(Planner &P, uint64_t k, MgLevel &L, const T *D, const T *b, T *x, T *&cur, T *t, T om)
 {
     if (L.assembled) {
-        P.add(k, kd<T>(K_ST_D, K_ST_F),
-              BStencil<T>{L.grid.nx, L.grid.ny, L.grid.nz, stencil_of<T>(L), x, t},
-              bstencil_blocks(L.nn));
-        P.add(k + 1, kd<T>(K_SM1_D, K_SM1_F), BSmooth<T>{D, b, t, x, L.nn, om},
-              bsmooth_blocks(L.nn));
+        T *nxt = cur == x ? alt_of<T>(L) : x;
+        P.add(k, kd<T>(K_SS_D, K_SS_F),
+              BStencilSmooth<T>{L.grid.nx, L.grid.ny, L.grid.nz, stencil_of<T>(L), D, b, cur, nxt, om},
+              bstencil_smooth_blocks(L.nn));
+        cur = nxt;
         return;
     }
-    const BElemSmooth<T> a{L.geo, state_of<T>(L), x, L.gamma, L.s, L.nmask, t, (T *)L.slots, D, b,
+    const BElemSmooth<T> a{L.geo, state_of<T>(L), cur, L.gamma, L.s, L.nmask, t, (T *)L.slots, D, b,
                            om};
     P.add(k, kd<T>(K_ESM_D, K_ESM_F), a, belem_blocks(L.geo));
     P.add(k + 1, kd<T>(K_CSM_D, K_CSM_F), a, bnode_blocks(L.geo));
@@ -205,25 +220,30 @@ void emit_vcycle(Planner &P, Mg *mg, const double *v, T *z)
     const int nl = (int)mg->lev.size();
     const T om = (T)mg->omega;
     std::vector<const T *> bl(nl);
-    std::vector<T *> xl(nl);
+    std::vector<T *> xl(nl), cur(nl);
+    bool first_done = false;
     if constexpr (sizeof(T) == 4) {
+        // the first sweep from zero reads the FP64 Krylov vector and keeps its cast
         MgLevel &L0 = mg->lev[0];
-        P.add(key(1, 0, 0), K_CAST, BCast{v, L0.b32, L0.ndof}, belt_blocks(L0.ndof));
+        P.add(key(1, 0, 1), K_SM0C, BSmooth0Cast{L0.D32, v, L0.b32, z, L0.nn, om},
+              bsmooth_blocks(L0.nn));
         bl[0] = L0.b32;
+        first_done = true;
     } else {
         bl[0] = v;
     }
     xl[0] = z;
-    bool first_done = false;
     for (int l = 0; l + 1 < nl; ++l) {
         MgLevel &L = mg->lev[l], &C = mg->lev[l + 1];
         const T *D = blocks_of<T>(L);
         T *t = vec_of<T>(L, 2);
+        cur[l] = xl[l];
         if (!first_done)
             P.add(key(1, l, 1), kd<T>(K_SM0_D, K_SM0_F), BSmooth<T>{D, bl[l], nullptr, xl[l], L.nn, om},
                   bsmooth_blocks(L.nn));
-        for (int it = 1; it < mg->nu1; ++it) emit_sweep<T>(P, key(1, l, 2 * it), L, D, bl[l], xl[l], t, om);
-        emit_op<T>(P, key(1, l, 40), L, xl[l], t);
+        for (int it = 1; it < mg->nu1; ++it)
+            emit_sweep<T>(P, key(1, l, 2 * it), L, D, bl[l], xl[l], cur[l], t, om);
+        emit_op<T>(P, key(1, l, 40), L, cur[l], t);
         T *bc = vec_of<T>(C, 0), *xc = vec_of<T>(C, 1);
         bl[l + 1] = bc;
         xl[l + 1] = xc;
@@ -250,10 +270,13 @@ void emit_vcycle(Planner &P, Mg *mg, const double *v, T *z)
         T *t = vec_of<T>(L, 2);
         P.add(key(2, MAXD - l, 0), kd<T>(K_PR_D, K_PR_F),
               BProlong<T>{L.grid.nx, L.grid.ny, L.grid.nz, C.grid.nx, C.grid.ny, xl[l + 1], L.nmask,
-                          xl[l]},
+                          cur[l]},
               bprolong_blocks(L.nn));
         for (int it = 0; it < mg->nu2; ++it)
-            emit_sweep<T>(P, key(2, MAXD - l, 1 + 2 * it), L, D, bl[l], xl[l], t, om);
+            emit_sweep<T>(P, key(2, MAXD - l, 1 + 2 * it), L, D, bl[l], xl[l], cur[l], t, om);
+        if (cur[l] != xl[l])
+            P.add(key(2, MAXD - l, 39), kd<T>(K_CPY_D, K_CPY_F), BCopy<T>{cur[l], xl[l], L.ndof},
+                  belt_blocks(L.ndof));
     }
 }
 

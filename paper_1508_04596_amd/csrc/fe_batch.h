@@ -112,7 +112,22 @@ struct BCoarse {  // x = A_c^{-1} b through the explicit inverse of the free DOF
     T *x;
     double *P;
 };
+template <typename T>
+struct BStencilSmooth {  // x_out = x_in + omega D^{-1} (b - S x_in), x_out != x_in
+    int nx, ny, nz;
+    const T *S, *D, *b, *xin;
+    T *xout;
+    T omega;
+};
+struct BSmooth0Cast {  // b32 = (float) v, x = omega D^{-1} b32
+    const float *D;
+    const double *v;
+    float *b32, *x;
+    int64_t nn;
+    float omega;
+};
 inline int bstencil_blocks(int64_t nn) { return (int)((NF * nn + 63) / 64); }
+inline int bstencil_smooth_blocks(int64_t nn) { return (int)((nn + 63) / 64); }
 inline int bsmooth_blocks(int64_t nn) { return (int)((nn + 255) / 256); }
 inline int brestrict_blocks(int64_t nn_c) { return (int)((NF * nn_c + 255) / 256); }
 inline int brestrict_smooth_blocks(int64_t nn_c) { return (int)((nn_c + 50) / 51); }
@@ -133,6 +148,9 @@ template <typename T>
 hipError_t blaunch_coarse_part(const BLaunch &L, hipStream_t st);
 template <typename T>
 hipError_t blaunch_coarse_sum(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_stencil_smooth(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_smooth0_cast(const BLaunch &L, hipStream_t st);
 
 // ---- vectors and reductions (fe_batch.hip) ---------------------------------
 // Reductions split a problem's vector of n entries into nchunk chunks of
@@ -164,6 +182,12 @@ struct BAxpby {  // y = a x + b y
     const double *x;
     double b;
     double *y;
+};
+template <typename T>
+struct BCopy {  // b = a
+    const T *a;
+    T *b;
+    int64_t n;
 };
 struct BScale {  // y = x / s[0]
     int64_t n;
@@ -218,6 +242,8 @@ hipError_t blaunch_axpby(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_scale(const BLaunch &L, hipStream_t st);
 template <typename Tz>
 hipError_t blaunch_comb(const BLaunch &L, hipStream_t st);
+template <typename T>
+hipError_t blaunch_copy(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_dots(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_reduce(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_update(const BLaunch &L, hipStream_t st);

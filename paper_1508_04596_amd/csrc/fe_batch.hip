@@ -82,6 +82,16 @@ __global__ __launch_bounds__(256) void kb_comb(const BComb<Tz> *__restrict__ tab
     a.x[i] = acc;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void kb_copy(const BCopy<T> *__restrict__ tab,
+                                               const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BCopy<T> &a = tab[e];
+    const int64_t i = (int64_t)(blockIdx.x - (unsigned)off[e]) * 256 + threadIdx.x;
+    if (i < a.n) a.b[i] = a.a[i];
+}
+
 // Partials of <V_c, w> for the BDOT_GROUP columns c of group g (column k is
 // <w, w> when norm), over chunk ch of the problem's vector.
 __global__ __launch_bounds__(256) void kb_dots(const BDots *__restrict__ tab,
@@ -220,5 +230,16 @@ hipError_t blaunch_comb(const BLaunch &L, hipStream_t st)
 }
 template hipError_t blaunch_comb<double>(const BLaunch &, hipStream_t);
 template hipError_t blaunch_comb<float>(const BLaunch &, hipStream_t);
+
+template <typename T>
+hipError_t blaunch_copy(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_copy<T>, dim3((unsigned)L.blocks), dim3(256), 0, st,
+                       (const BCopy<T> *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
+template hipError_t blaunch_copy<double>(const BLaunch &, hipStream_t);
+template hipError_t blaunch_copy<float>(const BLaunch &, hipStream_t);
 
 }  // namespace fe

@@ -55,6 +55,13 @@ hipError_t mg_coarse_inverse(int n, int kl, int ku, const double *Lc, const doub
 template <typename T>
 hipError_t mg_coarse_apply(int n, int m, const double *X, const int *fidx, const int *pos, const T *b,
                            T *x, double *P, bool transpose, hipStream_t st);
+template <typename T>
+hipError_t mg_stencil_smooth(int nx, int ny, int nz, const T *S, const T *D, const T *b, const T *xin,
+                             T *xout, T omega, bool transpose, hipStream_t st);
+hipError_t mg_smooth0_cast(const float *D, const double *v, float *b32, float *x, int64_t nn,
+                           float omega, bool transpose, hipStream_t st);
+template <typename T>
+hipError_t mg_copy(const T *a, T *b, int64_t n, hipStream_t st);
 
 constexpr int64_t MG_MAX_COARSE_DOF = 2400;   // largest directly factored level
 constexpr int64_t MG_TARGET_COARSE_DOF = 1500; // stop coarsening below this size
@@ -74,6 +81,8 @@ static void free_level(fe_problem *p, MgLevel &L, bool owned)
     }
     dfree(p, L.S);
     dfree(p, L.S32);
+    dfree(p, L.xa);
+    dfree(p, L.xa32);
     dfree(p, L.b);
     dfree(p, L.xs);
     dfree(p, L.t);
@@ -174,8 +183,8 @@ int64_t mg_footprint_bytes(const fe_grid &g0, bool mixed, int64_t asm_nodes)
         b += r256(8 * ndof);
         if (mixed) b += r256(4 * ndof);
         if (l < nl - 1 && nn <= asm_nodes) {
-            b += r256(8 * 675 * nn);
-            if (mixed) b += r256(4 * 675 * nn);
+            b += r256(8 * 675 * nn) + r256(8 * ndof);
+            if (mixed) b += r256(4 * 675 * nn) + r256(4 * ndof);
             ne_je = std::max(ne_je, ne);
         }
         ndof_c = ndof;
@@ -237,6 +246,8 @@ int mg_create(fe_problem *p, bool mixed, int64_t asm_nodes, Mg **out)
         if (L.assembled) {
             if (e == hipSuccess) e = dalloc(p, &L.S, sizeof(double) * 675 * L.nn);
             if (e == hipSuccess && mixed) e = dalloc(p, &L.S32, sizeof(float) * 675 * L.nn);
+            if (e == hipSuccess) e = dalloc(p, &L.xa, nb);
+            if (e == hipSuccess && mixed) e = dalloc(p, &L.xa32, sizeof(float) * L.ndof);
         }
     }
     const MgLevel &C = mg->lev.back();
@@ -564,22 +575,6 @@ static hipError_t op(const MgLevel &L, const T *v, T *out, bool tr, hipStream_t 
                              (T *)L.slots, st);
 }
 
-// One damped block-Jacobi sweep x += omega D^{-1} (b - A x) (transposed when tr):
-// fused with the element pass on matrix-free levels, stencil product then
-// nodal update on assembled ones.
-template <typename T>
-static hipError_t smooth_sweep(const MgLevel &L, const T *D, const T *b, T *x, T *t, T om, bool tr,
-                               hipStream_t st)
-{
-    if (L.assembled) {
-        hipError_t e = op<T>(L, x, t, tr, st);
-        if (e != hipSuccess) return e;
-        return mg_smooth<T>(D, b, t, x, L.nn, om, tr, true, st);
-    }
-    return launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), x, L.gamma, L.s, L.nmask, t, (T *)L.slots,
-                                 D, b, om, st);
-}
-
 template <typename T>
 static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
 {
@@ -588,9 +583,21 @@ static int coarse_solve(Mg *mg, const T *b, T *x, bool tr, hipStream_t st)
     return FE_OK;
 }
 
+template <typename T>
+static T *altT(MgLevel &L);
+template <>
+double *altT<double>(MgLevel &L) { return L.xa; }
+template <>
+float *altT<float>(MgLevel &L) { return L.xa32; }
+
 // V-cycle from level l on b; x receives the result.  first_done: the first
 // pre-smoothing sweep from x = 0 (x = omega D^{-1} b) has already been applied
-// to x, by the restriction kernel of the level above.
+// to x, by the restriction kernel of the level above (or, at the finest level
+// of a mixed-precision cycle, together with the cast of the Krylov vector).
+// A damped block-Jacobi sweep x += omega D^{-1} (b - A x) (transposed when tr)
+// is fused with the element pass on matrix-free levels, and is one kernel on
+// assembled ones, which writes the new iterate to the level's second buffer:
+// the iterate alternates between x and that buffer, and ends in x.
 template <typename T>
 static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st, bool first_done = false)
 {
@@ -600,10 +607,22 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st, bool
     const T om = (T)mg->omega;
     const T *D = blocksT<T>(L);
     T *t = vecT<T>(L, 2);
+    T *cur = x;
+    auto sweep = [&]() -> hipError_t {
+        if (L.assembled) {
+            T *nxt = cur == x ? altT<T>(L) : x;
+            const hipError_t e = mg_stencil_smooth<T>(L.grid.nx, L.grid.ny, L.grid.nz, stencilT<T>(L),
+                                                      D, b, cur, nxt, om, tr, st);
+            cur = nxt;
+            return e;
+        }
+        return launch_elem_smooth<T>(tr, L.geo, stateT<T>(L), cur, L.gamma, L.s, L.nmask, t,
+                                     (T *)L.slots, D, b, om, st);
+    };
     if (!first_done) FE_CHECK_HIP(mg_smooth<T>(D, b, nullptr, x, L.nn, om, tr, false, st));
-    for (int it = 1; it < mg->nu1; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
+    for (int it = 1; it < mg->nu1; ++it) FE_CHECK_HIP(sweep());
     MgLevel &C = mg->lev[l + 1];
-    FE_CHECK_HIP(op<T>(L, x, t, tr, st));
+    FE_CHECK_HIP(op<T>(L, cur, t, tr, st));
     T *bc = vecT<T>(C, 0), *xc = vecT<T>(C, 1);
     // below the coarse level's first sweep is fused into the restriction,
     // except where that level is the directly solved coarsest one
@@ -615,8 +634,9 @@ static int vcycle(Mg *mg, int l, const T *b, T *x, bool tr, hipStream_t st, bool
         FE_CHECK_HIP(mg_restrict<T>(C.grid, L.grid, b, t, C.nmask, bc, st));
     int rc = vcycle<T>(mg, l + 1, bc, xc, tr, st, fuse);
     if (rc) return rc;
-    FE_CHECK_HIP(mg_prolong_add<T>(L.grid, C.grid, xc, L.nmask, x, st));
-    for (int it = 0; it < mg->nu2; ++it) FE_CHECK_HIP(smooth_sweep<T>(L, D, b, x, t, om, tr, st));
+    FE_CHECK_HIP(mg_prolong_add<T>(L.grid, C.grid, xc, L.nmask, cur, st));
+    for (int it = 0; it < mg->nu2; ++it) FE_CHECK_HIP(sweep());
+    if (cur != x) FE_CHECK_HIP(mg_copy<T>(cur, x, L.ndof, st));
     return FE_OK;
 }
 
@@ -628,8 +648,8 @@ int mg_apply64(Mg *mg, const double *v, double *z, bool tr, hipStream_t st)
 int mg_apply32(Mg *mg, const double *v, float *z, bool tr, hipStream_t st)
 {
     MgLevel &L0 = mg->lev[0];
-    FE_CHECK_HIP((launch_cast<double, float>(v, L0.b32, L0.ndof, st)));
-    return vcycle<float>(mg, 0, L0.b32, z, tr, st);
+    FE_CHECK_HIP(mg_smooth0_cast(L0.D32, v, L0.b32, z, L0.nn, (float)mg->omega, tr, st));
+    return vcycle<float>(mg, 0, L0.b32, z, tr, st, true);
 }
 
 }  // namespace fe

@@ -24,6 +24,8 @@ struct MgLevel {
     bool assembled = false;
     double *S = nullptr;
     float *S32 = nullptr;
+    double *xa = nullptr;   // second iterate buffer of the one-kernel sweeps
+    float *xa32 = nullptr;
 };
 
 struct Mg {

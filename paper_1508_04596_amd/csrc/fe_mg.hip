@@ -292,6 +292,147 @@ __global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, c
     stencil_apply_dofs<T, TR>(nx, ny, nz, S, v, out, blockIdx.x);
 }
 
+// One damped block-Jacobi sweep on an assembled level in one kernel:
+// x_out = x_in + omega D^{-1} (b - A x_in) (A^T and D^{-T} when TR) for 64 nodes
+// per workgroup.  Wave p sums the offsets d = 3p .. 3p + 2 for all five row
+// fields, the nine partials of a row are added in wave order (as in
+// k_stencil_apply), and the node's update is that of k_smooth, so x_out is
+// bitwise the result of the two-kernel sweep.  x_out must not alias x_in
+// (other workgroups read x_in at their neighbours).
+template <typename T, bool TR>
+__device__ __forceinline__ void stencil_smooth_nodes(int nx, int ny, int nz, const T *__restrict__ S,
+                                                     const T *__restrict__ D,
+                                                     const T *__restrict__ b,
+                                                     const T *__restrict__ xin,
+                                                     T *__restrict__ xout, T omega, unsigned blk)
+{
+    __shared__ T part[9][NF][64];
+    __shared__ T sD[64 * 25];
+    const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int64_t n0 = (int64_t)blk * 64;
+    // the workgroup's 64 nodal blocks, coalesced (entries past nn repeat the last)
+    {
+        const int64_t left = nn - n0;
+        const int cnt = (int)(left < 64 ? left : 64) * 25;
+        const T *src = D + n0 * 25;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int q = (int)threadIdx.x + 576 * k;
+            if (q < 64 * 25) sD[q] = src[q < cnt ? q : cnt - 1];
+        }
+    }
+    const int64_t N = n0 + lane;
+    const bool live = N < nn;
+    const int64_t Nc = live ? N : nn - 1;
+    const int I = (int)(Nc % (nx + 1));
+    const int64_t r = Nc / (nx + 1);
+    const int J = (int)(r % (ny + 1)), K = (int)(r / (ny + 1));
+    const int j = J + p % 3 - 1, k = K + p / 3 - 1;
+    const bool injk = j >= 0 && j <= ny && k >= 0 && k <= nz;
+    T xm[3][NF];
+    int64_t Mc[3];
+    bool inc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int i = I + c - 1;
+        inc[c] = live && injk && i >= 0 && i <= nx;
+        Mc[c] = inc[c] ? i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k) : Nc;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) xm[c][f] = xin[NF * Mc[c] + f];
+    }
+#pragma unroll
+    for (int g = 0; g < NF; ++g) {
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int d = 3 * p + c;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const T a = TR ? S[((26 - d) * 25 + f * NF + g) * nn + Mc[c]]
+                               : S[(d * 25 + g * NF + f) * nn + Nc];
+                const T t = a * xm[c][f];
+                acc += inc[c] ? t : T(0);
+            }
+        }
+        part[p][g][lane] = acc;
+    }
+    __syncthreads();
+    if (p == 0 && live) {
+        const T *Dn = sD + lane * 25;
+        T rr[NF];
+#pragma unroll
+        for (int g = 0; g < NF; ++g) {
+            T sum = part[0][g][lane];
+#pragma unroll
+            for (int w = 1; w < 9; ++w) sum += part[w][g][lane];
+            rr[g] = b[NF * N + g] - sum;
+        }
+#pragma unroll
+        for (int a = 0; a < NF; ++a) {
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < NF; ++c) acc += (TR ? Dn[c * NF + a] : Dn[a * NF + c]) * rr[c];
+            xout[NF * N + a] = xin[NF * N + a] + omega * acc;
+        }
+    }
+}
+
+template <typename T, bool TR>
+__global__ __launch_bounds__(576) void k_stencil_smooth(int nx, int ny, int nz, const T *__restrict__ S,
+                                                        const T *__restrict__ D,
+                                                        const T *__restrict__ b,
+                                                        const T *__restrict__ xin,
+                                                        T *__restrict__ xout, T omega)
+{
+    stencil_smooth_nodes<T, TR>(nx, ny, nz, S, D, b, xin, xout, omega, blockIdx.x);
+}
+
+// The first sweep from x = 0 of a mixed-precision V-cycle, reading the FP64
+// Krylov vector: b32 = (float) v and x = omega D^{-1} b32 (D^{-T} when TR) per
+// node -- bitwise k_cast followed by k_smooth<float, TR, false>.
+template <bool TR>
+__device__ __forceinline__ void smooth0_cast_nodes(const float *__restrict__ D,
+                                                   const double *__restrict__ v,
+                                                   float *__restrict__ b32, float *__restrict__ x,
+                                                   int64_t nn, float omega, unsigned blk)
+{
+    __shared__ float sD[256 * 25];
+    const int64_t n0 = (int64_t)blk * 256;
+    const float *Dn = stage_blocks256(D, n0, nn, sD);
+    const int64_t n = n0 + threadIdx.x;
+    if (n >= nn) return;
+    float r[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        r[f] = (float)v[NF * n + f];
+        b32[NF * n + f] = r[f];
+    }
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NF; ++c) acc += (TR ? Dn[c * NF + a] : Dn[a * NF + c]) * r[c];
+        x[NF * n + a] = omega * acc;
+    }
+}
+
+template <bool TR>
+__global__ __launch_bounds__(256) void k_smooth0_cast(const float *__restrict__ D,
+                                                      const double *__restrict__ v,
+                                                      float *__restrict__ b32, float *__restrict__ x,
+                                                      int64_t nn, float omega)
+{
+    smooth0_cast_nodes<TR>(D, v, b32, x, nn, omega, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T *__restrict__ a, T *__restrict__ b, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 // ---- coarsest level: explicit inverse from the band LU factors ---------------
 
 // Factors of P A = L U as the host factorisation leaves them (partial pivoting
@@ -675,6 +816,24 @@ __global__ __launch_bounds__(256) void kb_coarse_sum(const BCoarse<T> *__restric
     coarse_apply_rows<T>(a.nfull, a.n, a.nt, a.pos, a.P, a.b, a.x, blockIdx.x - (unsigned)off[e]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(576) void kb_stencil_smooth(const BStencilSmooth<T> *__restrict__ tab,
+                                                         const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BStencilSmooth<T> &a = tab[e];
+    stencil_smooth_nodes<T, false>(a.nx, a.ny, a.nz, a.S, a.D, a.b, a.xin, a.xout, a.omega,
+                                   blockIdx.x - (unsigned)off[e]);
+}
+
+__global__ __launch_bounds__(256) void kb_smooth0_cast(const BSmooth0Cast *__restrict__ tab,
+                                                       const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BSmooth0Cast &a = tab[e];
+    smooth0_cast_nodes<false>(a.D, a.v, a.b32, a.x, a.nn, a.omega, blockIdx.x - (unsigned)off[e]);
+}
+
 }  // namespace
 
 hipError_t mg_coarsen_elem(const fe_grid &c, const fe_grid &f, const double *fv, double *cv,
@@ -808,6 +967,39 @@ hipError_t mg_coarse_apply(int nfull, int m, const double *X, const int *fidx, c
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t mg_stencil_smooth(int nx, int ny, int nz, const T *S, const T *D, const T *b, const T *xin,
+                             T *xout, T omega, bool transpose, hipStream_t st)
+{
+    const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    if (transpose)
+        hipLaunchKernelGGL((k_stencil_smooth<T, true>), dim3(nblk(n, 64)), dim3(576), 0, st, nx, ny,
+                           nz, S, D, b, xin, xout, omega);
+    else
+        hipLaunchKernelGGL((k_stencil_smooth<T, false>), dim3(nblk(n, 64)), dim3(576), 0, st, nx, ny,
+                           nz, S, D, b, xin, xout, omega);
+    return hipGetLastError();
+}
+
+hipError_t mg_smooth0_cast(const float *D, const double *v, float *b32, float *x, int64_t nn,
+                           float omega, bool transpose, hipStream_t st)
+{
+    if (transpose)
+        hipLaunchKernelGGL(k_smooth0_cast<true>, dim3(nblk(nn)), dim3(256), 0, st, D, v, b32, x, nn,
+                           omega);
+    else
+        hipLaunchKernelGGL(k_smooth0_cast<false>, dim3(nblk(nn)), dim3(256), 0, st, D, v, b32, x,
+                           nn, omega);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mg_copy(const T *a, T *b, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy<T>, dim3(nblk(n)), dim3(256), 0, st, a, b, n);
+    return hipGetLastError();
+}
+
 #define FE_MG_INST(T)                                                                          \
     template hipError_t mg_restrict<T>(const fe_grid &, const fe_grid &, const T *, const T *,      \
                                        const uint8_t *, T *,                                      \
@@ -823,7 +1015,10 @@ hipError_t mg_coarse_apply(int nfull, int m, const double *X, const int *fidx, c
     template hipError_t mg_stencil_apply<T>(int, int, int, const T *, const T *, T *, bool,      \
                                             hipStream_t);                                      \
     template hipError_t mg_coarse_apply<T>(int, int, const double *, const int *, const int *,    \
-                                           const T *, T *, double *, bool, hipStream_t);
+                                           const T *, T *, double *, bool, hipStream_t);        \
+    template hipError_t mg_stencil_smooth<T>(int, int, int, const T *, const T *, const T *,      \
+                                             const T *, T *, T, bool, hipStream_t);              \
+    template hipError_t mg_copy<T>(const T *, T *, int64_t, hipStream_t);
 FE_MG_INST(double)
 FE_MG_INST(float)
 #undef FE_MG_INST
@@ -845,7 +1040,16 @@ FE_BLAUNCH(blaunch_restrict_smooth, kb_restrict_smooth<T>, BRestrict<T>, 255)
 FE_BLAUNCH(blaunch_prolong, kb_prolong<T>, BProlong<T>, 256)
 FE_BLAUNCH(blaunch_coarse_part, kb_coarse_part<T>, BCoarse<T>, 256)
 FE_BLAUNCH(blaunch_coarse_sum, kb_coarse_sum<T>, BCoarse<T>, 256)
+FE_BLAUNCH(blaunch_stencil_smooth, kb_stencil_smooth<T>, BStencilSmooth<T>, 576)
 #undef FE_BLAUNCH
+
+hipError_t blaunch_smooth0_cast(const BLaunch &L, hipStream_t st)
+{
+    if (L.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_smooth0_cast, dim3((unsigned)L.blocks), dim3(256), 0, st,
+                       (const BSmooth0Cast *)L.tab, L.off, L.n);
+    return hipGetLastError();
+}
 
 template <typename T, bool ACC>
 hipError_t blaunch_smooth(const BLaunch &L, hipStream_t st)
@@ -863,6 +1067,7 @@ hipError_t blaunch_smooth(const BLaunch &L, hipStream_t st)
     template hipError_t blaunch_prolong<T>(const BLaunch &, hipStream_t);                      \
     template hipError_t blaunch_coarse_part<T>(const BLaunch &, hipStream_t);                  \
     template hipError_t blaunch_coarse_sum<T>(const BLaunch &, hipStream_t);                   \
+    template hipError_t blaunch_stencil_smooth<T>(const BLaunch &, hipStream_t);               \
     template hipError_t blaunch_smooth<T, false>(const BLaunch &, hipStream_t);                \
     template hipError_t blaunch_smooth<T, true>(const BLaunch &, hipStream_t);
 FE_BMG_INST(double)
