@@ -139,10 +139,18 @@ hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, 
 // <V_j, w_new> for j < k2 (k2 may differ from k) or of <w_new, w_new> when k2 == -1.
 hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h, double *w,
                              int64_t n, int k2, double *partial, hipStream_t st);
-// out[j] = sum_b partial[j*RED_BLOCKS + b] (+ add[j] if add != NULL), j < k,
-// summed in a fixed order; if sqrt_last, out[k-1] = sqrt(out[k-1]).
+// out[j] = sum_{b < nparts} partial[j*RED_BLOCKS + b] (+ add[j] if add != NULL),
+// j < k, summed in a fixed order; if sqrt_last, out[k-1] = sqrt(out[k-1]).
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
-                         bool sqrt_last, hipStream_t st);
+                         bool sqrt_last, hipStream_t st, int nparts = RED_BLOCKS);
+// Workgroups (and partials per sum) of the Krylov vectors' reductions over n
+// entries: at least two entries per thread, at most RED_BLOCKS (reached from
+// n = 512 RED_BLOCKS on); short vectors thus avoid a grid of mostly idle
+// workgroups.  The partition depends on n only, so the sums are deterministic.
+inline int red_blocks(int64_t n)
+{
+    return (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 511) / 512));
+}
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st);
 // Orthogonalise w against V_0..V_{k-1} by classical Gram-Schmidt with one
 // conditional second pass (taken when the first pass removes more than 1 -

@@ -110,7 +110,7 @@ static int ensure_ws(fe_problem *p, int m, bool mixed)
 static int norm2(fe_problem *p, const double *a, hipStream_t st, double *out)
 {
     FE_CHECK_HIP(launch_norm2_partial(a, p->ndof, p->partial, st));
-    FE_CHECK_HIP(launch_reduce(p->partial, 1, p->scal, nullptr, true, st));
+    FE_CHECK_HIP(launch_reduce(p->partial, 1, p->scal, nullptr, true, st, red_blocks(p->ndof)));
     FE_CHECK_HIP(hipMemcpyAsync(p->ws->hhost, p->scal, sizeof(double), hipMemcpyDeviceToHost, st));
     FE_CHECK_HIP(hipStreamSynchronize(st));
     *out = p->ws->hhost[0];

@@ -199,21 +199,21 @@ __global__ void k_reorth_flag2(const double *__restrict__ w2_before, const doubl
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial,
                                                 double *__restrict__ out,
                                                 const double *__restrict__ add, int k, int sqrt_last,
-                                                const double *__restrict__ flag, int flag_mode)
+                                                const double *__restrict__ flag, int flag_mode,
+                                                int nparts)
 {
     // flag_mode 1: write zeros when *flag == 0; 2: leave out untouched when *flag == 0
     if (flag && flag[0] == 0.0) {
         if (flag_mode == 1 && threadIdx.x == 0) out[blockIdx.x] = 0.0;
         return;
     }
-    // one workgroup per output; RED_BLOCKS partials, summed in a fixed tree
-    static_assert(RED_BLOCKS % 256 == 0, "RED_BLOCKS must be a multiple of 256");
+    // one workgroup per output; nparts (<= RED_BLOCKS) partials, summed in a
+    // fixed tree: thread t adds partials t, t + 256, ... in order, then the waves
     __shared__ double red[4];
     const int j = blockIdx.x;
     const double *p = partial + (int64_t)j * RED_BLOCKS;
     double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < RED_BLOCKS / 256; ++q) s += p[threadIdx.x + 256 * q];
+    for (int q = threadIdx.x; q < nparts; q += 256) s += p[q];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -473,11 +473,11 @@ hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, 
                            double *partial, hipStream_t st)
 {
     if (k <= 8)
-        hipLaunchKernelGGL(k_multidot<8>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+        hipLaunchKernelGGL(k_multidot<8>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
     else if (k <= 32)
-        hipLaunchKernelGGL(k_multidot<32>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+        hipLaunchKernelGGL(k_multidot<32>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
     else
-        hipLaunchKernelGGL(k_multidot<65>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
+        hipLaunchKernelGGL(k_multidot<65>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
     return hipGetLastError();
 }
 
@@ -486,19 +486,19 @@ hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h
 {
     const int kk = k > k2 ? k : k2;
     if (kk <= 8)
-        hipLaunchKernelGGL(k_update_dot<8>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+        hipLaunchKernelGGL(k_update_dot<8>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
     else if (kk <= 32)
-        hipLaunchKernelGGL(k_update_dot<32>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+        hipLaunchKernelGGL(k_update_dot<32>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
     else
-        hipLaunchKernelGGL(k_update_dot<65>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
+        hipLaunchKernelGGL(k_update_dot<65>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
-                         bool sqrt_last, hipStream_t st)
+                         bool sqrt_last, hipStream_t st, int nparts)
 {
     hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, out, add, k, sqrt_last ? 1 : 0,
-                       (const double *)nullptr, 0);
+                       (const double *)nullptr, 0, nparts);
     return hipGetLastError();
 }
 
@@ -510,7 +510,7 @@ hipError_t launch_reduce(const double *partial, int k, double *out, const double
 static hipError_t mdot_exact(int k, bool norm, const double *V, int64_t ld, const double *w,
                              int64_t n, double *partial, const double *flag, hipStream_t st)
 {
-    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    const dim3 g(red_blocks(n)), b(RED_THREADS);
     switch (k) {
 #define FE_MD(K)                                                                               \
     case K:                                                                                    \
@@ -530,7 +530,7 @@ static hipError_t mdot_exact(int k, bool norm, const double *V, int64_t ld, cons
 static hipError_t upd_exact(int k, const double *V, int64_t ld, const double *h, double *w,
                             int64_t n, double *partial, const double *flag, hipStream_t st)
 {
-    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    const dim3 g(red_blocks(n)), b(RED_THREADS);
     switch (k) {
 #define FE_UP(K)                                                                               \
     case K:                                                                                    \
@@ -547,7 +547,7 @@ static hipError_t upd_exact(int k, const double *V, int64_t ld, const double *h,
 static hipError_t upd_mdot_exact(int k, const double *V, int64_t ld, const double *h, double *w,
                                  int64_t n, double *partial, hipStream_t st)
 {
-    const dim3 g(RED_BLOCKS), b(RED_THREADS);
+    const dim3 g(red_blocks(n)), b(RED_THREADS);
     switch (k) {
 #define FE_UM(K)                                                                               \
     case K:                                                                                    \
@@ -565,35 +565,36 @@ hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, 
                       double *partial, hipStream_t st)
 {
     hipError_t e;
+    const int np = red_blocks(n);
     if (k > 32) {  // long bases: unconditional two passes with the generic kernels
         if ((e = launch_multidot(V, ld, k, w, n, partial, st)) != hipSuccess) return e;
-        if ((e = launch_reduce(partial, k, hbuf, nullptr, false, st)) != hipSuccess) return e;
+        if ((e = launch_reduce(partial, k, hbuf, nullptr, false, st, np)) != hipSuccess) return e;
         if ((e = launch_update_dot(V, ld, k, hbuf, w, n, k, partial, st)) != hipSuccess) return e;
-        if ((e = launch_reduce(partial, k, hbuf + 65, nullptr, false, st)) != hipSuccess) return e;
+        if ((e = launch_reduce(partial, k, hbuf + 65, nullptr, false, st, np)) != hipSuccess) return e;
         if ((e = launch_update_dot(V, ld, k, hbuf + 65, w, n, -1, partial, st)) != hipSuccess) return e;
-        return launch_reduce(partial, 1, hbuf + 130, nullptr, true, st);
+        return launch_reduce(partial, 1, hbuf + 130, nullptr, true, st, np);
     }
     double *flag = hbuf + 131;
     // pass 1: h1 = V^T w and |w|^2 (stored at hbuf[k])
     if ((e = mdot_exact(k, true, V, ld, w, n, partial, nullptr, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf, (const double *)nullptr,
-                       k + 1, 0, (const double *)nullptr, 0);
+                       k + 1, 0, (const double *)nullptr, 0, np);
     // w -= V h1 and, in the same read of V, h2 = V^T w and beta1 = |w| (hbuf[65 + k])
     if ((e = upd_mdot_exact(k, V, ld, hbuf, w, n, partial, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf + 65,
-                       (const double *)nullptr, k + 1, 1, (const double *)nullptr, 0);
+                       (const double *)nullptr, k + 1, 1, (const double *)nullptr, 0, np);
     hipLaunchKernelGGL(k_reorth_flag2, dim3(1), dim3(64), 0, st, (const double *)(hbuf + k),
                        (const double *)(hbuf + 65 + k), flag, hbuf + 65, k, hbuf + 130);
     // the second pass's update only where the flag asks for it: w -= V h2, beta
     if ((e = upd_exact(k, V, ld, hbuf + 65, w, n, partial, flag, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
-                       (const double *)nullptr, 1, 1, flag, 2);
+                       (const double *)nullptr, 1, 1, flag, 2, np);
     return hipGetLastError();
 }
 
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_norm2_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, a, n, partial);
+    hipLaunchKernelGGL(k_norm2_partial, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, a, n, partial);
     return hipGetLastError();
 }
 
