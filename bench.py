@@ -46,13 +46,13 @@ PEAK_HBM = 8.0e12
 # torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
 # 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
 # whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.56, 17217.13
+ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.69, 17217.09
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
                       if ELEM_FETCH_KIB is not None else None)
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
-ELEM_TRAFFIC_SRC_SHA256 = "b06d00ff2bb7f5cb58e56714e4709d240cb3a9439729e817ee654f723fe40e13"
+ELEM_TRAFFIC_SRC_SHA256 = "bd823b2899c8aedc0a9ffff1ce7e1b6fed40a382440cf86e0a638cc1111f5d19"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
        "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
