@@ -278,10 +278,12 @@ typedef struct fe_server fe_server;
 int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
 /* flags = FE_SERVE_BATCHED: the same server, but the requests' linear solves
  * (one per Newton step: FGMRES with the multigrid V-cycle) run in lockstep on
- * one engine thread -- each FGMRES step launches every kernel once over a
- * device table of all running requests (concatenated element and DOF index
+ * engine threads -- each FGMRES step launches every kernel once over a device
+ * table of the engine's running requests (concatenated element and DOF index
  * spaces, per-request segmented reductions) -- while the workers keep the
- * set-up and line search of their requests.  max_active may then be up to 256.
+ * set-up and line search of their requests.  Requests go to one of four
+ * engines by their DOF count (below 50,000 / 150,000 / 450,000 / above), each
+ * with its own stream, so that requests batch with requests of similar size.  max_active may then be up to 256.
  * A request's result is the same alone and in any mix (its arithmetic does not
  * depend on the batch); it can differ from the default mode's in the last bits
  * (the batched Gram-Schmidt step always takes its second pass).  Requests whose

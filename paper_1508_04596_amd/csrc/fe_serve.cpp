@@ -2,8 +2,12 @@
 //
 // Two modes.  Default: each running request's whole Newton solve runs on its
 // worker's stream.  Batched (FE_SERVE_BATCHED): the workers run set-up and line
-// searches, and hand every linear solve to one lockstep engine (fe_batch.cpp)
-// whose FGMRES steps launch each kernel once over all running requests.
+// searches, and hand every linear solve to a lockstep engine (fe_batch.cpp)
+// whose FGMRES steps launch each kernel once over all its running requests.
+// There is one engine per size class of the grids (by DOF count, each class
+// three times the last), each with its own thread and stream: requests batch
+// with requests of similar size, a small request never waits for the steps of
+// a large one, and the classes' steps overlap on the device.
 //
 // One device arena of hbm_budget_bytes is allocated at creation.  An admitted
 // request takes one contiguous block of the arena, sized by its predicted
@@ -275,7 +279,9 @@ struct fe_server {
     uint64_t next_ticket = 1;
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point t0;
-    fe::BatchEngine *engine = nullptr;  // batched mode: lockstep FGMRES of all requests
+    // batched mode: lockstep FGMRES engines by grid size class
+    static constexpr int N_ENGINES = 4;
+    fe::BatchEngine *engine[N_ENGINES] = {};
 
     double now() const
     {
@@ -284,6 +290,16 @@ struct fe_server {
 };
 
 namespace {
+
+// Engine of a request in batched mode: classes of DOF count below 50,000, below
+// 150,000, below 450,000 and above (16^3, 24^3, 32^3 and 48^3 grids, 24,565 to
+// 588,245 DOF, fall in one class each).
+int engine_class(int64_t ndof)
+{
+    int c = 0;
+    for (int64_t lim = 50000; c < fe_server::N_ENGINES - 1 && ndof >= lim; lim *= 3) ++c;
+    return c;
+}
 
 size_t request_footprint(const fe_grid &g, const fe_solve_opts &o)
 {
@@ -302,7 +318,7 @@ int run_request(fe_server *S, Request *r, hipStream_t st)
     fe_problem *p = nullptr;
     int rc = problem_create_ex(&r->grid, &r->phys, nullptr, MASK_WALLS_PIN, &mem, st, &p);
     if (rc) return rc;
-    p->batch = S->engine;
+    p->batch = S->engine[engine_class(p->ndof)];
     const int64_t ne = p->ne, ndof = p->ndof;
     double *g = nullptr, *s = nullptr, *x = nullptr;
     hipError_t e = dalloc(p, &g, sizeof(double) * ne);
@@ -444,10 +460,13 @@ int serve_create_ex(size_t hbm_budget_bytes, int max_active, int flags, fe_serve
                                          (size_t)512 << 20);
     if (S->host_pool.init(pool) != hipSuccess) (void)hipGetLastError();  // pageable only
     if (batched) {
-        const int rc = batch_engine_create(S->device, &S->engine);
-        if (rc) {
-            delete S;
-            return rc;
+        for (auto &E : S->engine) {
+            const int rc = batch_engine_create(S->device, &E);
+            if (rc) {
+                for (auto &F : S->engine) batch_engine_destroy(F);
+                delete S;
+                return rc;
+            }
         }
     }
     S->t0 = std::chrono::steady_clock::now();
@@ -565,7 +584,7 @@ int serve_destroy(fe_server *S)
     }
     S->cv.notify_all();
     for (auto &t : S->workers) t.join();
-    batch_engine_destroy(S->engine);
+    for (auto &E : S->engine) batch_engine_destroy(E);
     delete S;
     return FE_OK;
 }
@@ -576,7 +595,15 @@ int serve_engine_stats(fe_server *S, uint64_t *steps, uint64_t *launches)
         set_error("serve_engine_stats: NULL server");
         return FE_EINVAL;
     }
-    batch_engine_stats(S->engine, steps, launches);
+    uint64_t st = 0, la = 0;
+    for (auto *E : S->engine) {
+        uint64_t a = 0, b = 0;
+        batch_engine_stats(E, &a, &b);
+        st += a;
+        la += b;
+    }
+    if (steps) *steps = st;
+    if (launches) *launches = la;
     return FE_OK;
 }
 
