@@ -301,7 +301,6 @@ struct BatchEngine {
     std::thread th;
     std::mutex mu;
     std::condition_variable cv;       // work arrived / stop
-    std::condition_variable cv_done;  // a solve finished
     std::vector<BJob *> incoming;
     bool stop = false;
     std::vector<Solve> active;
@@ -647,9 +646,13 @@ void BatchEngine::run()
                 if (gone) free_slots.push_back(S.slot);
             }
             active.swap(keep);
-            for (BJob *jb : done) jb->done = true;
+            // only the finished solves' workers are woken; notified under the
+            // lock, since a woken worker returns and its job object ends
+            for (BJob *jb : done) {
+                jb->done = true;
+                jb->cv.notify_one();
+            }
         }
-        if (!done.empty()) cv_done.notify_all();
     }
 }
 
@@ -713,7 +716,7 @@ int batch_fgmres(BatchEngine *E, BJob *job, hipStream_t st)
         std::unique_lock<std::mutex> lk(E->mu);
         E->incoming.push_back(job);
         E->cv.notify_all();
-        E->cv_done.wait(lk, [&] { return job->done; });
+        job->cv.wait(lk, [&] { return job->done; });
     }
     if (job->rc != FE_OK && !job->error.empty()) set_error(job->error);
     return job->rc;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -207,6 +208,7 @@ struct BJob {
     bool converged = false, done = false;
     double res_true = 0.0;
     std::string error;
+    std::condition_variable cv;       // the submitting worker waits here for done
 };
 int batch_engine_create(int device, BatchEngine **out);
 void batch_engine_destroy(BatchEngine *E);

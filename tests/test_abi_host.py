@@ -82,13 +82,14 @@ def test_footprint_grows_with_grid_and_restart(fe):
 
 def test_footprint_counts_assembled_levels(fe):
     """32^3: levels 16^3 and 8^3 (4913 and 729 nodes) are assembled by default,
-    each holding 675 FP64 stencil entries per node (plus FP32 copies when mixed)."""
+    each holding 675 FP64 stencil entries per node and a second iterate of 5
+    values per node for its one-kernel sweeps (plus FP32 copies when mixed)."""
     for prec in ("fp64", "mixed"):
         base = fe.fe_solve_footprint_bytes(32, 32, 32, opts=fe.solve_opts(krylov_op_prec=prec,
                                                                           mg_assembled_nodes=0))
         full = fe.fe_solve_footprint_bytes(32, 32, 32, opts=fe.solve_opts(krylov_op_prec=prec))
         per = 12 if prec == "mixed" else 8
-        stencil = per * 675 * (4913 + 729)
+        stencil = per * (675 + 5) * (4913 + 729)
         je = 8 * 1600 * (16 ** 3 - 4 ** 3)  # element Jacobians sized for the 16^3 level
         assert full - base == pytest.approx(stencil + je, abs=4 * 256)
 
