@@ -283,7 +283,10 @@ int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
  * spaces, per-request segmented reductions) -- while the workers keep the
  * set-up and line search of their requests.  Requests go to one of four
  * engines by their DOF count (below 50,000 / 150,000 / 450,000 / above), each
- * with its own stream, so that requests batch with requests of similar size.  max_active may then be up to 256.
+ * with its own stream, so that requests batch with requests of similar size.
+ * Requests that leave fe_solve_opts.mg_assembled_nodes at its default (-1)
+ * get a limit of 1,000 nodes for assembled multigrid levels in this mode
+ * (over a batch the element pass moves far fewer bytes than a stencil).  max_active may then be up to 256.
  * A request's result is the same alone and in any mix (its arithmetic does not
  * depend on the batch); it can differ from the default mode's in the last bits
  * (the batched Gram-Schmidt step always takes its second pass).  Requests whose
