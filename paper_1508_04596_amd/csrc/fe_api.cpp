@@ -123,7 +123,7 @@ int problem_create_ex(const fe_grid *grid, const fe_phys *phys, const uint8_t *d
     if ((e = dalloc(p, &p->nmask, p->nn)) != hipSuccess ||
         (e = dalloc(p, &p->dof_mask, p->ndof)) != hipSuccess ||
         (e = dalloc(p, &p->slots, slot_bytes)) != hipSuccess ||
-        (e = dalloc(p, &p->partial, sizeof(double) * 66 * RED_BLOCKS)) != hipSuccess ||
+        (e = dalloc(p, &p->partial, sizeof(double) * PARTIAL_COLS * RED_BLOCKS)) != hipSuccess ||
         (e = dalloc(p, &p->scal, sizeof(double) * 256)) != hipSuccess) {
         fe_problem_destroy(p);
         return hip_fail(e, "device allocation (problem)");

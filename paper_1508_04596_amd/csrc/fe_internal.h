@@ -133,13 +133,6 @@ hipError_t launch_invert_blocks32(float *D32, int64_t nn, hipStream_t st);
 template <typename Tm, typename Tin, typename Tout>
 hipError_t launch_block_apply(const Tm *D, const Tin *v, Tout *z, int64_t nn, bool transpose,
                               const double *scale_dev, hipStream_t st);
-// partial[j*RED_BLOCKS + b] = block b's share of <V_j, w>, j < k; V_j = V + j*ld.
-hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
-                           double *partial, hipStream_t st);
-// w -= sum_j h[j] V_j (h on device), and, if partial != NULL, partial sums of
-// <V_j, w_new> for j < k2 (k2 may differ from k) or of <w_new, w_new> when k2 == -1.
-hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h, double *w,
-                             int64_t n, int k2, double *partial, hipStream_t st);
 // out[j] = sum_{b < nparts} partial[j*RED_BLOCKS + b] (+ add[j] if add != NULL),
 // j < k, summed in a fixed order; if sqrt_last, out[k-1] = sqrt(out[k-1]).
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
@@ -153,12 +146,28 @@ inline int red_blocks(int64_t n)
     return (int)std::min<int64_t>(RED_BLOCKS, std::max<int64_t>(1, (n + 511) / 512));
 }
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st);
-// Orthogonalise w against V_0..V_{k-1} by classical Gram-Schmidt with one
-// conditional second pass (taken when the first pass removes more than 1 -
-// 1/sqrt(2) of the norm): hbuf[0..k) = first-pass coefficients, hbuf[65..65+k)
-// = second-pass coefficients (0 when skipped), hbuf[130] = |w| after.
-hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, double *hbuf,
-                      double *partial, hipStream_t st);
+// Columns of the reduction buffer `partial` (RED_BLOCKS partials each): the
+// dot pass of a Gram-Schmidt step with J <= 63 final basis vectors fills 2J + 3.
+constexpr int PARTIAL_COLS = 130;
+// One FGMRES Arnoldi step's orthogonalisation by classical Gram-Schmidt with a
+// delayed second projection (V of leading dimension ld: final basis vectors
+// in columns 0 .. J-1, the scaled once-projected candidate in column J, the
+// new Krylov vector w in column J + 1).  One pass reads the basis for all dot
+// products, one pass updates: column J becomes the basis vector q_J (the
+// candidate projected a second time and normalised), column J + 1 the next
+// candidate (w projected once against q_0 .. q_J, divided by |w|).  hb (device)
+// receives s_i = <q_i, c> at i < J, a = <c, c> at J, p_i = <q_i, w> at J + 1 + i,
+// t = <c, w> at 2J + 1, e = <w, w> at 2J + 2, sigma = |c - sum s_i q_i|, the
+// coefficient h = <q_J, w>, omega = |w|, 1/sigma, 1/omega at 2J + 3 .. 2J + 7
+// and the squared norm of the next candidate at 2J + 8 (sigma = 0: nothing left
+// of the candidate, q_J = 0).  0 <= J <= 63.
+hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, double *partial,
+                           hipStream_t st);
+// The candidate's dot products alone (no new Krylov vector; it finishes the
+// last Hessenberg column of a cycle): hb[i] = <q_i, c> for i < J, hb[J] = <c, c>.
+// 1 <= J <= 64.
+hipError_t launch_dgs_final(const double *V, int64_t ld, int J, int64_t n, double *hb,
+                            double *partial, hipStream_t st);
 // y = a*x + b*y (y is not read when b == 0)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
 // y = x + lam*d
@@ -249,7 +258,7 @@ struct fe_problem {
     uint8_t *dof_mask = nullptr;  // per DOF copy of the caller's mask
     double *slots = nullptr;      // tile-face partial sums (5 values / node box entry)
     double *slots25 = nullptr;    // block-diagonal partial sums (25 values)
-    double *partial = nullptr;    // reduction partials, 66 * RED_BLOCKS
+    double *partial = nullptr;    // reduction partials, PARTIAL_COLS * RED_BLOCKS
     double *scal = nullptr;       // device scalars
     fe::SolverWs *ws = nullptr;    // Newton/FGMRES workspace (allocated on first solve)
     fe::BatchEngine *batch = nullptr; // if set, Newton's multigrid FGMRES solves run on it

@@ -1,13 +1,13 @@
 // Host-driven solvers over the device kernels: flexible GMRES with classical
-// Gram-Schmidt (a second pass where the first loses more than 1 - 1/sqrt(2) of
-// the norm) in FP64, damped Newton with the quadratic L2 line
+// Gram-Schmidt (two projections per basis vector, the second delayed into the
+// next step) in FP64, damped Newton with the quadratic L2 line
 // search (Sec. "Solving the non-linear system"), the adjoint solve, and the
 // FP32-operator / FP64-residual refinement used in mixed mode.
 //
 // The Krylov basis V, the Hessenberg matrix, the Givens rotations and every
 // norm are FP64.  One Arnoldi step runs entirely on the device; the host reads
-// back one Hessenberg column (j+2 numbers) per step to update the Givens
-// rotations and test convergence.
+// back its dot products (2j + 9 numbers) to finish a Hessenberg column, update
+// the Givens rotations and test convergence.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -30,7 +30,7 @@ struct SolverWs {
     double *R = nullptr, *Rh = nullptr, *R1 = nullptr, *xt = nullptr, *delta = nullptr;
     double *rhs = nullptr, *V = nullptr, *Z = nullptr, *D = nullptr, *tmp = nullptr;
     float *Z32 = nullptr, *D32 = nullptr, *x32 = nullptr;
-    double *hbuf = nullptr;  // device: h1[65] | h2[65] | beta
+    double *hbuf = nullptr;  // device: Gram-Schmidt products of a step | [255] cycle scale
     double *ydev = nullptr;  // device: combination coefficients
     double *hhost = nullptr; // pinned host copy of hbuf / y
     hipEvent_t ev[8] = {};
@@ -135,10 +135,65 @@ struct LinStats {
     double res_true = 0;
 };
 
+// Column c of the Hessenberg matrix H (m columns, entries 0 .. c+1 set) gets
+// the rotations 0 .. c-1, defines rotation c and advances g; returns the
+// residual estimate |g[c+1]|.
+static double givens_column(std::vector<double> &H, int m, int c, std::vector<double> &cs,
+                            std::vector<double> &sn, std::vector<double> &g)
+{
+    for (int i = 0; i < c; ++i) {
+        const double a = H[(size_t)i * m + c], b = H[(size_t)(i + 1) * m + c];
+        H[(size_t)i * m + c] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + c] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[(size_t)c * m + c], hn = H[(size_t)(c + 1) * m + c];
+    const double den = std::hypot(a, hn);
+    if (den == 0.0) {
+        cs[c] = 1.0;
+        sn[c] = 0.0;
+    } else {
+        cs[c] = a / den;
+        sn[c] = hn / den;
+    }
+    H[(size_t)c * m + c] = cs[c] * a + sn[c] * hn;
+    H[(size_t)(c + 1) * m + c] = 0.0;
+    g[c + 1] = -sn[c] * g[c];
+    g[c] = cs[c] * g[c];
+    return std::fabs(g[c + 1]);
+}
+
+// The residual estimate that column c with entries col[0 .. c+1] would give,
+// state unchanged.
+static double givens_estimate(const std::vector<double> &col, int c, const std::vector<double> &cs,
+                              const std::vector<double> &sn, const std::vector<double> &g)
+{
+    std::vector<double> v(col.begin(), col.begin() + c + 2);
+    for (int i = 0; i < c; ++i) {
+        const double a = v[i], b = v[i + 1];
+        v[i] = cs[i] * a + sn[i] * b;
+        v[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double den = std::hypot(v[c], v[c + 1]);
+    return den == 0.0 ? std::fabs(g[c]) : std::fabs(g[c]) * std::fabs(v[c + 1]) / den;
+}
+
 // Solve A x = b for x (x = 0 on entry) to |b - A x| <= rtol |b|, FGMRES(m).
 // Mixed mode (z32): the Arnoldi process uses the FP32 operator; each cycle
 // ends with the true FP64 residual b - A x, and cycles continue while it is
 // above the target, at most n_refine cycles beyond the first convergence.
+//
+// Orthogonalisation is classical Gram-Schmidt with two projections per basis
+// vector, the second one delayed by a step (launch_dgs_step): step j
+// preconditions the candidate c_j (the previous Krylov vector after its first
+// projection, divided by that vector's norm omega_j), and the same pass over
+// the basis that projects the new Krylov vector also gives the candidate's
+// second projection.  So column j - 1 of H is final only in step j:
+// A z_{j-1} = sum_{i<j} Hp_i q_i + omega_j c_j with c_j = sum_{i<j} s_i q_i +
+// sigma_j q_j gives H_{i,j-1} = Hp_i + omega_j s_i and H_{j,j-1} = omega_j
+// sigma_j.  Before each step the residual that the provisional column would
+// give (subdiagonal omega_j |c_j|) is checked; when it reaches the target, the
+// column is finished from the candidate's dot products alone
+// (launch_dgs_final), so the cycle does not pay for a step it does not use.
 static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, double rtol, int m,
                   int max_its, int n_refine, hipStream_t st, LinStats *stats, int verbose)
 {
@@ -160,78 +215,103 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
         return FE_OK;
     }
     const double target = rtol * beta0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), Hp(m + 2);
     const double *r = b;  // residual of the current cycle (b on the first cycle)
     double beta = beta0;
     int refine_left = n_refine;
-    bool first = true;
     while (true) {
-        // v0 = r / beta
+        // candidate c_0 = r / beta (r = beta c_0)
         w->hhost[200] = beta;
-        FE_CHECK_HIP(hipMemcpyAsync(w->hbuf + 130, w->hhost + 200, sizeof(double),
+        FE_CHECK_HIP(hipMemcpyAsync(w->hbuf + 255, w->hhost + 200, sizeof(double),
                                     hipMemcpyHostToDevice, st));
-        FE_CHECK_HIP(launch_scale_div(n, r, w->hbuf + 130, w->V, st));
+        FE_CHECK_HIP(launch_scale_div(n, r, w->hbuf + 255, w->V, st));
         std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int j = 0;
+        double om = beta, c2 = 1.0;  // scale and squared norm of the candidate
         double res = beta;
         bool breakdown = false;
-        for (j = 0; j < m; ++j) {
-            double *vj = w->V + (int64_t)j * ld;
+        int kk = 0;  // final columns of H
+        // column j - 1 of H from its provisional entries Hp and the candidate's
+        // dot products s (host copy) and remaining norm sig
+        auto finish = [&](int j, const double *s, double sig) {
+            for (int i = 0; i < j; ++i) H[(size_t)i * m + (j - 1)] = Hp[i] + om * s[i];
+            H[(size_t)j * m + (j - 1)] = om * sig;
+            res = givens_column(H, m, j - 1, cs, sn, g);
+            kk = j;
+            if (!(om * sig > 1e-300 * beta0)) breakdown = true;
+        };
+        for (int j = 0;; ++j) {
+            if (j >= 1) {
+                bool fin = j == m || stats->its >= max_its;
+                if (!fin) {
+                    Hp[j] = om * std::sqrt(std::max(c2, 0.0));
+                    fin = givens_estimate(Hp, j - 1, cs, sn, g) <= target;
+                }
+                if (fin) {
+                    FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
+                    FE_CHECK_HIP(launch_dgs_final(w->V, ld, j, n, w->hbuf, p->partial, st));
+                    FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
+                    FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * (j + 1),
+                                                hipMemcpyDeviceToHost, st));
+                    FE_CHECK_HIP(hipStreamSynchronize(st));
+                    float ms;
+                    if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
+                    const double *hh = w->hhost;
+                    double ss = 0.0;
+                    for (int i = 0; i < j; ++i) ss += hh[i] * hh[i];
+                    const double s2 = hh[j] - ss;
+                    if (!std::isfinite(s2)) {
+                        set_error("non-finite Krylov norm");
+                        return FE_ENAN;
+                    }
+                    finish(j, hh, s2 > 0.0 ? std::sqrt(s2) : 0.0);
+                    if (res <= target || stats->its >= max_its || j == m || breakdown) break;
+                }
+            } else if (stats->its >= max_its) {
+                break;
+            }
+            // Arnoldi step j: z_j = M c_j, w = A z_j into column j + 1, then the
+            // two Gram-Schmidt passes
+            double *cj = w->V + (int64_t)j * ld;
             double *vn = w->V + (int64_t)(j + 1) * ld;
             void *zj = L.z32 ? (void *)(w->Z32 + (int64_t)j * ld) : (void *)(w->Z + (int64_t)j * ld);
             FE_CHECK_HIP(hipEventRecord(w->ev[0], st));
-            FE_CHECK_HIP(L.prec(vj, zj));
+            FE_CHECK_HIP(L.prec(cj, zj));
             FE_CHECK_HIP(hipEventRecord(w->ev[1], st));
             FE_CHECK_HIP(L.op_z(zj, vn));
             FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
-            const int k = j + 1;
-            FE_CHECK_HIP(launch_cgs(w->V, ld, k, vn, n, w->hbuf, p->partial, st));
-            FE_CHECK_HIP(launch_scale_div(n, vn, w->hbuf + 130, vn, st));
+            FE_CHECK_HIP(launch_dgs_step(w->V, ld, j, n, w->hbuf, p->partial, st));
             FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
-            FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * 131,
+            FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * (2 * j + 9),
                                         hipMemcpyDeviceToHost, st));
             FE_CHECK_HIP(hipStreamSynchronize(st));
+            stats->its++;
             float ms;
             if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) stats->t_prec += ms * 1e-3;
             if (hipEventElapsedTime(&ms, w->ev[1], w->ev[2]) == hipSuccess) stats->t_jv += ms * 1e-3;
             if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
             const double *hh = w->hhost;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[65 + i];
-            const double hn = hh[130];
-            if (!std::isfinite(hn)) {
+            const double sig = hh[2 * j + 3], hj = hh[2 * j + 4], omn = hh[2 * j + 5];
+            const double cn2 = hh[2 * j + 8];
+            if (!std::isfinite(sig) || !std::isfinite(hj) || !std::isfinite(omn) || !std::isfinite(cn2)) {
                 set_error("non-finite Krylov norm");
                 return FE_ENAN;
             }
-            // apply previous rotations to column j
-            for (int i = 0; i < j; ++i) {
-                double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-            }
-            double a = H[(size_t)j * m + j];
-            double den = std::hypot(a, hn);
-            if (den == 0.0) {
-                cs[j] = 1.0;
-                sn[j] = 0.0;
+            if (j == 0) {
+                g[0] = om * sig;  // r = beta sigma_0 q_0
+                if (!(sig > 0.0)) breakdown = true;
             } else {
-                cs[j] = a / den;
-                sn[j] = hn / den;
+                finish(j, hh, sig);
             }
-            H[(size_t)j * m + j] = cs[j] * a + sn[j] * hn;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            res = std::fabs(g[j + 1]);
-            stats->its++;
-            if (hn <= 1e-300 * beta0) breakdown = true;
-            if (res <= target || stats->its >= max_its || breakdown) {
-                ++j;
-                break;
-            }
+            // a column that already meets the target ends the cycle; the step's
+            // Krylov vector is then not used
+            if (breakdown || (j >= 1 && res <= target)) break;
+            // provisional column j: the coefficients of w's first projection
+            for (int i = 0; i < j; ++i) Hp[i] = hh[j + 1 + i];
+            Hp[j] = hj;
+            om = omn;
+            c2 = cn2;
         }
-        // y = H^{-1} g (upper triangular j x j), x += Z y
-        const int kk = j;
+        // y = H^{-1} g (upper triangular kk x kk), x += Z y
         for (int i = kk - 1; i >= 0; --i) {
             double s = g[i];
             for (int c = i + 1; c < kk; ++c) s -= H[(size_t)i * m + c] * y[c];
@@ -271,9 +351,7 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
         // next cycle solves A d = r and adds d to x: keep x, restart from r
         // (x accumulates across cycles since each cycle adds Z y to it)
         r = w->tmp;
-        (void)first;
-        first = false;
-        // r lives in tmp; the next cycle's v0 = r / beta copies it into V before
+        // r lives in tmp; the next cycle's c_0 = r / beta copies it into V before
         // tmp is reused for the following true residual.
     }
     return FE_OK;
@@ -354,7 +432,7 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
     auto r = [](int64_t b) { return (b + 255) / 256 * 256; };
     int64_t b = 0;
     // problem handle
-    b += r(nn) + r(ndof) + r(ntile * BOXN * NF * 8) + r(66 * RED_BLOCKS * 8) + r(256 * 8);
+    b += r(nn) + r(ndof) + r(ntile * BOXN * NF * 8) + r((int64_t)PARTIAL_COLS * RED_BLOCKS * 8) + r(256 * 8);
     // solver workspace
     b += 7 * r(8 * ndof) + r(8 * ndof * (opts->restart + 1)) + r(8 * ndof * opts->restart);
     if (mixed) b += r(4 * ndof * opts->restart) + r(4 * 25 * nn) + r(4 * ndof);

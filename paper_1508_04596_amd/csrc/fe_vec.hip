@@ -3,9 +3,9 @@
 // Reductions are deterministic: a fixed grid of RED_BLOCKS workgroups each sums
 // a fixed strided range (wave64 shuffles, then LDS across the four waves) into
 // one partial per workgroup; a second kernel adds the partials in a fixed tree
-// order.  Multi-dot products for classical Gram-Schmidt keep up to 64 running
-// sums per thread in registers, so the basis vectors are streamed once per
-// pass; the update w -= V h is fused with the next pass's dot products.
+// order.  Gram-Schmidt is classical with the second projection of each basis
+// vector delayed into the next step, so that a step streams the basis twice:
+// one pass for all its dot products, one for the updates.
 #include "fe_internal.h"
 
 namespace fe {
@@ -39,174 +39,155 @@ __device__ __forceinline__ void block_sums(double (&acc)[KMAX], int k, double *p
     }
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(RED_THREADS) void k_multidot(const double *__restrict__ V, int64_t ld,
-                                                          int k, const double *__restrict__ w,
-                                                          int64_t n, double *__restrict__ partial)
+// ---- delayed classical Gram-Schmidt ---------------------------------------
+// A step with J final basis vectors q_0 .. q_{J-1} (columns 0 .. J-1 of V),
+// the candidate c (column J: the previous Krylov vector after one projection,
+// scaled) and the new Krylov vector w (column J + 1) streams V twice.  The dot
+// pass forms, as reduction columns of `partial`,
+//   s_i = <q_i, c> at i (i < J), a = <c, c> at J, p_i = <q_i, w> at J + 1 + i,
+//   t = <c, w> at 2J + 1, e = <w, w> at 2J + 2,
+// so the candidate's second projection and w's first one share one read of
+// the basis; the update pass then writes q_J = (c - sum s_i q_i) / sigma and
+// the next candidate (w - sum p_i q_i - h q_J) / omega (sigma, h, omega from
+// k_dgs_coef).  A launch covers at most DGS_GROUP basis columns; the group that
+// starts at column 0 also accumulates a, t and e.
+constexpr int DGS_GROUP = 32;
+
+// Reduction column of accumulator q of a group of nc columns from c0.
+__device__ __forceinline__ int dgs_out(int q, int nc, bool w, int J, int c0)
 {
-    double acc[KMAX];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < k) acc[j] += V[j * ld + i] * wi;
+    if (q < nc) return c0 + q;  // s
+    q -= nc;
+    if (w) {
+        if (q < nc) return J + 1 + c0 + q;  // p
+        q -= nc;
     }
-    block_sums<KMAX>(acc, k, partial);
+    return q == 0 ? J : (q == 1 ? 2 * J + 1 : 2 * J + 2);  // a, t, e
 }
 
-// w -= sum_{j<k} h[j] V_j; then partial <V_j, w> for j < k2, or <w, w> if k2 == -1.
-template <int KMAX>
-__global__ __launch_bounds__(RED_THREADS) void k_update_dot(const double *__restrict__ V, int64_t ld,
-                                                            int k, const double *__restrict__ h,
-                                                            double *__restrict__ w, int64_t n,
-                                                            int k2, double *__restrict__ partial)
+template <int NC, bool W, bool FIRST>
+__global__ __launch_bounds__(RED_THREADS) void k_dgs_dots(const double *__restrict__ V, int64_t ld,
+                                                          int J, int c0, int64_t n,
+                                                          double *__restrict__ partial)
 {
-    __shared__ double hs[KMAX];
-    if (threadIdx.x < KMAX && (int)threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc[KMAX];
+    constexpr int NS = NC * (W ? 2 : 1);
+    constexpr int NA = NS + (FIRST ? (W ? 3 : 1) : 0);
+    const double *__restrict__ c = V + (int64_t)J * ld;
+    const double *__restrict__ w = V + (int64_t)(J + 1) * ld;
+    double acc[NA];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double vj[KMAX];
-        double wi = w[i];
+        const double ci = c[i];
+        const double wi = W ? w[i] : 0.0;
+        double qv[NC > 0 ? NC : 1];
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < k) {
-                vj[j] = V[j * ld + i];
-                wi -= hs[j] * vj[j];
+        for (int k = 0; k < NC; ++k) qv[k] = V[(int64_t)(c0 + k) * ld + i];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += qv[k] * ci;
+        if (W) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) acc[NC + k] += qv[k] * wi;
+        }
+        if (FIRST) {
+            acc[NS] += ci * ci;
+            if (W) {
+                acc[NS + 1] += ci * wi;
+                acc[NS + 2] += wi * wi;
             }
-        w[i] = wi;
-        if (k2 == -1) {
-            acc[0] += wi * wi;
-        } else {
-#pragma unroll
-            for (int j = 0; j < KMAX; ++j)
-                if (j < k2) acc[j] += vj[j] * wi;
         }
     }
-    if (partial) block_sums<KMAX>(acc, k2 == -1 ? 1 : k2, partial);
-}
-
-// Exact-count variants (K known at compile time, every load of an element
-// issued together).  flag: optional device flag; the kernel does nothing
-// when it is 0 (conditional second Gram-Schmidt pass).
-template <int K, bool NORM>
-__global__ __launch_bounds__(RED_THREADS) void k_mdot(const double *__restrict__ V, int64_t ld,
-                                                      const double *__restrict__ w, int64_t n,
-                                                      double *__restrict__ partial,
-                                                      const double *__restrict__ flag)
-{
-    if (flag && flag[0] == 0.0) return;
-    constexpr int KA = K + (NORM ? 1 : 0);
-    double acc[KA];
+    __shared__ double red[RED_THREADS / 64][NA];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < KA; ++j) acc[j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double wi = w[i];
-        double vj[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] += vj[j] * wi;
-        if (NORM) acc[KA - 1] += wi * wi;
+    for (int q = 0; q < NA; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = v;
     }
-    block_sums<KA>(acc, KA, partial);
+    __syncthreads();
+    if ((int)threadIdx.x < NA) {
+        const int q = threadIdx.x;
+        partial[(int64_t)dgs_out(q, NC, W, J, c0) * RED_BLOCKS + blockIdx.x] =
+            (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
 }
 
-template <int K>
-__global__ __launch_bounds__(RED_THREADS) void k_upd(const double *__restrict__ V, int64_t ld,
-                                                     const double *__restrict__ h,
-                                                     double *__restrict__ w, int64_t n,
-                                                     double *__restrict__ partial,
-                                                     const double *__restrict__ flag)
+// sigma = sqrt(a - |s|^2) (the candidate's norm after its second projection;
+// 0 when nothing is left of it), h = (t - <s, p>) / sigma (the coefficient of w
+// on q_J), omega = |w|.  One wave, J <= 64; hb holds the reduced dot products
+// and receives sigma, h, omega, 1/sigma, 1/omega at 2J + 3 .. 2J + 7.
+__global__ void k_dgs_coef(double *__restrict__ hb, int J)
 {
-    if (flag && flag[0] == 0.0) return;
-    __shared__ double hs[K];
-    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+    const int l = threadIdx.x;
+    const double sl = l < J ? hb[l] : 0.0;
+    const double pl = l < J ? hb[J + 1 + l] : 0.0;
+    const double ss = wave_sum(sl * sl), sp = wave_sum(sl * pl);
+    const double s2 = hb[J] - ss;
+    const double sig = s2 > 0.0 ? sqrt(s2) : 0.0;
+    const double h = sig > 0.0 ? (hb[2 * J + 1] - sp) / sig : 0.0;
+    const double om = sqrt(hb[2 * J + 2]);
+    if (l == 0) {
+        hb[2 * J + 3] = sig;
+        hb[2 * J + 4] = h;
+        hb[2 * J + 5] = om;
+        hb[2 * J + 6] = sig > 0.0 ? 1.0 / sig : 0.0;
+        hb[2 * J + 7] = om > 0.0 ? 1.0 / om : 0.0;
+    }
+}
+
+// Update pass over the basis columns c0 .. c0 + NC - 1: c -= sum s_i q_i and
+// w -= sum p_i q_i.  FINAL (the last group): then q_J = c / sigma into column
+// J, the next candidate (w - h q_J) / omega into column J + 1, and the
+// partials of its squared norm.  Columns below J are only read, so the three
+// pointers never address the same entries.
+template <int NC, bool FINAL>
+__global__ __launch_bounds__(RED_THREADS) void k_dgs_update(const double *__restrict__ Q, double *__restrict__ c,
+                                                            double *__restrict__ w, int64_t ld, int J,
+                                                            int c0, int64_t n,
+                                                            const double *__restrict__ hb,
+                                                            double *__restrict__ partial)
+{
+    __shared__ double cs[NC > 0 ? NC : 1], cp[NC > 0 ? NC : 1];
+    if ((int)threadIdx.x < NC) {
+        cs[threadIdx.x] = hb[c0 + threadIdx.x];
+        cp[threadIdx.x] = hb[J + 1 + c0 + threadIdx.x];
+    }
     __syncthreads();
+    const double h = FINAL ? hb[2 * J + 4] : 0.0;
+    const double isg = FINAL ? hb[2 * J + 6] : 0.0;
+    const double iom = FINAL ? hb[2 * J + 7] : 0.0;
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double vj[K];
+        double qv[NC > 0 ? NC : 1];
 #pragma unroll
-        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
-        double wi = w[i];
+        for (int k = 0; k < NC; ++k) qv[k] = Q[(int64_t)(c0 + k) * ld + i];
+        double ci = c[i], wi = w[i];
 #pragma unroll
-        for (int j = 0; j < K; ++j) wi -= hs[j] * vj[j];
-        w[i] = wi;
-        acc[0] += wi * wi;
+        for (int k = 0; k < NC; ++k) {
+            ci -= cs[k] * qv[k];
+            wi -= cp[k] * qv[k];
+        }
+        if (FINAL) {
+            const double qj = ci * isg;
+            const double cn = (wi - h * qj) * iom;
+            c[i] = qj;
+            w[i] = cn;
+            acc[0] += cn * cn;
+        } else {
+            c[i] = ci;
+            w[i] = wi;
+        }
     }
-    block_sums<1>(acc, 1, partial);
-}
-
-// The first pass's update fused with the second pass's projection: w -= V h
-// (h = V^T w from the first pass), then the partials of V^T w and |w|^2 of the
-// updated w, in the same per-thread order as k_upd followed by k_mdot<K, true>,
-// so V is read once for both.
-template <int K>
-__global__ __launch_bounds__(RED_THREADS) void k_upd_mdot(const double *__restrict__ V, int64_t ld,
-                                                          const double *__restrict__ h,
-                                                          double *__restrict__ w, int64_t n,
-                                                          double *__restrict__ partial)
-{
-    __shared__ double hs[K];
-    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc[K + 1];
-#pragma unroll
-    for (int j = 0; j <= K; ++j) acc[j] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double vj[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
-        double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < K; ++j) wi -= hs[j] * vj[j];
-        w[i] = wi;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] += vj[j] * wi;
-        acc[K] += wi * wi;
-    }
-    block_sums<K + 1>(acc, K + 1, partial);
-}
-
-// After the fused pass: flag = 1 when the projected norm beta1 fell below
-// 1/sqrt(2) of the original norm (the second pass's update is needed), else 0,
-// in which case the second-pass coefficients h2 are zeroed and beta = beta1.
-// One wave (k <= 32): lane j zeroes h2[j], lane 0 writes the flag and beta.
-__global__ void k_reorth_flag2(const double *__restrict__ w2_before, const double *__restrict__ beta1,
-                               double *__restrict__ flag, double *__restrict__ h2, int k,
-                               double *__restrict__ beta)
-{
-    const int t = threadIdx.x;
-    const double nb = sqrt(w2_before[0]);
-    const double b1 = beta1[0];
-    const double again = (b1 < 0.70710678118654752 * nb) ? 1.0 : 0.0;
-    if (t == 0) {
-        flag[0] = again;
-        if (again == 0.0) beta[0] = b1;
-    }
-    if (t < k && again == 0.0) h2[t] = 0.0;
+    if (FINAL) block_sums<1>(acc, 1, partial);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partial,
                                                 double *__restrict__ out,
                                                 const double *__restrict__ add, int k, int sqrt_last,
-                                                const double *__restrict__ flag, int flag_mode,
                                                 int nparts)
 {
-    // flag_mode 1: write zeros when *flag == 0; 2: leave out untouched when *flag == 0
-    if (flag && flag[0] == 0.0) {
-        if (flag_mode == 1 && threadIdx.x == 0) out[blockIdx.x] = 0.0;
-        return;
-    }
     // one workgroup per output; nparts (<= RED_BLOCKS) partials, summed in a
     // fixed tree: thread t adds partials t, t + 256, ... in order, then the waves
     __shared__ double red[4];
@@ -469,127 +450,107 @@ template hipError_t launch_block_apply<float, double, float>(const float *, cons
                                                              int64_t, bool, const double *,
                                                              hipStream_t);
 
-hipError_t launch_multidot(const double *V, int64_t ld, int k, const double *w, int64_t n,
-                           double *partial, hipStream_t st)
-{
-    if (k <= 8)
-        hipLaunchKernelGGL(k_multidot<8>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
-    else if (k <= 32)
-        hipLaunchKernelGGL(k_multidot<32>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
-    else
-        hipLaunchKernelGGL(k_multidot<65>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, w, n, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_update_dot(const double *V, int64_t ld, int k, const double *h, double *w,
-                             int64_t n, int k2, double *partial, hipStream_t st)
-{
-    const int kk = k > k2 ? k : k2;
-    if (kk <= 8)
-        hipLaunchKernelGGL(k_update_dot<8>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
-    else if (kk <= 32)
-        hipLaunchKernelGGL(k_update_dot<32>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
-    else
-        hipLaunchKernelGGL(k_update_dot<65>, dim3(red_blocks(n)), dim3(RED_THREADS), 0, st, V, ld, k, h, w, n, k2, partial);
-    return hipGetLastError();
-}
-
 hipError_t launch_reduce(const double *partial, int k, double *out, const double *add,
                          bool sqrt_last, hipStream_t st, int nparts)
 {
     hipLaunchKernelGGL(k_reduce, dim3(k), dim3(256), 0, st, partial, out, add, k, sqrt_last ? 1 : 0,
-                       (const double *)nullptr, 0, nparts);
+                       nparts);
     return hipGetLastError();
 }
 
-// Exact-count dispatch for 1 <= k <= 32.
-#define FE_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) \
+#define FE_NC_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) \
     X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) \
     X(29) X(30) X(31) X(32)
 
-static hipError_t mdot_exact(int k, bool norm, const double *V, int64_t ld, const double *w,
-                             int64_t n, double *partial, const double *flag, hipStream_t st)
+// Dot pass over the basis columns c0 .. c0 + nc - 1 (0 <= nc <= DGS_GROUP;
+// nc = 0 only for the first group of a step with no final basis vector yet).
+static hipError_t dgs_dots_group(int nc, bool w, bool first, const double *V, int64_t ld, int J,
+                                 int c0, int64_t n, double *partial, hipStream_t st)
 {
     const dim3 g(red_blocks(n)), b(RED_THREADS);
-    switch (k) {
-#define FE_MD(K)                                                                               \
-    case K:                                                                                    \
-        if (norm)                                                                              \
-            hipLaunchKernelGGL((k_mdot<K, true>), g, b, 0, st, V, ld, w, n, partial, flag);    \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_mdot<K, false>), g, b, 0, st, V, ld, w, n, partial, flag);   \
+#define FE_DD(NC, W, F) hipLaunchKernelGGL((k_dgs_dots<NC, W, F>), g, b, 0, st, V, ld, J, c0, n, partial)
+    if (nc == 0) {
+        if (!first) return hipErrorInvalidValue;
+        if (w)
+            FE_DD(0, true, true);
+        else
+            FE_DD(0, false, true);
+        return hipGetLastError();
+    }
+    switch (nc) {
+#define FE_DC(K)                                     \
+    case K:                                          \
+        if (first && w)                              \
+            FE_DD(K, true, true);                    \
+        else if (first)                              \
+            FE_DD(K, false, true);                   \
+        else if (w)                                  \
+            FE_DD(K, true, false);                   \
+        else                                         \
+            FE_DD(K, false, false);                  \
         break;
-        FE_K_CASES(FE_MD)
-#undef FE_MD
+        FE_NC_CASES(FE_DC)
+#undef FE_DC
     default:
         return hipErrorInvalidValue;
     }
+#undef FE_DD
     return hipGetLastError();
 }
 
-static hipError_t upd_exact(int k, const double *V, int64_t ld, const double *h, double *w,
-                            int64_t n, double *partial, const double *flag, hipStream_t st)
+static hipError_t dgs_dots(bool w, const double *V, int64_t ld, int J, int64_t n, double *partial,
+                           hipStream_t st)
 {
-    const dim3 g(red_blocks(n)), b(RED_THREADS);
-    switch (k) {
-#define FE_UP(K)                                                                               \
-    case K:                                                                                    \
-        hipLaunchKernelGGL((k_upd<K>), g, b, 0, st, V, ld, h, w, n, partial, flag);            \
-        break;
-        FE_K_CASES(FE_UP)
-#undef FE_UP
-    default:
-        return hipErrorInvalidValue;
+    for (int c0 = 0;; c0 += DGS_GROUP) {
+        const int nc = std::min(DGS_GROUP, J - c0);
+        const hipError_t e = dgs_dots_group(nc, w, c0 == 0, V, ld, J, c0, n, partial, st);
+        if (e != hipSuccess) return e;
+        if (c0 + DGS_GROUP >= J) return hipSuccess;
     }
-    return hipGetLastError();
 }
 
-static hipError_t upd_mdot_exact(int k, const double *V, int64_t ld, const double *h, double *w,
-                                 int64_t n, double *partial, hipStream_t st)
+hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, double *partial,
+                           hipStream_t st)
 {
-    const dim3 g(red_blocks(n)), b(RED_THREADS);
-    switch (k) {
-#define FE_UM(K)                                                                               \
-    case K:                                                                                    \
-        hipLaunchKernelGGL((k_upd_mdot<K>), g, b, 0, st, V, ld, h, w, n, partial);             \
-        break;
-        FE_K_CASES(FE_UM)
-#undef FE_UM
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_cgs(const double *V, int64_t ld, int k, double *w, int64_t n, double *hbuf,
-                      double *partial, hipStream_t st)
-{
-    hipError_t e;
+    if (J < 0 || J > 63) return hipErrorInvalidValue;
     const int np = red_blocks(n);
-    if (k > 32) {  // long bases: unconditional two passes with the generic kernels
-        if ((e = launch_multidot(V, ld, k, w, n, partial, st)) != hipSuccess) return e;
-        if ((e = launch_reduce(partial, k, hbuf, nullptr, false, st, np)) != hipSuccess) return e;
-        if ((e = launch_update_dot(V, ld, k, hbuf, w, n, k, partial, st)) != hipSuccess) return e;
-        if ((e = launch_reduce(partial, k, hbuf + 65, nullptr, false, st, np)) != hipSuccess) return e;
-        if ((e = launch_update_dot(V, ld, k, hbuf + 65, w, n, -1, partial, st)) != hipSuccess) return e;
-        return launch_reduce(partial, 1, hbuf + 130, nullptr, true, st, np);
+    hipError_t e;
+    if ((e = dgs_dots(true, V, ld, J, n, partial, st)) != hipSuccess) return e;
+    if ((e = launch_reduce(partial, 2 * J + 3, hb, nullptr, false, st, np)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, st, hb, J);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    double *c = V + (int64_t)J * ld, *w = V + (int64_t)(J + 1) * ld;
+    const dim3 g(np), b(RED_THREADS);
+    int c0 = 0;
+    if (J > DGS_GROUP) {  // the first DGS_GROUP columns in place, the rest with the final step
+        hipLaunchKernelGGL((k_dgs_update<DGS_GROUP, false>), g, b, 0, st, (const double *)V, c, w, ld,
+                           J, 0, n, (const double *)hb, partial);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        c0 = DGS_GROUP;
     }
-    double *flag = hbuf + 131;
-    // pass 1: h1 = V^T w and |w|^2 (stored at hbuf[k])
-    if ((e = mdot_exact(k, true, V, ld, w, n, partial, nullptr, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf, (const double *)nullptr,
-                       k + 1, 0, (const double *)nullptr, 0, np);
-    // w -= V h1 and, in the same read of V, h2 = V^T w and beta1 = |w| (hbuf[65 + k])
-    if ((e = upd_mdot_exact(k, V, ld, hbuf, w, n, partial, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(256), 0, st, partial, hbuf + 65,
-                       (const double *)nullptr, k + 1, 1, (const double *)nullptr, 0, np);
-    hipLaunchKernelGGL(k_reorth_flag2, dim3(1), dim3(64), 0, st, (const double *)(hbuf + k),
-                       (const double *)(hbuf + 65 + k), flag, hbuf + 65, k, hbuf + 130);
-    // the second pass's update only where the flag asks for it: w -= V h2, beta
-    if ((e = upd_exact(k, V, ld, hbuf + 65, w, n, partial, flag, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, hbuf + 130,
-                       (const double *)nullptr, 1, 1, flag, 2, np);
-    return hipGetLastError();
+    switch (J - c0) {
+#define FE_UF(K)                                                                              \
+    case K:                                                                                   \
+        hipLaunchKernelGGL((k_dgs_update<K, true>), g, b, 0, st, (const double *)V, c, w, ld, J, \
+                           c0, n, (const double *)hb, partial);                              \
+        break;
+        FE_UF(0)
+        FE_NC_CASES(FE_UF)
+#undef FE_UF
+    default:
+        return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_reduce(partial, 1, hb + 2 * J + 8, nullptr, false, st, np);
+}
+
+hipError_t launch_dgs_final(const double *V, int64_t ld, int J, int64_t n, double *hb,
+                            double *partial, hipStream_t st)
+{
+    if (J < 1 || J > 64) return hipErrorInvalidValue;
+    hipError_t e;
+    if ((e = dgs_dots(false, V, ld, J, n, partial, st)) != hipSuccess) return e;
+    return launch_reduce(partial, J + 1, hb, nullptr, false, st, red_blocks(n));
 }
 
 hipError_t launch_norm2_partial(const double *a, int64_t n, double *partial, hipStream_t st)
