@@ -4,10 +4,12 @@
 // (Sec. "Solving the non-linear system": flexible GMRES, preconditioned by a
 // geometric multigrid V-cycle).  The requests' worker threads hand these solves
 // to one engine thread, which advances all of them together: each engine step
-// performs one action per solve -- start (x = 0, |b|, v_0 = b / |b|), one
-// FGMRES iteration (V-cycle, J z, two classical Gram-Schmidt passes, norm,
-// v_{j+1}), or the end of a cycle (x += Z y, then in mixed mode or when the
-// estimate has not converged the true residual b - J x and its norm) -- and
+// performs one action per solve -- start (x = 0, |b|, c_0 = b / |b|), one
+// FGMRES iteration (V-cycle, J z, the dot and update passes of classical
+// Gram-Schmidt with the second projection delayed by a step), the candidate's
+// dot pass alone that finishes the last Hessenberg column of a cycle, or the
+// end of a cycle (x += Z y, then in mixed mode or when the estimate has not
+// converged the true residual b - J x and its norm) -- and
 // every kernel of the step runs as ONE batched launch over the table of all
 // solves that need it, whatever their grid sizes.  A step ends with one copy
 // of the solves' small results (Hessenberg column, norms) to the host, where
@@ -18,8 +20,9 @@
 // A solve's arithmetic does not depend on the other solves of a step: the
 // element and multigrid kernels are the one-problem kernels' bodies, and the
 // reductions chunk each vector by its own length.  Its result is therefore the
-// same alone and in any mix.  It differs from the one-problem FGMRES only in
-// the Gram-Schmidt step, which here always takes the second pass.
+// same alone and in any mix.  It follows the one-problem FGMRES step for step;
+// only the reductions are chunked differently, so the two agree to rounding,
+// not bitwise.
 #include <algorithm>
 #include <cmath>
 #include <condition_variable>
@@ -37,13 +40,13 @@ namespace fe {
 namespace {
 
 constexpr int MAX_SLOTS = 512;   // solves in flight at once
-constexpr int RS = 136;          // result doubles per slot: h1[65] h2[65] beta nrm2 ...
-constexpr int R_H1 = 0, R_H2 = 65, R_BETA = 130, R_NRM2 = 131;
+constexpr int RS = 136;          // result doubles per slot: Gram-Schmidt products (2j + 9), or
+constexpr int R_BETA = 130, R_NRM2 = 131;  // |b| and |b|^2 of a start / cycle end
 constexpr int MAXD = 64;         // depth bound of the V-cycle phase keys
 
 // launch kinds
 enum Kind {
-    K_FILL, K_CAST, K_AXPBY, K_SCALE, K_COMB64, K_COMB32, K_DOTS, K_REDUCE, K_UPDATE, K_SCNORM,
+    K_FILL, K_CAST, K_AXPBY, K_SCALE, K_COMB64, K_COMB32, K_DOTS, K_REDUCE, K_DGSD, K_DGSU, K_SCNORM,
     K_EJV_DD, K_CJV_DD, K_EJV_FD, K_CJV_FD, K_EJV_FF, K_CJV_FF,
     K_ESM_D, K_CSM_D, K_ESM_F, K_CSM_F,
     K_ST_D, K_ST_F, K_SM0_D, K_SM0_F, K_SM1_D, K_SM1_F,
@@ -55,7 +58,8 @@ enum Kind {
 using LaunchFn = hipError_t (*)(const BLaunch &, hipStream_t);
 const LaunchFn kLaunch[K_COUNT] = {
     blaunch_fill, blaunch_cast, blaunch_axpby, blaunch_scale, blaunch_comb<double>,
-    blaunch_comb<float>, blaunch_dots, blaunch_reduce, blaunch_update, blaunch_scale_norm,
+    blaunch_comb<float>, blaunch_dots, blaunch_reduce, blaunch_dgs_dots, blaunch_dgs_update,
+    blaunch_scale_norm,
     blaunch_elem_jv<double, double>, blaunch_combine_jv<double, double>,
     blaunch_elem_jv<float, double>, blaunch_combine_jv<float, double>,
     blaunch_elem_jv<float, float>, blaunch_combine_jv<float, float>,
@@ -116,7 +120,7 @@ struct Planner {
     }
 };
 
-enum JState { J_INIT, J_ITER, J_CEND };
+enum JState { J_INIT, J_ITER, J_FINAL, J_CEND };
 
 struct Solve {
     BJob *job = nullptr;
@@ -124,6 +128,8 @@ struct Solve {
     JState state = J_INIT;
     int m = 0, j = 0, kk = 0, refine_left = 0;
     std::vector<double> H, cs, sn, g, y;
+    std::vector<double> Hp;  // provisional column j - 1 (first-projection coefficients)
+    double om = 0, c2 = 0;   // scale and squared norm of the candidate c_j
     double beta0 = 0, target = 0, res = 0;
     bool breakdown = false, est_conv = false, need_true = false, waited = false;
 };
@@ -290,6 +296,23 @@ void emit_norm_scale(Planner &P, int stage, const BJob &J, double *res, const do
           BScaleNorm{J.partial, nch, J.n, w, v, res + R_NRM2, res + R_BETA}, belt_blocks(J.n));
 }
 
+// Delayed Gram-Schmidt with J basis vectors: the dot pass (with the new
+// Krylov vector when w, else the candidate's products alone) reduced into the
+// slot, and with w the update pass and the next candidate's |c|^2 (slot 2J + 8).
+void emit_dgs(Planner &P, const BJob &J, double *res, int nb, bool w)
+{
+    int nch, ept;
+    bred_chunks(J.n, &nch, &ept);
+    const int ngrp = std::max(1, (nb + BDOT_GROUP - 1) / BDOT_GROUP);
+    P.add(key(3, 0, 10), K_DGSD, BDgsDots{J.V, J.n, nb, w ? 1 : 0, J.n, nch, ept, ngrp, J.partial},
+          nch * ngrp);
+    const int ncol = w ? 2 * nb + 3 : nb + 1;
+    P.add(key(3, 0, 11), K_REDUCE, BReduce{J.partial, ncol, nch, res, nullptr}, ncol);
+    if (!w) return;
+    P.add(key(3, 0, 12), K_DGSU, BDgsUpdate{J.V, J.n, nb, J.n, nch, ept, res, J.partial}, nch);
+    P.add(key(3, 0, 13), K_REDUCE, BReduce{J.partial, 1, nch, res + 2 * nb + 8, nullptr}, 1);
+}
+
 }  // namespace
 
 struct BatchEngine {
@@ -366,7 +389,6 @@ void BatchEngine::plan(Solve &S)
     case J_ITER: {
         const fe_problem *p = J.p;
         double *vj = J.V + (int64_t)S.j * n, *vn = J.V + (int64_t)(S.j + 1) * n;
-        const int k = S.j + 1;
         if (J.mixed) {
             float *zj = J.Z32 + (int64_t)S.j * n;
             emit_vcycle<float>(P, J.mg, vj, zj);
@@ -380,22 +402,12 @@ void BatchEngine::plan(Solve &S)
             P.add(key(3, 0, 0), K_EJV_DD, a, belem_blocks(p->geo));
             P.add(key(3, 0, 1), K_CJV_DD, a, bnode_blocks(p->geo));
         }
-        // classical Gram-Schmidt, two passes, then |w| and v_{j+1}
-        int nch, ept;
-        bred_chunks(n, &nch, &ept);
-        const int ngrp = (k + BDOT_GROUP - 1) / BDOT_GROUP;
-        const BDots d{vn, J.V, n, k, 0, n, nch, ept, ngrp, J.partial};
-        P.add(key(3, 0, 10), K_DOTS, d, nch * ngrp);
-        P.add(key(3, 0, 11), K_REDUCE, BReduce{J.partial, k, nch, res + R_H1, nullptr}, k);
-        P.add(key(3, 0, 12), K_UPDATE, BUpdate{vn, J.V, n, k, n, nch, ept, res + R_H1, nullptr}, nch);
-        P.add(key(3, 0, 13), K_DOTS, d, nch * ngrp);
-        P.add(key(3, 0, 14), K_REDUCE, BReduce{J.partial, k, nch, res + R_H2, nullptr}, k);
-        P.add(key(3, 0, 15), K_UPDATE, BUpdate{vn, J.V, n, k, n, nch, ept, res + R_H2, J.partial},
-              nch);
-        P.add(key(3, 0, 16), K_SCNORM,
-              BScaleNorm{J.partial, nch, n, vn, vn, res + R_NRM2, res + R_BETA}, belt_blocks(n));
+        emit_dgs(P, J, res, S.j, true);
         break;
     }
+    case J_FINAL:
+        emit_dgs(P, J, res, S.j, false);
+        break;
     }
 }
 
@@ -475,13 +487,51 @@ void BatchEngine::update(Solve &S, bool *finished)
         J.rc = rc;
         *finished = true;
     };
+    // the cycle ends with kk final columns: y = H^{-1} g, then the cycle-end step
+    auto end_cycle = [&](int kk) {
+        for (int i = kk - 1; i >= 0; --i) {
+            double s = S.g[i];
+            for (int c = i + 1; c < kk; ++c) s -= S.H[(size_t)i * m + c] * S.y[c];
+            S.y[i] = s / S.H[(size_t)i * m + i];
+        }
+        S.kk = kk;
+        S.est_conv = S.res <= S.target;
+        S.need_true = J.mixed || !S.est_conv;
+        S.state = J_CEND;
+    };
+    // before step j: finish column j - 1 from the candidate's dot products
+    // alone (J_FINAL) when the step would not be used, else take the step
+    auto next_step = [&]() {
+        const int j = S.j;
+        if (j == 0) {
+            if (J.its >= J.max_its)
+                end_cycle(0);
+            else
+                S.state = J_ITER;
+            return;
+        }
+        bool fin = j == m || J.its >= J.max_its;
+        if (!fin) {
+            S.Hp[j] = S.om * std::sqrt(std::max(S.c2, 0.0));
+            fin = givens_estimate(S.Hp, j - 1, S.cs, S.sn, S.g) <= S.target;
+        }
+        S.state = fin ? J_FINAL : J_ITER;
+    };
     auto start_cycle = [&](double beta) {
         std::fill(S.g.begin(), S.g.end(), 0.0);
-        S.g[0] = beta;
         S.j = 0;
+        S.om = beta;
+        S.c2 = 1.0;
         S.res = beta;
         S.breakdown = false;
-        S.state = J_ITER;
+        next_step();
+    };
+    // column j - 1 from its provisional entries, the candidate's s and sigma
+    auto finish_column = [&](int j, const double *s, double sig) {
+        for (int i = 0; i < j; ++i) S.H[(size_t)i * m + (j - 1)] = S.Hp[i] + S.om * s[i];
+        S.H[(size_t)j * m + (j - 1)] = S.om * sig;
+        S.res = givens_column(S.H, m, j - 1, S.cs, S.sn, S.g);
+        if (!(S.om * sig > 1e-300 * S.beta0)) S.breakdown = true;
     };
     switch (S.state) {
     case J_INIT: {
@@ -506,49 +556,47 @@ void BatchEngine::update(Solve &S, bool *finished)
     }
     case J_ITER: {
         const int j = S.j;
-        std::vector<double> &H = S.H;
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[R_H1 + i] + hh[R_H2 + i];
-        const double hn = hh[R_BETA];
-        if (!std::isfinite(hn)) {
+        const double sig = hh[2 * j + 3], hj = hh[2 * j + 4], omn = hh[2 * j + 5];
+        const double cn2 = hh[2 * j + 8];
+        J.its++;
+        if (!std::isfinite(sig) || !std::isfinite(hj) || !std::isfinite(omn) || !std::isfinite(cn2)) {
             J.error = "non-finite Krylov norm";
             finish(FE_ENAN);
             return;
         }
-        for (int i = 0; i < j; ++i) {
-            const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-            H[(size_t)i * m + j] = S.cs[i] * a + S.sn[i] * c;
-            H[(size_t)(i + 1) * m + j] = -S.sn[i] * a + S.cs[i] * c;
-        }
-        const double a = H[(size_t)j * m + j];
-        const double den = std::hypot(a, hn);
-        if (den == 0.0) {
-            S.cs[j] = 1.0;
-            S.sn[j] = 0.0;
+        if (j == 0) {
+            S.g[0] = S.om * sig;
+            if (!(sig > 0.0)) S.breakdown = true;
         } else {
-            S.cs[j] = a / den;
-            S.sn[j] = hn / den;
+            finish_column(j, hh, sig);
         }
-        H[(size_t)j * m + j] = S.cs[j] * a + S.sn[j] * hn;
-        H[(size_t)(j + 1) * m + j] = 0.0;
-        S.g[j + 1] = -S.sn[j] * S.g[j];
-        S.g[j] = S.cs[j] * S.g[j];
-        S.res = std::fabs(S.g[j + 1]);
-        J.its++;
-        if (hn <= 1e-300 * S.beta0) S.breakdown = true;
-        if (S.res <= S.target || J.its >= J.max_its || S.breakdown || j + 1 == m) {
-            const int kk = j + 1;
-            for (int i = kk - 1; i >= 0; --i) {
-                double s = S.g[i];
-                for (int c = i + 1; c < kk; ++c) s -= H[(size_t)i * m + c] * S.y[c];
-                S.y[i] = s / H[(size_t)i * m + i];
-            }
-            S.kk = kk;
-            S.est_conv = S.res <= S.target;
-            S.need_true = J.mixed || !S.est_conv;
-            S.state = J_CEND;
-        } else {
-            S.j = j + 1;
+        if (S.breakdown || (j >= 1 && S.res <= S.target)) {
+            end_cycle(j);
+            return;
         }
+        for (int i = 0; i < j; ++i) S.Hp[i] = hh[j + 1 + i];
+        S.Hp[j] = hj;
+        S.om = omn;
+        S.c2 = cn2;
+        S.j = j + 1;
+        next_step();
+        return;
+    }
+    case J_FINAL: {
+        const int j = S.j;
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) ss += hh[i] * hh[i];
+        const double s2 = hh[j] - ss;
+        if (!std::isfinite(s2)) {
+            J.error = "non-finite Krylov norm";
+            finish(FE_ENAN);
+            return;
+        }
+        finish_column(j, hh, s2 > 0.0 ? std::sqrt(s2) : 0.0);
+        if (S.res <= S.target || J.its >= J.max_its || j == m || S.breakdown)
+            end_cycle(j);
+        else
+            S.state = J_ITER;
         return;
     }
     case J_CEND: {
@@ -577,7 +625,7 @@ void BatchEngine::update(Solve &S, bool *finished)
             finish(FE_OK);
             return;
         }
-        start_cycle(beta);  // v_0 = r / |r| was formed on the device in this step
+        start_cycle(beta);  // c_0 = r / |r| was formed on the device in this step
         return;
     }
     }
@@ -606,6 +654,7 @@ void BatchEngine::run()
                 S.sn.assign(S.m, 0.0);
                 S.g.assign(S.m + 1, 0.0);
                 S.y.assign(S.m, 0.0);
+                S.Hp.assign(S.m + 2, 0.0);
                 active.push_back(std::move(S));
             }
             incoming.erase(incoming.begin(), incoming.begin() + taken);

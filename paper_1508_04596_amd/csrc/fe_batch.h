@@ -225,14 +225,29 @@ struct BReduce {  // out[c] = sum of the nchunk partials of column c < ncol (one
     int ncol, nchunk;
     double *out, *beta;
 };
-struct BUpdate {  // w -= sum_{c<k} h_c V_c; partial[chunk] of <w, w> after it (if partial)
-    double *w;
+// Delayed classical Gram-Schmidt (the one-problem FGMRES's scheme): basis
+// vectors q_0 .. q_{J-1} in columns 0 .. J-1 of V, the candidate c in column J,
+// the new Krylov vector w in column J + 1.
+struct BDgsDots {  // partials of s_i = <q_i, c>, a = <c, c> and, if w: p_i = <q_i, w>, t = <c, w>,
+                   // e = <w, w>, as columns i, J, J + 1 + i, 2J + 1, 2J + 2 (BDOT_GROUP basis
+                   // columns per workgroup and chunk; the group of column 0 also takes a, t, e)
     const double *V;
     int64_t ld;
-    int k;
+    int J, w;
+    int64_t n;
+    int nchunk, ept, ngrp;
+    double *partial;
+};
+struct BDgsUpdate {  // from the reduced dot products in res: sigma, h, omega (to res[2J+3 ..
+                     // 2J+5]), q_J = (c - sum s_i q_i) / sigma into column J, the next candidate
+                     // (w - sum p_i q_i - h q_J) / omega into column J + 1, chunk partials of its
+                     // squared norm
+    double *V;
+    int64_t ld;
+    int J;
     int64_t n;
     int nchunk, ept;
-    const double *h;
+    double *res;
     double *partial;
 };
 inline int belt_blocks(int64_t n) { return (int)((n + 255) / 256); }
@@ -246,7 +261,8 @@ template <typename T>
 hipError_t blaunch_copy(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_dots(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_reduce(const BLaunch &L, hipStream_t st);
-hipError_t blaunch_update(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_dgs_dots(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_dgs_update(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_scale_norm(const BLaunch &L, hipStream_t st);
 
 }  // namespace fe

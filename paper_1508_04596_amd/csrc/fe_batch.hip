@@ -173,31 +173,139 @@ __global__ __launch_bounds__(256) void kb_scale_norm(const BScaleNorm *__restric
     if (i < a.n) a.y[i] = a.x[i] / beta;
 }
 
-// w -= sum_{c<k} h_c V_c over one chunk, then (optionally) the chunk's <w, w>.
-__global__ __launch_bounds__(256) void kb_update(const BUpdate *__restrict__ tab,
-                                                 const int *__restrict__ off, int n)
+// Reduction column of accumulator q of a group of nc basis columns from c0.
+__device__ __forceinline__ int bdgs_out(int q, int nc, int w, int J, int c0)
 {
-    __shared__ double hs[BCOMB_MAX + 1];
-    __shared__ double red[4];
+    if (q < nc) return c0 + q;  // s
+    q -= nc;
+    if (w) {
+        if (q < nc) return J + 1 + c0 + q;  // p
+        q -= nc;
+    }
+    return q == 0 ? J : (q == 1 ? 2 * J + 1 : 2 * J + 2);  // a, t, e
+}
+
+// Partials of the delayed Gram-Schmidt dot products for the BDOT_GROUP basis
+// columns of group g over chunk ch of the problem's vectors.
+__global__ __launch_bounds__(256) void kb_dgs_dots(const BDgsDots *__restrict__ tab,
+                                                   const int *__restrict__ off, int n)
+{
+    constexpr int G = BDOT_GROUP, NA = 2 * G + 3;
+    __shared__ double red[NA][4];
     const int e = batch_entry(off, n);
-    const BUpdate &a = tab[e];
-    const int ch = (int)blockIdx.x - off[e];
-    if ((int)threadIdx.x < a.k) hs[threadIdx.x] = a.h[threadIdx.x];
+    const BDgsDots &a = tab[e];
+    const int lb = (int)blockIdx.x - off[e];
+    const int ch = lb % a.nchunk, grp = lb / a.nchunk;
+    const int c0 = grp * G;
+    const int nc = min(G, a.J - c0);  // may be 0 (group 0 of J = 0)
+    const double *__restrict__ c = a.V + (int64_t)a.J * a.ld;
+    const double *__restrict__ w = a.V + (int64_t)(a.J + 1) * a.ld;
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    const int64_t base = (int64_t)ch * 256 * a.ept + threadIdx.x;
+    for (int r = 0; r < a.ept; ++r) {
+        const int64_t i = base + (int64_t)r * 256;
+        if (i >= a.n) break;
+        const double ci = c[i];
+        const double wi = a.w ? w[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k < nc) {
+                const double qk = a.V[(int64_t)(c0 + k) * a.ld + i];
+                acc[k] += qk * ci;
+                acc[G + k] += qk * wi;
+            }
+        }
+        if (grp == 0) {
+            acc[2 * G] += ci * ci;
+            acc[2 * G + 1] += ci * wi;
+            acc[2 * G + 2] += wi * wi;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const double s = bwave_sum(acc[q]);
+        if (lane == 0) red[q][wv] = s;
+    }
     __syncthreads();
+    // the group's outputs in the order s (nc), p (nc, if w), then a, t, e (group 0)
+    const int nout = nc * (a.w ? 2 : 1) + (grp == 0 ? (a.w ? 3 : 1) : 0);
+    if ((int)threadIdx.x < nout) {
+        const int q = threadIdx.x;
+        int src;  // accumulator of output q
+        if (q < nc)
+            src = q;
+        else if (a.w && q < 2 * nc)
+            src = G + (q - nc);
+        else
+            src = 2 * G + (q - nc * (a.w ? 2 : 1));
+        a.partial[(int64_t)bdgs_out(q, nc, a.w, a.J, c0) * a.nchunk + ch] =
+            (red[src][0] + red[src][1]) + (red[src][2] + red[src][3]);
+    }
+}
+
+// Update pass of delayed Gram-Schmidt over one chunk.  Every workgroup of a
+// problem derives sigma = sqrt(a - |s|^2), h = (t - <s, p>) / sigma and
+// omega = |w| from the reduced dot products in the same fixed order (wave 0,
+// lane i holding s_i and p_i), so all use the same values; workgroup 0 stores
+// them.
+__global__ __launch_bounds__(256) void kb_dgs_update(const BDgsUpdate *__restrict__ tab,
+                                                     const int *__restrict__ off, int n)
+{
+    __shared__ double cs[64], cp[64], coef[4];
+    const int e = batch_entry(off, n);
+    const BDgsUpdate &a = tab[e];
+    const int ch = (int)blockIdx.x - off[e];
+    const int J = a.J;
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        const double sl = l < J ? a.res[l] : 0.0;
+        const double pl = l < J ? a.res[J + 1 + l] : 0.0;
+        cs[l] = sl;
+        cp[l] = pl;
+        const double ss = bwave_sum(sl * sl), sp = bwave_sum(sl * pl);
+        const double s2 = a.res[J] - ss;
+        const double sig = s2 > 0.0 ? sqrt(s2) : 0.0;
+        const double h = sig > 0.0 ? (a.res[2 * J + 1] - sp) / sig : 0.0;
+        const double om = sqrt(a.res[2 * J + 2]);
+        if (l == 0) {
+            coef[0] = sig > 0.0 ? 1.0 / sig : 0.0;
+            coef[1] = h;
+            coef[2] = om > 0.0 ? 1.0 / om : 0.0;
+            if (ch == 0) {
+                a.res[2 * J + 3] = sig;
+                a.res[2 * J + 4] = h;
+                a.res[2 * J + 5] = om;
+            }
+        }
+    }
+    __syncthreads();
+    const double isg = coef[0], h = coef[1], iom = coef[2];
+    double *__restrict__ c = a.V + (int64_t)J * a.ld;
+    double *__restrict__ w = a.V + (int64_t)(J + 1) * a.ld;
+    const double *__restrict__ Q = a.V;
     double acc = 0.0;
     const int64_t base = (int64_t)ch * 256 * a.ept + threadIdx.x;
     for (int r = 0; r < a.ept; ++r) {
         const int64_t i = base + (int64_t)r * 256;
         if (i >= a.n) break;
-        double wi = a.w[i];
-        for (int c = 0; c < a.k; ++c) wi -= hs[c] * a.V[(int64_t)c * a.ld + i];
-        a.w[i] = wi;
-        acc += wi * wi;
+        double ci = c[i], wi = w[i];
+        for (int k = 0; k < J; ++k) {
+            const double qk = Q[(int64_t)k * a.ld + i];
+            ci -= cs[k] * qk;
+            wi -= cp[k] * qk;
+        }
+        const double qj = ci * isg;
+        const double cn = (wi - h * qj) * iom;
+        c[i] = qj;
+        w[i] = cn;
+        acc += cn * cn;
     }
-    if (a.partial) {
-        const double s = bblock_sum(acc, red);
-        if (threadIdx.x == 0) a.partial[ch] = s;
-    }
+    __shared__ double red[4];
+    const double s = bblock_sum(acc, red);
+    if (threadIdx.x == 0) a.partial[ch] = s;
 }
 
 }  // namespace
@@ -216,7 +324,8 @@ FE_BVLAUNCH(blaunch_axpby, kb_axpby, BAxpby)
 FE_BVLAUNCH(blaunch_scale, kb_scale, BScale)
 FE_BVLAUNCH(blaunch_dots, kb_dots, BDots)
 FE_BVLAUNCH(blaunch_reduce, kb_reduce, BReduce)
-FE_BVLAUNCH(blaunch_update, kb_update, BUpdate)
+FE_BVLAUNCH(blaunch_dgs_dots, kb_dgs_dots, BDgsDots)
+FE_BVLAUNCH(blaunch_dgs_update, kb_dgs_update, BDgsUpdate)
 FE_BVLAUNCH(blaunch_scale_norm, kb_scale_norm, BScaleNorm)
 #undef FE_BVLAUNCH
 

@@ -168,6 +168,15 @@ hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, 
 // 1 <= J <= 64.
 hipError_t launch_dgs_final(const double *V, int64_t ld, int J, int64_t n, double *hb,
                             double *partial, hipStream_t st);
+// Givens rotations of the FGMRES least-squares problem (host): column c of H
+// (m columns, row-major (m + 1) x m, entries 0 .. c+1 set) gets the rotations
+// 0 .. c-1, defines rotation c and advances g; returns the residual estimate
+// |g[c+1]|.  givens_estimate: the estimate that column c with entries
+// col[0 .. c+1] would give, nothing changed.
+double givens_column(std::vector<double> &H, int m, int c, std::vector<double> &cs,
+                     std::vector<double> &sn, std::vector<double> &g);
+double givens_estimate(const std::vector<double> &col, int c, const std::vector<double> &cs,
+                       const std::vector<double> &sn, const std::vector<double> &g);
 // y = a*x + b*y (y is not read when b == 0)
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
 // y = x + lam*d

@@ -138,8 +138,8 @@ struct LinStats {
 // Column c of the Hessenberg matrix H (m columns, entries 0 .. c+1 set) gets
 // the rotations 0 .. c-1, defines rotation c and advances g; returns the
 // residual estimate |g[c+1]|.
-static double givens_column(std::vector<double> &H, int m, int c, std::vector<double> &cs,
-                            std::vector<double> &sn, std::vector<double> &g)
+double givens_column(std::vector<double> &H, int m, int c, std::vector<double> &cs,
+                     std::vector<double> &sn, std::vector<double> &g)
 {
     for (int i = 0; i < c; ++i) {
         const double a = H[(size_t)i * m + c], b = H[(size_t)(i + 1) * m + c];
@@ -164,8 +164,8 @@ static double givens_column(std::vector<double> &H, int m, int c, std::vector<do
 
 // The residual estimate that column c with entries col[0 .. c+1] would give,
 // state unchanged.
-static double givens_estimate(const std::vector<double> &col, int c, const std::vector<double> &cs,
-                              const std::vector<double> &sn, const std::vector<double> &g)
+double givens_estimate(const std::vector<double> &col, int c, const std::vector<double> &cs,
+                       const std::vector<double> &sn, const std::vector<double> &g)
 {
     std::vector<double> v(col.begin(), col.begin() + c + 2);
     for (int i = 0; i < c; ++i) {
