@@ -158,9 +158,9 @@ constexpr int PARTIAL_COLS = 130;
 // candidate (w projected once against q_0 .. q_J, divided by |w|).  hb (device)
 // receives s_i = <q_i, c> at i < J, a = <c, c> at J, p_i = <q_i, w> at J + 1 + i,
 // t = <c, w> at 2J + 1, e = <w, w> at 2J + 2, sigma = |c - sum s_i q_i|, the
-// coefficient h = <q_J, w>, omega = |w|, 1/sigma, 1/omega at 2J + 3 .. 2J + 7
-// and the squared norm of the next candidate at 2J + 8 (sigma = 0: nothing left
-// of the candidate, q_J = 0).  0 <= J <= 63.
+// coefficient h = <q_J, w> and omega = |w| at 2J + 3 .. 2J + 5 and the squared
+// norm of the next candidate at 2J + 8 (sigma = 0: nothing left of the
+// candidate, q_J = 0).  0 <= J <= 63.
 hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, double *partial,
                            hipStream_t st);
 // The candidate's dot products alone (no new Krylov vector; it finishes the

@@ -48,8 +48,9 @@ __device__ __forceinline__ void block_sums(double (&acc)[KMAX], int k, double *p
 //   t = <c, w> at 2J + 1, e = <w, w> at 2J + 2,
 // so the candidate's second projection and w's first one share one read of
 // the basis; the update pass then writes q_J = (c - sum s_i q_i) / sigma and
-// the next candidate (w - sum p_i q_i - h q_J) / omega (sigma, h, omega from
-// k_dgs_coef).  A launch covers at most DGS_GROUP basis columns; the group that
+// the next candidate (w - sum p_i q_i - h q_J) / omega, with sigma, h and omega
+// derived from the dot products.  A launch covers at most DGS_GROUP basis
+// columns; the group that
 // starts at column 0 also accumulates a, t and e.
 constexpr int DGS_GROUP = 32;
 
@@ -113,50 +114,52 @@ __global__ __launch_bounds__(RED_THREADS) void k_dgs_dots(const double *__restri
     }
 }
 
-// sigma = sqrt(a - |s|^2) (the candidate's norm after its second projection;
-// 0 when nothing is left of it), h = (t - <s, p>) / sigma (the coefficient of w
-// on q_J), omega = |w|.  One wave, J <= 64; hb holds the reduced dot products
-// and receives sigma, h, omega, 1/sigma, 1/omega at 2J + 3 .. 2J + 7.
-__global__ void k_dgs_coef(double *__restrict__ hb, int J)
-{
-    const int l = threadIdx.x;
-    const double sl = l < J ? hb[l] : 0.0;
-    const double pl = l < J ? hb[J + 1 + l] : 0.0;
-    const double ss = wave_sum(sl * sl), sp = wave_sum(sl * pl);
-    const double s2 = hb[J] - ss;
-    const double sig = s2 > 0.0 ? sqrt(s2) : 0.0;
-    const double h = sig > 0.0 ? (hb[2 * J + 1] - sp) / sig : 0.0;
-    const double om = sqrt(hb[2 * J + 2]);
-    if (l == 0) {
-        hb[2 * J + 3] = sig;
-        hb[2 * J + 4] = h;
-        hb[2 * J + 5] = om;
-        hb[2 * J + 6] = sig > 0.0 ? 1.0 / sig : 0.0;
-        hb[2 * J + 7] = om > 0.0 ? 1.0 / om : 0.0;
-    }
-}
-
 // Update pass over the basis columns c0 .. c0 + NC - 1: c -= sum s_i q_i and
 // w -= sum p_i q_i.  FINAL (the last group): then q_J = c / sigma into column
 // J, the next candidate (w - h q_J) / omega into column J + 1, and the
-// partials of its squared norm.  Columns below J are only read, so the three
-// pointers never address the same entries.
+// partials of its squared norm, where sigma = sqrt(a - |s|^2) (the candidate's
+// norm after its second projection; 0 when nothing is left of it), h =
+// (t - <s, p>) / sigma (the coefficient of w on q_J) and omega = |w| come from
+// the reduced dot products in hb: every workgroup derives them in the same
+// fixed order (wave 0, lane i holding s_i and p_i), and workgroup 0 stores
+// them at hb[2J + 3 .. 2J + 5].  Columns below J are only read, so the three
+// pointers never address the same entries; J <= 63.
 template <int NC, bool FINAL>
 __global__ __launch_bounds__(RED_THREADS) void k_dgs_update(const double *__restrict__ Q, double *__restrict__ c,
                                                             double *__restrict__ w, int64_t ld, int J,
                                                             int c0, int64_t n,
-                                                            const double *__restrict__ hb,
+                                                            double *__restrict__ hb,
                                                             double *__restrict__ partial)
 {
-    __shared__ double cs[NC > 0 ? NC : 1], cp[NC > 0 ? NC : 1];
+    __shared__ double cs[NC > 0 ? NC : 1], cp[NC > 0 ? NC : 1], coef[3];
     if ((int)threadIdx.x < NC) {
         cs[threadIdx.x] = hb[c0 + threadIdx.x];
         cp[threadIdx.x] = hb[J + 1 + c0 + threadIdx.x];
     }
+    if (FINAL && threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        const double sl = l < J ? hb[l] : 0.0;
+        const double pl = l < J ? hb[J + 1 + l] : 0.0;
+        const double ss = wave_sum(sl * sl), sp = wave_sum(sl * pl);
+        const double s2 = hb[J] - ss;
+        const double sig = s2 > 0.0 ? sqrt(s2) : 0.0;
+        const double h = sig > 0.0 ? (hb[2 * J + 1] - sp) / sig : 0.0;
+        const double om = sqrt(hb[2 * J + 2]);
+        if (l == 0) {
+            coef[0] = sig > 0.0 ? 1.0 / sig : 0.0;
+            coef[1] = h;
+            coef[2] = om > 0.0 ? 1.0 / om : 0.0;
+            if (blockIdx.x == 0) {
+                hb[2 * J + 3] = sig;
+                hb[2 * J + 4] = h;
+                hb[2 * J + 5] = om;
+            }
+        }
+    }
     __syncthreads();
-    const double h = FINAL ? hb[2 * J + 4] : 0.0;
-    const double isg = FINAL ? hb[2 * J + 6] : 0.0;
-    const double iom = FINAL ? hb[2 * J + 7] : 0.0;
+    const double isg = FINAL ? coef[0] : 0.0;
+    const double h = FINAL ? coef[1] : 0.0;
+    const double iom = FINAL ? coef[2] : 0.0;
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -517,14 +520,12 @@ hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, 
     hipError_t e;
     if ((e = dgs_dots(true, V, ld, J, n, partial, st)) != hipSuccess) return e;
     if ((e = launch_reduce(partial, 2 * J + 3, hb, nullptr, false, st, np)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, st, hb, J);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     double *c = V + (int64_t)J * ld, *w = V + (int64_t)(J + 1) * ld;
     const dim3 g(np), b(RED_THREADS);
     int c0 = 0;
     if (J > DGS_GROUP) {  // the first DGS_GROUP columns in place, the rest with the final step
         hipLaunchKernelGGL((k_dgs_update<DGS_GROUP, false>), g, b, 0, st, (const double *)V, c, w, ld,
-                           J, 0, n, (const double *)hb, partial);
+                           J, 0, n, hb, partial);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         c0 = DGS_GROUP;
     }
@@ -532,7 +533,7 @@ hipError_t launch_dgs_step(double *V, int64_t ld, int J, int64_t n, double *hb, 
 #define FE_UF(K)                                                                              \
     case K:                                                                                   \
         hipLaunchKernelGGL((k_dgs_update<K, true>), g, b, 0, st, (const double *)V, c, w, ld, J, \
-                           c0, n, (const double *)hb, partial);                              \
+                           c0, n, hb, partial);                                              \
         break;
         FE_UF(0)
         FE_NC_CASES(FE_UF)
