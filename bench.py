@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--serve-burst-rate", type=float, default=1000.0,
                     help="arrival rate of the burst comparison (default vs batched server); 0 = skip")
     ap.add_argument("--serve-burst-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-sizes", type=str, default="16,24,32,48",
+                    help="grid sizes n (n^3 elements) the serving trace draws from, comma-separated")
     ap.add_argument("--serve-only", action="store_true",
                     help="diagnostic: run only the serving legs and print their JSON")
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
@@ -251,32 +253,35 @@ def serving_legs(fe, inputs, args):
     worker's stream) and on the batched one (lockstep FGMRES, one launch per
     kernel over all running requests); then a burst that keeps many requests
     in flight, on both."""
+    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
     serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                        args.serve_max_active, args.serve_rate)
+                        args.serve_max_active, args.serve_rate, sizes=sizes)
     serve["batched"] = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                                   args.serve_batched_max_active, args.serve_rate, batched=True)
+                                   args.serve_batched_max_active, args.serve_rate, batched=True,
+                                   sizes=sizes)
     if args.serve_burst_rate > 0:
         serve["burst"] = {
             "default": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
-                                   args.serve_max_active, args.serve_burst_rate),
+                                   args.serve_max_active, args.serve_burst_rate, sizes=sizes),
             "batched": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
                                    args.serve_batched_max_active, args.serve_burst_rate,
-                                   batched=True)}
+                                   batched=True, sizes=sizes)}
     return serve
 
 
-def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
+def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False,
+                sizes=(16, 24, 32, 48)):
     """Serving workload: n requests with Poisson arrivals (20/s by default), grids uniform
-    over {16,24,32,48}^3, log10 Gr uniform in [3,5], 40 %-solid smoothed random
-    designs, mixed precision to 1e-8; latency = completion - arrival.  ``batched``:
-    the lockstep server (one launch per kernel over all running requests)."""
+    over sizes^3 ({16,24,32,48}^3 by default), log10 Gr uniform in [3,5], 40 %-solid
+    smoothed random designs, mixed precision to 1e-8; latency = completion - arrival.
+    ``batched``: the lockstep server (one launch per kernel over all running requests)."""
     import time as _t
-    reqs = inputs.serving_trace(n_requests=n, rate_per_s=rate, seed=4000)
+    reqs = inputs.serving_trace(n_requests=n, rate_per_s=rate, seed=4000, sizes=sizes)
     # the requests' grids, designs and Grashof numbers do not depend on the
     # arrival rate (the arrival gaps are drawn first): build them once
-    if n not in _SERVE_PROBS:
-        _SERVE_PROBS[n] = [inputs.request_problem(r) for r in reqs]
-    probs = _SERVE_PROBS[n]
+    if (n, sizes) not in _SERVE_PROBS:
+        _SERVE_PROBS[(n, sizes)] = [inputs.request_problem(r) for r in reqs]
+    probs = _SERVE_PROBS[(n, sizes)]
     opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
     lat, tickets, statuses = [], [], []
     with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active, batched=batched) as srv:
@@ -304,8 +309,8 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False):
         steps, launches = steps - steps0, launches - launches0
     lat = np.array([d - a for a, _, d in times])
     makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
-    return {"requests": n, "rate_per_s": rate, "budget_gb": budget_gb, "max_active": max_active,
-            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+    return {"requests": n, "sizes": list(sizes), "rate_per_s": rate, "budget_gb": budget_gb,
+            "max_active": max_active, "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "solves_per_s": n / makespan, "all_converged": all(s == 0 for s in statuses),
             "mode": "batched" if batched else "default",
             "engine_steps": steps, "engine_launches": launches,

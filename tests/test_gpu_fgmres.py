@@ -1,0 +1,87 @@
+"""FGMRES with the delayed Gram-Schmidt at its cycle boundaries.
+
+A basis vector's second projection happens in the step after it was formed, so
+the last Hessenberg column of a cycle is finished from the candidate's dot
+products alone, at convergence, at the restart length and at the iteration
+cap.  These solves run restart lengths from 3 to 64 (the dot pass covers up to
+32 basis vectors per launch, so 33 and 64 take two launches), in FP64 and in
+mixed precision, and check every converged Newton solve with the oracle's
+residual; the iteration cap must hold exactly, also with cycles of one step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_04596_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_04596_amd import fe as fe_mod
+    fe_mod.lib()
+    return fe_mod
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _solve(fe, p, **kw):
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    allow = kw.pop("allow_not_converged", False)
+    rep = fe.newton_solve(prob, dev(p.gamma), dev(p.s), x, fe.solve_opts(**kw),
+                          allow_not_converged=allow)
+    xs = host(x)
+    prob.close()
+    return xs, rep
+
+
+# (preconditioner, restart, grid): multigrid converges in few iterations, so the
+# short restarts use it; block-Jacobi needs more than 32 iterations per linear
+# solve, which the long restarts need to reach their second column group.
+# Restart 1 is covered by the iteration-cap test: GMRES(1) stagnates on this
+# nonsymmetric system (as restarted GMRES(1) may), so it cannot reach the bar.
+CASES = [("multigrid", 3, 16), ("multigrid", 7, 16), ("bjacobi", 33, 8), ("bjacobi", 64, 8)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("pc,restart,n", CASES)
+def test_restart_lengths_reach_the_oracle_bar(fe, pc, restart, n, prec):
+    p = inputs.config(1) if n == 8 else inputs.scaled_config(n, n, n, 1e4, seed=71)
+    print(f"[fgmres] {n}^3 {pc} restart {restart} {prec}", flush=True)
+    xs, rep = _solve(fe, p, rtol_newton=1e-8, krylov_op_prec=prec, precond=pc, restart=restart,
+                     max_lin=4000)
+    its = rep["lin_its"][:rep["newton_its"]]
+    r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+    r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
+    print(f"[fgmres] newton {rep['newton_its']} lin {its}: oracle |R|/|R0| = {r / r0:.3e}")
+    assert rep["precond"] == pc
+    assert r <= 1e-8 * r0 * 1.0001
+    if restart > 32:
+        assert max(its) > 32, "the second column group was not reached"
+
+
+@pytest.mark.parametrize("restart,cap", [(1, 7), (4, 9), (64, 10), (5, 5)])
+def test_iteration_cap_is_exact(fe, restart, cap):
+    """Every linear solve stops at exactly max_lin iterations when it cannot
+    converge in fewer (block-Jacobi on C1 needs far more)."""
+    p = inputs.config(1)
+    xs, rep = _solve(fe, p, rtol_newton=1e-8, precond="bjacobi", restart=restart, max_lin=cap,
+                     max_newton=2, allow_not_converged=True)
+    its = rep["lin_its"][:rep["newton_its"]]
+    print(f"[fgmres] restart {restart} cap {cap}: lin {its}")
+    assert rep["newton_its"] >= 1
+    assert all(k == cap for k in its), its
+    assert np.all(np.isfinite(xs))
