@@ -140,3 +140,32 @@ def test_batched_server_with_requests_that_have_no_multigrid(fe):
         print(f"[batched] {p.nx}x{p.ny}x{p.nz}: levels {rep['mg_levels']}, oracle |R|/|R0| = {r / r0:.3e}")
         assert r <= 1e-8 * r0 * 1.0001, (i, r / r0)
         assert np.array_equal(x, alone[i][0]), f"request {i} differs alone vs in the mix"
+
+
+@pytest.mark.parametrize("prec,restart", [("mixed", 5), ("fp64", 8)])
+def test_batched_server_short_restarts(fe, prec, restart):
+    """Cycles that end at the restart length: the engine finishes a cycle's last
+    Hessenberg column from the candidate's dot products alone (the delayed
+    Gram-Schmidt), then restarts from the true residual.  (At restart 3 two of
+    these four systems stagnate, in the one-problem solver as well: restarted
+    GMRES with so short a cycle does not converge on them.)"""
+    reqs = inputs.serving_trace(n_requests=4, seed=4200, sizes=(16, 24))
+    probs = [inputs.request_problem(r) for r in reqs]
+    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, restart=restart)
+    alone = []
+    with fe.Server(2 << 30, max_active=1, batched=True) as srv:
+        for p in probs:
+            rc, x, rep = srv.wait(_submit(fe, srv, p, opts))
+            assert rc == fe.FE_OK, rep
+            alone.append(x)
+    with fe.Server(4 << 30, max_active=4, batched=True) as srv:
+        res = [srv.wait(t) for t in [_submit(fe, srv, p, opts) for p in probs]]
+    for i, ((rc, x, rep), p) in enumerate(zip(res, probs)):
+        assert rc == fe.FE_OK, (i, rep)
+        its = rep["lin_its"][:rep["newton_its"]]
+        r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+        r = np.linalg.norm(oracle.residual(p, x, mask="solve"))
+        print(f"[batched] restart {restart} {prec} {p.nx}^3: lin {its}, oracle |R|/|R0| = {r / r0:.3e}")
+        assert max(its) > restart, "no cycle reached the restart length"
+        assert r <= 1e-8 * r0 * 1.0001, (i, r / r0)
+        assert np.array_equal(x, alone[i]), f"request {i} differs alone vs in the mix"
