@@ -289,7 +289,7 @@ int serve_create(size_t hbm_budget_bytes, int max_active, fe_server **out);
  * (over a batch the element pass moves far fewer bytes than a stencil).  max_active may then be up to 256.
  * A request's result is the same alone and in any mix (its arithmetic does not
  * depend on the batch); it can differ from the default mode's in the last bits
- * (the batched Gram-Schmidt step always takes its second pass).  Requests whose
+ * (the batched reductions chunk the vectors differently).  Requests whose
  * grid has no multigrid hierarchy use their worker's one-problem FGMRES. */
 #define FE_SERVE_BATCHED 1
 int serve_create_ex(size_t hbm_budget_bytes, int max_active, int flags, fe_server **out);
