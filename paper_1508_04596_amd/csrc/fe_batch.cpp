@@ -130,6 +130,7 @@ struct Solve {
     std::vector<double> H, cs, sn, g, y;
     std::vector<double> Hp;  // provisional column j - 1 (first-projection coefficients)
     double om = 0, c2 = 0;   // scale and squared norm of the candidate c_j
+    bool col_final = false;  // column j - 1 was finished before step j (J_FINAL)
     double beta0 = 0, target = 0, res = 0;
     bool breakdown = false, est_conv = false, need_true = false, waited = false;
 };
@@ -524,6 +525,7 @@ void BatchEngine::update(Solve &S, bool *finished)
         S.c2 = 1.0;
         S.res = beta;
         S.breakdown = false;
+        S.col_final = false;
         next_step();
     };
     // column j - 1 from its provisional entries, the candidate's s and sigma
@@ -567,9 +569,10 @@ void BatchEngine::update(Solve &S, bool *finished)
         if (j == 0) {
             S.g[0] = S.om * sig;
             if (!(sig > 0.0)) S.breakdown = true;
-        } else {
+        } else if (!S.col_final) {
             finish_column(j, hh, sig);
         }
+        S.col_final = false;
         if (S.breakdown || (j >= 1 && S.res <= S.target)) {
             end_cycle(j);
             return;
@@ -593,10 +596,14 @@ void BatchEngine::update(Solve &S, bool *finished)
             return;
         }
         finish_column(j, hh, s2 > 0.0 ? std::sqrt(s2) : 0.0);
-        if (S.res <= S.target || J.its >= J.max_its || j == m || S.breakdown)
+        if (S.res <= S.target || J.its >= J.max_its || j == m || S.breakdown) {
             end_cycle(j);
-        else
+        } else {
+            // the estimate was optimistic: take step j, whose dot pass must not
+            // finish column j - 1 (and rotate g) a second time
+            S.col_final = true;
             S.state = J_ITER;
+        }
         return;
     }
     case J_CEND: {

@@ -229,7 +229,8 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
         double om = beta, c2 = 1.0;  // scale and squared norm of the candidate
         double res = beta;
         bool breakdown = false;
-        int kk = 0;  // final columns of H
+        int kk = 0;               // final columns of H
+        bool col_final = false;   // column j - 1 was finished before step j
         // column j - 1 of H from its provisional entries Hp and the candidate's
         // dot products s (host copy) and remaining norm sig
         auto finish = [&](int j, const double *s, double sig) {
@@ -265,6 +266,9 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
                     }
                     finish(j, hh, s2 > 0.0 ? std::sqrt(s2) : 0.0);
                     if (res <= target || stats->its >= max_its || j == m || breakdown) break;
+                    // the estimate was optimistic: take step j, whose dot pass
+                    // must not finish column j - 1 (and rotate g) a second time
+                    col_final = true;
                 }
             } else if (stats->its >= max_its) {
                 break;
@@ -299,9 +303,10 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
             if (j == 0) {
                 g[0] = om * sig;  // r = beta sigma_0 q_0
                 if (!(sig > 0.0)) breakdown = true;
-            } else {
+            } else if (!col_final) {
                 finish(j, hh, sig);
             }
+            col_final = false;
             // a column that already meets the target ends the cycle; the step's
             // Krylov vector is then not used
             if (breakdown || (j >= 1 && res <= target)) break;
