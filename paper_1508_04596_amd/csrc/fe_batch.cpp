@@ -24,6 +24,7 @@
 // only the reductions are chunked differently, so the two agree to rounding,
 // not bitwise.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -330,7 +331,7 @@ struct BatchEngine {
     std::vector<Solve> active;
     std::vector<int> free_slots;
     Planner P;
-    uint64_t steps = 0, launches = 0;
+    std::atomic<uint64_t> steps{0}, launches{0};  // read by other threads (batch_engine_stats)
 
     int ensure_stage(size_t bytes)
     {
@@ -780,8 +781,8 @@ int batch_fgmres(BatchEngine *E, BJob *job, hipStream_t st)
 
 void batch_engine_stats(const BatchEngine *E, uint64_t *steps, uint64_t *launches)
 {
-    if (steps) *steps = E ? E->steps : 0;
-    if (launches) *launches = E ? E->launches : 0;
+    if (steps) *steps = E ? E->steps.load() : 0;
+    if (launches) *launches = E ? E->launches.load() : 0;
 }
 
 }  // namespace fe
