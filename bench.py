@@ -40,16 +40,21 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_ELEM_JV = 3371.0
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
-# HBM bytes per launch of the FP64 J v element-pass kernel on the 64^3 workload
-# (1024 tiles), from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
-# torch's double->float copy of a 1,373,125-entry vector (10,985,000 B read,
-# 5,492,500 B written): reads x 1.951, writes x 1.000.  Stale (set to None)
-# whenever the element kernel changes.
-ELEM_FETCH_KIB, ELEM_WRITE_KIB = 14235.69, 17217.09
+# HBM traffic per launch of the FP64 J v element-pass kernel, per workload
+# (64^3: 1024 tiles; 160x160x320: 32,000 tiles), from two rocprofv3 --pmc runs
+# of this script each (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the same counter reads for torch's double->float copy of a
+# 1,373,125-entry vector (10,985,000 B read, 5,492,500 B written): reads
+# x 1.951, writes x 1.000.  Workloads without counters report null.
+ELEM_COUNTERS_KIB = {2: (14235.69, 17217.09), 3: (474298.5, 537484.2)}
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
-ELEM_TRAFFIC_BYTES = (1024 * (ELEM_FETCH_KIB * FETCH_SCALE + ELEM_WRITE_KIB * WRITE_SCALE)
-                      if ELEM_FETCH_KIB is not None else None)
+
+
+def elem_traffic_bytes(config):
+    kib = ELEM_COUNTERS_KIB.get(config)
+    return None if kib is None else 1024 * (kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE)
+
+
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
 ELEM_TRAFFIC_SRC_SHA256 = "bd823b2899c8aedc0a9ffff1ce7e1b6fed40a382440cf86e0a638cc1111f5d19"
@@ -198,8 +203,8 @@ def main():
     t_elem32 = float(np.median([q["t_elem32"] for q in recs]))
     bytes_alg = jv_bytes(n_nodes, n_el)
     achieved = FLOPS_PER_ELEM_JV * n_el / t_elem64
-    # the traffic counters were taken on the 64^3 workload, for one source of the kernel
-    traffic = ELEM_TRAFFIC_BYTES if args.config == 2 and elem_source_sha256() == \
+    # the traffic counters were taken per workload, for one source of the kernel
+    traffic = elem_traffic_bytes(args.config) if elem_source_sha256() == \
         ELEM_TRAFFIC_SRC_SHA256 else None
     n_tiles = -(-p.nx // 8) * -(-p.ny // 8) * -(-p.nz // 4)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,

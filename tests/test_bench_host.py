@@ -43,3 +43,14 @@ def test_traffic_guard_tracks_the_element_source():
     import bench
     sha = bench.elem_source_sha256()
     assert len(sha) == 64 and len(bench.ELEM_TRAFFIC_SRC_SHA256) == 64
+
+
+def test_traffic_per_workload():
+    """Counter-based traffic exists for the 64^3 and 160x160x320 workloads (KiB
+    per dispatch scaled by the copy calibration), and is null elsewhere."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t2, t3 = bench.elem_traffic_bytes(2), bench.elem_traffic_bytes(3)
+    assert t2 == pytest.approx(1024 * (14235.69 * 1.951 + 17217.09))
+    assert t3 > 30 * t2  # 32,000 tiles against 1,024
+    assert bench.elem_traffic_bytes(4) is None
