@@ -5,6 +5,8 @@ the bench workload (64^3) is compared in full, element by element.  FP64
 operators must match to 1e-11 relative (norm-wise and per entry against the
 vector's largest entry); the FP32 product is compared at its own precision.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -42,6 +44,11 @@ CASES = [
     ("ragged 17x10x5 Gr=1e5", lambda: inputs.scaled_config(17, 10, 5, 1e5, seed=78, extra_passes=1)),
     ("single element", lambda: inputs.tiny_problem(1, 1, 1, Gr=5e2)),
     ("thin 2x21x3", lambda: inputs.tiny_problem(2, 21, 3, Gr=2e4)),
+    # degenerate designs: no Brinkman term anywhere, and the largest everywhere
+    ("all fluid 11x9x6", lambda: dataclasses.replace(inputs.scaled_config(11, 9, 6, 1e4, seed=79),
+                                                     gamma=np.ones(11 * 9 * 6))),
+    ("all solid 11x9x6", lambda: dataclasses.replace(inputs.scaled_config(11, 9, 6, 1e4, seed=80),
+                                                     gamma=np.zeros(11 * 9 * 6))),
 ]
 
 

@@ -213,3 +213,28 @@ def test_multigrid_wide_band_coarsest_level(fe, prec):
     assert bwd <= 1e-8
     assert arep["lin_its_total"] <= 25
     prob.close()
+
+
+@pytest.mark.parametrize("design", ["all fluid", "all solid"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_degenerate_designs(fe, design, prec):
+    """A design with no Brinkman term anywhere (free natural convection in the
+    box) and one with the largest everywhere (conduction through solid, the
+    velocity held near zero) both reach the oracle's bar."""
+    import dataclasses
+    base = inputs.scaled_config(16, 16, 12, 1e4, seed=81)
+    g = np.ones(base.n_el) if design == "all fluid" else np.zeros(base.n_el)
+    p = dataclasses.replace(base, gamma=g)
+    print(f"[solve] {design} {prec}", flush=True)
+    prob = fe.Problem.from_inputs(p, mask="solve")
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
+    rep = fe.newton_solve(prob, dev(p.gamma), dev(p.s), x,
+                          fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec))
+    xs = host(x)
+    r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
+    r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
+    vel = np.abs(xs.reshape(-1, 5)[:, :3]).max()
+    print(f"[solve] {design} {prec}: newton {rep['newton_its']} lin {rep['lin_its'][:rep['newton_its']]} "
+          f"rel {r / r0:.3e} max |u| {vel:.3e} levels {rep['mg_levels']}")
+    assert r <= 1e-8 * r0 * 1.0001
+    prob.close()
