@@ -356,6 +356,32 @@ def test_design_derivative_against_central_differences():
         assert g[e] == pytest.approx(fd, rel=1e-6, abs=1e-12 * np.abs(g).max())
 
 
+def test_jv_and_design_derivative_in_the_last_continuation_step():
+    """Sec. "Continuation scheme", last step (q_f = 881, q_alpha = 998,
+    alpha_bar = 1e7, C_k = 1e-2): alpha spans five decades over the design
+    range and is 1e7 in the source region, so the Brinkman rows dwarf the rest.
+    J v and lambda^T dR/dgamma against central differences there."""
+    p = inputs.tiny_problem(4, 3, 4, Gr=5e3, seed=13, Ck=0.01, qf=881.0, alpha_max=1e7,
+                            q_alpha=998.0)
+    p.gamma = np.clip(p.gamma, 0.1, 0.9)
+    x = inputs.random_state(p, 25)
+    m = p.mask_walls.astype(bool)
+    for seed in (1, 2):
+        v = inputs.random_direction(p, seed)
+        eps = 1e-6 * (1 + np.abs(x).max()) / np.abs(v).max()
+        fd = (oracle.residual(p, x + eps * v) - oracle.residual(p, x - eps * v)) / (2 * eps)
+        jv = oracle.jvp(p, x, v)
+        assert np.linalg.norm(fd[~m] - jv[~m]) <= 1e-7 * np.linalg.norm(jv[~m])
+    lam = inputs.random_direction(p, 26)
+    g = oracle.dR_dgamma(p, x, lam)
+    for seed in (33, 34):
+        d = inputs.random_gamma_direction(p, seed)
+        eps = 1e-7
+        fd = lam @ (oracle.residual(p, x, gamma=p.gamma + eps * d)
+                    - oracle.residual(p, x, gamma=p.gamma - eps * d)) / (2 * eps)
+        assert g @ d == pytest.approx(fd, rel=1e-6)
+
+
 # ------------------------------------------------------------------ solves --
 
 def test_line_search_rule_on_scripted_norms():
