@@ -33,7 +33,10 @@ struct SolverWs {
     double *hbuf = nullptr;  // device: Gram-Schmidt products of a step | [255] cycle scale
     double *ydev = nullptr;  // device: combination coefficients
     double *hhost = nullptr; // pinned host copy of hbuf / y
-    hipEvent_t ev[8] = {};
+    // 0-2 / 8-10: preconditioner start, operator start, operator end of even /
+    // odd Arnoldi steps; 3: Gram-Schmidt end; 4-5: set-up; 6: batched job;
+    // 11: a step's results copied; 12-13: the candidate-only dot pass
+    hipEvent_t ev[16] = {};
     Mg *mg = nullptr;        // multigrid hierarchy (created on first use)
     fe_problem *owner = nullptr;  // allocations go through owner->alloc
 };
@@ -194,6 +197,10 @@ double givens_estimate(const std::vector<double> &col, int c, const std::vector<
 // give (subdiagonal omega_j |c_j|) is checked; when it reaches the target, the
 // column is finished from the candidate's dot products alone
 // (launch_dgs_final), so the cycle does not pay for a step it does not use.
+// The next step's preconditioner and operator act on the candidate that the
+// update pass leaves on the device, so while the residual is far above the
+// target (SPEC_MARGIN) they are enqueued before the host waits for the step's
+// results, and the GPU does not idle during the host's Givens update.
 static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, double rtol, int m,
                   int max_its, int n_refine, hipStream_t st, LinStats *stats, int verbose)
 {
@@ -219,6 +226,7 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
     const double *r = b;  // residual of the current cycle (b on the first cycle)
     double beta = beta0;
     int refine_left = n_refine;
+    constexpr double SPEC_MARGIN = 100.0;
     while (true) {
         // candidate c_0 = r / beta (r = beta c_0)
         w->hhost[200] = beta;
@@ -231,6 +239,19 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
         bool breakdown = false;
         int kk = 0;               // final columns of H
         bool col_final = false;   // column j - 1 was finished before step j
+        bool spec = false;        // step j's preconditioner and operator are enqueued
+        // z_j = M c_j and w = A z_j into column j + 1, between the step's events
+        auto step_events = [&](int jj) { return w->ev + ((jj & 1) ? 8 : 0); };
+        auto enqueue_step = [&](int jj) -> hipError_t {
+            hipEvent_t *Ej = step_events(jj);
+            void *zj = L.z32 ? (void *)(w->Z32 + (int64_t)jj * ld) : (void *)(w->Z + (int64_t)jj * ld);
+            hipError_t e;
+            if ((e = hipEventRecord(Ej[0], st)) != hipSuccess) return e;
+            if ((e = L.prec(w->V + (int64_t)jj * ld, zj)) != hipSuccess) return e;
+            if ((e = hipEventRecord(Ej[1], st)) != hipSuccess) return e;
+            if ((e = L.op_z(zj, w->V + (int64_t)(jj + 1) * ld)) != hipSuccess) return e;
+            return hipEventRecord(Ej[2], st);
+        };
         // column j - 1 of H from its provisional entries Hp and the candidate's
         // dot products s (host copy) and remaining norm sig
         auto finish = [&](int j, const double *s, double sig) {
@@ -248,14 +269,14 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
                     fin = givens_estimate(Hp, j - 1, cs, sn, g) <= target;
                 }
                 if (fin) {
-                    FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
+                    FE_CHECK_HIP(hipEventRecord(w->ev[12], st));
                     FE_CHECK_HIP(launch_dgs_final(w->V, ld, j, n, w->hbuf, p->partial, st));
-                    FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
+                    FE_CHECK_HIP(hipEventRecord(w->ev[13], st));
                     FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * (j + 1),
                                                 hipMemcpyDeviceToHost, st));
                     FE_CHECK_HIP(hipStreamSynchronize(st));
                     float ms;
-                    if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
+                    if (hipEventElapsedTime(&ms, w->ev[12], w->ev[13]) == hipSuccess) stats->t_orth += ms * 1e-3;
                     const double *hh = w->hhost;
                     double ss = 0.0;
                     for (int i = 0; i < j; ++i) ss += hh[i] * hh[i];
@@ -273,26 +294,26 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
             } else if (stats->its >= max_its) {
                 break;
             }
-            // Arnoldi step j: z_j = M c_j, w = A z_j into column j + 1, then the
-            // two Gram-Schmidt passes
-            double *cj = w->V + (int64_t)j * ld;
-            double *vn = w->V + (int64_t)(j + 1) * ld;
-            void *zj = L.z32 ? (void *)(w->Z32 + (int64_t)j * ld) : (void *)(w->Z + (int64_t)j * ld);
-            FE_CHECK_HIP(hipEventRecord(w->ev[0], st));
-            FE_CHECK_HIP(L.prec(cj, zj));
-            FE_CHECK_HIP(hipEventRecord(w->ev[1], st));
-            FE_CHECK_HIP(L.op_z(zj, vn));
-            FE_CHECK_HIP(hipEventRecord(w->ev[2], st));
+            // Arnoldi step j: z_j = M c_j, w = A z_j into column j + 1 (unless
+            // enqueued ahead), then the two Gram-Schmidt passes
+            hipEvent_t *E = step_events(j);
+            if (!spec) FE_CHECK_HIP(enqueue_step(j));
+            spec = false;
             FE_CHECK_HIP(launch_dgs_step(w->V, ld, j, n, w->hbuf, p->partial, st));
             FE_CHECK_HIP(hipEventRecord(w->ev[3], st));
             FE_CHECK_HIP(hipMemcpyAsync(w->hhost, w->hbuf, sizeof(double) * (2 * j + 9),
                                         hipMemcpyDeviceToHost, st));
-            FE_CHECK_HIP(hipStreamSynchronize(st));
+            FE_CHECK_HIP(hipEventRecord(w->ev[11], st));
+            if (res > SPEC_MARGIN * target && j + 1 < m && stats->its + 1 < max_its) {
+                FE_CHECK_HIP(enqueue_step(j + 1));
+                spec = true;
+            }
+            FE_CHECK_HIP(hipEventSynchronize(w->ev[11]));
             stats->its++;
             float ms;
-            if (hipEventElapsedTime(&ms, w->ev[0], w->ev[1]) == hipSuccess) stats->t_prec += ms * 1e-3;
-            if (hipEventElapsedTime(&ms, w->ev[1], w->ev[2]) == hipSuccess) stats->t_jv += ms * 1e-3;
-            if (hipEventElapsedTime(&ms, w->ev[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, E[0], E[1]) == hipSuccess) stats->t_prec += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, E[1], E[2]) == hipSuccess) stats->t_jv += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, E[2], w->ev[3]) == hipSuccess) stats->t_orth += ms * 1e-3;
             const double *hh = w->hhost;
             const double sig = hh[2 * j + 3], hj = hh[2 * j + 4], omn = hh[2 * j + 5];
             const double cn2 = hh[2 * j + 8];
