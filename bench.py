@@ -38,6 +38,11 @@ sys.path.insert(0, ROOT)
 # signs (FMA = 2 flops, add/mul = 1).  The kernel runs the same arithmetic with
 # run-time signs: multiplications by +-1 are not counted.
 FLOPS_PER_ELEM_JV = 3371.0
+# the FP32 J v element body counted the same way (FP32 arithmetic instructions)
+FLOPS_PER_ELEM_JV32 = 3306.0
+# MI355X FP32 vector peak (packed two-wide); the library is built without
+# packed FP32 instructions, which caps its FP32 arithmetic at the unpacked rate
+PEAK_FP32_VALU, PEAK_FP32_UNPACKED = 157.3e12, 78.6e12
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 # HBM traffic per launch of the FP64 J v element-pass kernel, per workload
@@ -215,6 +220,12 @@ def main():
             "traffic_GBps": traffic / t_elem64 / 1e9 if traffic else None,
             "jv_alg_bytes": bytes_alg,
             "jv_op_alg_GBps": bytes_alg / t_jv64 / 1e9}
+    achieved32 = FLOPS_PER_ELEM_JV32 * n_el / t_elem32
+    roof32 = {"bound": "alu", "achieved": achieved32 / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+              "unit": "TFLOP/s", "frac": achieved32 / PEAK_FP32_VALU,
+              "frac_of_unpacked": achieved32 / PEAK_FP32_UNPACKED,
+              "kernel": f"k_elem<float,float,JV> (FP32 J v element pass, {n_tiles} tiles of 8x8x4)",
+              "kernel_avg_us": t_elem32 * 1e6, "flops_per_elem": FLOPS_PER_ELEM_JV32}
 
     serve = serving_legs(fe, inputs, args) if args.serve_requests > 0 else None
 
@@ -232,7 +243,7 @@ def main():
                    "jv_reps": args.jv_reps},
         "jv_fp64_ms": t_jv64 * 1e3, "jv_fp32_ms": t_jv32 * 1e3,
         "elem_fp64_us": t_elem64 * 1e6, "elem_fp32_us": t_elem32 * 1e6,
-        "jv_fp32_gdofs": n_dof / t_jv32 / 1e9,
+        "jv_fp32_gdofs": n_dof / t_jv32 / 1e9, "roofline_fp32": roof32,
         "solve_fp64_s": last["t_solve64"], "solve_mixed_s": last["t_solvemx"],
         "solve_fp64_converged": last["rep64"]["status"] == 0,
         "solve_mixed_converged": last["repmx"]["status"] == 0,
