@@ -250,6 +250,7 @@ class Problem:
     @classmethod
     def from_inputs(cls, p, mask="solve", device="cuda"):
         """Problem for an ``inputs.Problem`` (``mask`` = 'solve', 'walls' or None)."""
+        lib()  # a missing library is the error to report, before any device work
         m = None
         if mask is not None:
             arr = p.mask_solve if mask == "solve" else p.mask_walls

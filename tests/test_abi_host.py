@@ -2,6 +2,8 @@
 every entry point ``include/fe.h`` declares, rejects bad arguments before
 touching the device, and its line-search rule matches the scripted cases."""
 import os
+import subprocess
+import sys
 import re
 
 import pytest
@@ -101,3 +103,36 @@ def test_footprint_counts_ramping_buffers(fe):
     a = fe.fe_solve_footprint_bytes(16, 16, 16, opts=fe.solve_opts())
     b = fe.fe_solve_footprint_bytes(16, 16, 16, opts=fe.solve_opts(ramp_steps=3))
     assert b - a == r(8 * 5 * 17 ** 3) + r(8 * 16 ** 3)
+
+
+def test_product_path_fails_loudly_without_the_hip_library():
+    """With the HIP library missing, every product entry point raises instead
+    of computing anything on the CPU (there is no fallback path)."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1508_04596_amd import fe, inputs\n"
+        "fe.LIB_PATH = '/nonexistent/libfe_hip.so'\n"
+        "p = inputs.config(1)\n"
+        "calls = [lambda: fe.lib(), lambda: fe.Problem.from_inputs(p, mask='solve'),\n"
+        "         lambda: fe.solve_opts(), lambda: fe.fe_solve_footprint_bytes(8, 8, 8)]\n"
+        "n = 0\n"
+        "for c in calls:\n"
+        "    try:\n"
+        "        c()\n"
+        "    except ImportError:\n"
+        "        n += 1\n"
+        "print(n)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "4"
+
+
+def test_product_modules_do_not_import_the_oracle():
+    """The oracle is test infrastructure: no module of the package imports it."""
+    import re
+    pkg = os.path.join(ROOT, "paper_1508_04596_amd")
+    for name in sorted(os.listdir(pkg)):
+        if name.endswith(".py"):
+            src = open(os.path.join(pkg, name)).read()
+            assert not re.search(r"^\s*(import|from)\s+oracle\b", src, re.M), name
+            assert "libfe_oracle" not in src, name
