@@ -52,7 +52,16 @@ __device__ __forceinline__ void block_sums(double (&acc)[KMAX], int k, double *p
 // derived from the dot products.  A launch covers at most DGS_GROUP basis
 // columns; the group that
 // starts at column 0 also accumulates a, t and e.
+//
+// Both passes run RED_BLOCKS workgroups of 4 waves, at most 4 waves per SIMD,
+// so their register budget is 128 VGPRs (DGS_WAVES).  Left to aim at 8 waves
+// (64 VGPRs), the compiler fits the per-thread accumulators by reusing one
+// load register and waits for each basis column's load before issuing the
+// next: the dot pass then ran at 3.2-3.9 TB/s from 8 columns on.  With the
+// budget stated, a group of up to 18 columns issues all its loads before the
+// first wait, and no instantiation spills.
 constexpr int DGS_GROUP = 32;
+#define DGS_WAVES __attribute__((amdgpu_waves_per_eu(1, 4)))
 
 // Reduction column of accumulator q of a group of nc columns from c0.
 __device__ __forceinline__ int dgs_out(int q, int nc, bool w, int J, int c0)
@@ -67,7 +76,7 @@ __device__ __forceinline__ int dgs_out(int q, int nc, bool w, int J, int c0)
 }
 
 template <int NC, bool W, bool FIRST>
-__global__ __launch_bounds__(RED_THREADS) void k_dgs_dots(const double *__restrict__ V, int64_t ld,
+__global__ __launch_bounds__(RED_THREADS) DGS_WAVES void k_dgs_dots(const double *__restrict__ V, int64_t ld,
                                                           int J, int c0, int64_t n,
                                                           double *__restrict__ partial)
 {
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_dgs_dots(const double *__restri
 // them at hb[2J + 3 .. 2J + 5].  Columns below J are only read, so the three
 // pointers never address the same entries; J <= 63.
 template <int NC, bool FINAL>
-__global__ __launch_bounds__(RED_THREADS) void k_dgs_update(const double *__restrict__ Q, double *__restrict__ c,
+__global__ __launch_bounds__(RED_THREADS) DGS_WAVES void k_dgs_update(const double *__restrict__ Q, double *__restrict__ c,
                                                             double *__restrict__ w, int64_t ld, int J,
                                                             int c0, int64_t n,
                                                             double *__restrict__ hb,
