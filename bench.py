@@ -63,13 +63,14 @@ def elem_traffic_bytes(config):
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
 ELEM_TRAFFIC_SRC_SHA256 = "bd823b2899c8aedc0a9ffff1ce7e1b6fed40a382440cf86e0a638cc1111f5d19"
+SOLVES = "Newton to 1e-8 FP64, mixed and FP64 with an FP32 preconditioner"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "
-       "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+       "{reps} Jv FP64 + {reps} Jv FP32 at x*, " + SOLVES,
     3: "C3: 160x160x320 elements (41,603,205 DOF), Gr=1e6, 30% solid smoothed random design; "
-       "{reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+       "{reps} Jv FP64 + {reps} Jv FP32 at x*, " + SOLVES,
     4: "C4: 96x96x96 elements (4,563,365 DOF), Gr=1e5, 40% solid smoothed random design with "
-       "intermediate values; {reps} Jv FP64 + {reps} Jv FP32 at x*, Newton to 1e-8 FP64 and mixed",
+       "intermediate values; {reps} Jv FP64 + {reps} Jv FP32 at x*, " + SOLVES,
 }
 
 
@@ -139,6 +140,9 @@ def main():
                            max_newton=args.max_newton, max_lin=args.max_lin)
     optsmx = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed", verbose=vb,
                            max_newton=args.max_newton, max_lin=args.max_lin)
+    # FP64 operator, basis and residuals with the FP32 preconditioner
+    optspc = fe.solve_opts(rtol_newton=1e-8, pc_prec="fp32", verbose=vb,
+                           max_newton=args.max_newton, max_lin=args.max_lin)
     stream = torch.cuda.current_stream()
 
     def step(rec):
@@ -174,12 +178,19 @@ def main():
         t0 = time.perf_counter()
         repmx = fe.newton_solve(prob, g, s, xm, optsmx, allow_not_converged=True)
         t_solvemx = time.perf_counter() - t0
+        xp = torch.zeros(n_dof, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reppc = fe.newton_solve(prob, g, s, xp, optspc, allow_not_converged=True)
+        t_solvepc = time.perf_counter() - t0
         torch.cuda.synchronize()
         rec.update(t_elem64=ms64 * 1e-3 / max(n64, 1), t_elem32=ms32 * 1e-3 / max(n32, 1),
                    t_jv64=e0.elapsed_time(e1) * 1e-3 / args.jv_reps,
                    t_jv32=e1.elapsed_time(e2) * 1e-3 / args.jv_reps,
                    t_solve64=t_solve64, t_solvemx=t_solvemx, rep64=rep64, repmx=repmx,
+                   t_solvepc=t_solvepc, reppc=reppc,
                    mixed_vs_fp64=float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)),
+                   pc32_vs_fp64=float(torch.linalg.norm(xp - x64) / torch.linalg.norm(x64)),
                    jv32_vs_jv64=float(torch.linalg.norm(out32.double() - out64) /
                                       torch.linalg.norm(out64)))
         # backward error of the mixed solution measured with the FP64 residual
@@ -254,6 +265,13 @@ def main():
         "solve_fp64_phase_s": {k: last["rep64"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
         "solve_mixed_phase_s": {k: last["repmx"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
         "mixed_vs_fp64_rel": last["mixed_vs_fp64"], "mixed_res_rel": last["mixed_res_rel"],
+        "solve_fp64_pc32_s": last["t_solvepc"],
+        "solve_fp64_pc32_converged": last["reppc"]["status"] == 0,
+        "solve_fp64_pc32_rel_res": last["reppc"]["res_final"] / last["reppc"]["res0"],
+        "newton_its_fp64_pc32": last["reppc"]["newton_its"],
+        "krylov_its_fp64_pc32": last["reppc"]["lin_its"],
+        "solve_fp64_pc32_phase_s": {k: last["reppc"][k] for k in ("t_jv_s", "t_prec_s", "t_orth_s", "t_res_s", "t_setup_s")},
+        "pc32_vs_fp64_rel": last["pc32_vs_fp64"],
         "jv32_vs_jv64_rel": last["jv32_vs_jv64"],
         "roofline": roof, "cpu_baseline": cpu, "serving": serve,
     }

@@ -171,6 +171,18 @@ typedef struct {
                                matrix-free element pass; -1 (default) = 10000, 0 = none */
     int mg_nu_post;         /* multigrid: smoothing sweeps after the coarse-grid correction
                                (default 1; -1 = mg_nu) */
+    fe_prec pc_prec;        /* preconditioner precision with the FP64 operator: FE_FP64
+                               (default) or FE_FP32.  FE_FP32 applies the block-Jacobi or
+                               multigrid preconditioner in FP32 (blocks, stencils and smoothing
+                               from the FP32 state, as in mixed mode) while the Krylov operator,
+                               basis and residuals stay FP64.  Flexible GMRES admits any
+                               preconditioner (Sec. "Solving the linear systems"), so the
+                               solution meets the same FP64 tolerance; only the iteration count
+                               can change.  Ignored when krylov_op_prec = FE_FP32 (the
+                               preconditioner is FP32 there already); also used by
+                               fe_adjoint_solve.  The lockstep engine of the batched server runs
+                               only all-FP64 and mixed solves; a request with this option runs
+                               its linear solves on its own stream instead. */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

@@ -2,7 +2,8 @@
 // Gram-Schmidt (two projections per basis vector, the second delayed into the
 // next step) in FP64, damped Newton with the quadratic L2 line
 // search (Sec. "Solving the non-linear system"), the adjoint solve, and the
-// FP32-operator / FP64-residual refinement used in mixed mode.
+// FP32-operator / FP64-residual refinement used in mixed mode.  An FP32
+// preconditioner can also serve the FP64 operator (fe_solve_opts.pc_prec).
 //
 // The Krylov basis V, the Hessenberg matrix, the Givens rotations and every
 // norm are FP64.  One Arnoldi step runs entirely on the device; the host reads
@@ -25,7 +26,7 @@ namespace fe {
 
 struct SolverWs {
     int m = 0;           // restart length the buffers were sized for
-    bool mixed = false;  // FP32 copies allocated
+    bool mixed = false;  // FP32 copies allocated (FP32 operator or preconditioner)
     int64_t ndof = 0, nn = 0;
     double *R = nullptr, *Rh = nullptr, *R1 = nullptr, *xt = nullptr, *delta = nullptr;
     double *rhs = nullptr, *V = nullptr, *Z = nullptr, *D = nullptr, *tmp = nullptr;
@@ -128,7 +129,8 @@ struct LinSys {
     std::function<hipError_t(const void *z, double *w)> op_z;
     // w = A x with x FP64 (true residual)
     std::function<hipError_t(const double *x, double *w)> op64;
-    bool z32 = false;  // Krylov vectors z_j stored in FP32
+    bool z32 = false;   // Krylov vectors z_j stored in FP32
+    bool op32 = false;  // FP32 operator: every cycle ends with the FP64 true residual
 };
 
 struct LinStats {
@@ -181,9 +183,11 @@ double givens_estimate(const std::vector<double> &col, int c, const std::vector<
 }
 
 // Solve A x = b for x (x = 0 on entry) to |b - A x| <= rtol |b|, FGMRES(m).
-// Mixed mode (z32): the Arnoldi process uses the FP32 operator; each cycle
+// Mixed mode (op32): the Arnoldi process uses the FP32 operator; each cycle
 // ends with the true FP64 residual b - A x, and cycles continue while it is
 // above the target, at most n_refine cycles beyond the first convergence.
+// With an FP32 preconditioner and the FP64 operator (z32 without op32) only
+// the storage of z_j differs from an FP64 solve.
 //
 // Orthogonalisation is classical Gram-Schmidt with two projections per basis
 // vector, the second one delayed by a step (launch_dgs_step): step j
@@ -350,7 +354,7 @@ static int fgmres(fe_problem *p, const LinSys &L, const double *b, double *x, do
         else
             FE_CHECK_HIP(launch_combine<double>(w->Z, ld, kk, w->ydev, x, n, st));
         const bool est_conv = res <= target;
-        const bool need_true = L.z32 || !est_conv;
+        const bool need_true = L.op32 || !est_conv;
         if (stats->its >= max_its && !est_conv) break;
         if (!need_true) {
             stats->converged = true;
@@ -414,6 +418,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->ramp_steps = 0;
     o->mg_assembled_nodes = -1;
     o->mg_nu_post = 1;
+    o->pc_prec = FE_FP64;
 }
 
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
@@ -450,7 +455,8 @@ int64_t fe_solve_footprint_bytes(const fe_grid *grid, const fe_solve_opts *opts)
     fe_solve_opts d;
     fe_solve_opts_default(&d);
     if (!opts) opts = &d;
-    const bool mixed = opts->krylov_op_prec == FE_FP32;
+    // FP32 copies for an FP32 operator or preconditioner
+    const bool mixed = opts->krylov_op_prec == FE_FP32 || opts->pc_prec == FE_FP32;
     const int64_t nn = (int64_t)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
     const int64_t ndof = NF * nn;
     const int64_t ntile = (int64_t)((grid->nx + TX - 1) / TX) * ((grid->ny + TY - 1) / TY) *
@@ -482,12 +488,13 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
                        const fe_solve_opts &opts, fe_solve_report *report, hipStream_t st)
 {
     auto t0 = std::chrono::steady_clock::now();
-    const bool mixed = opts.krylov_op_prec == FE_FP32;
-    int rc = ensure_ws(p, opts.restart, mixed);
+    const bool mixed = opts.krylov_op_prec == FE_FP32;        // FP32 operator (GMRES-IR)
+    const bool pc32 = mixed || opts.pc_prec == FE_FP32;       // FP32 preconditioner
+    int rc = ensure_ws(p, opts.restart, pc32);
     if (rc) return rc;
     SolverWs *w = p->ws;
     int pc = FE_PC_BJACOBI;
-    rc = choose_precond(p, opts, mixed, &pc);
+    rc = choose_precond(p, opts, pc32, &pc);
     if (rc) return rc;
     if (pc == FE_PC_MULTIGRID) {
         rc = mg_set_design(w->mg, p, gamma, s_elem, st);
@@ -513,14 +520,15 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
     }
     rn = r0;
     LinSys L;
-    L.z32 = mixed;
+    L.z32 = pc32;
+    L.op32 = mixed;
     L.prec = [&](const double *v, void *z) -> hipError_t {
         if (pc == FE_PC_MULTIGRID) {
-            int r = mixed ? mg_apply32(w->mg, v, (float *)z, false, st)
-                          : mg_apply64(w->mg, v, (double *)z, false, st);
+            int r = pc32 ? mg_apply32(w->mg, v, (float *)z, false, st)
+                         : mg_apply64(w->mg, v, (double *)z, false, st);
             return r == FE_OK ? hipSuccess : hipErrorUnknown;
         }
-        if (mixed)
+        if (pc32)
             return launch_block_apply<float, double, float>(w->D32, v, (float *)z, p->nn, false,
                                                             nullptr, st);
         return launch_block_apply<double, double, double>(w->D, v, (double *)z, p->nn, false,
@@ -530,8 +538,16 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         if (mixed)
             return launch_elem<float, double>(OP_JV, p->geo, w->x32, (const float *)z, gamma,
                                               s_elem, p->nmask, out, p->slots, st);
-        return launch_elem<double, double>(OP_JV, p->geo, x, (const double *)z, gamma, s_elem,
-                                           p->nmask, out, p->slots, st);
+        const double *z64 = (const double *)z;
+        if (pc32) {
+            // FP32 z_j, FP64 operator: z_j widened into w->Z (whose FP64
+            // columns are otherwise unused when z_j is stored in FP32)
+            hipError_t e = launch_cast<float, double>((const float *)z, w->Z, p->ndof, st);
+            if (e != hipSuccess) return e;
+            z64 = w->Z;
+        }
+        return launch_elem<double, double>(OP_JV, p->geo, x, z64, gamma, s_elem, p->nmask, out,
+                                           p->slots, st);
     };
     L.op64 = [&](const double *v, double *out) -> hipError_t {
         return launch_elem<double, double>(OP_JV, p->geo, x, v, gamma, s_elem, p->nmask, out,
@@ -557,9 +573,10 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
                 return rc;
             }
         }
-        if (mixed) {
-            // the mixed-precision preconditioner uses FP32 blocks only: they are
-            // formed and inverted in FP32 from the FP32 state
+        if (pc32) {
+            // the FP32 preconditioner uses FP32 blocks only: they are formed and
+            // inverted in FP32 from the FP32 state (which the FP32 operator of
+            // mixed mode also reads)
             FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
             FE_CHECK_HIP((launch_blockdiag<float>(p->geo, w->x32, gamma, s_elem, p->nmask, w->D32,
                                                   reinterpret_cast<float *>(p->slots25), st)));
@@ -570,8 +587,8 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
             FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
         }
         if (pc == FE_PC_MULTIGRID) {
-            rc = mg_setup_finish(w->mg, p, w->D, mixed ? w->D32 : nullptr,
-                                 mixed ? w->x32 : nullptr, st);
+            rc = mg_setup_finish(w->mg, p, w->D, pc32 ? w->D32 : nullptr,
+                                 pc32 ? w->x32 : nullptr, st);
             if (rc) {
                 rep.status = rc;
                 fill_report(report, rep);
@@ -581,7 +598,9 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         FE_CHECK_HIP(launch_axpby(n, -1.0, R, 0.0, w->rhs, st));
         FE_CHECK_HIP(hipEventRecord(e1, st));
         LinStats ls;
-        if (p->batch && pc == FE_PC_MULTIGRID && opts.restart <= 64) {
+        // the lockstep engine runs all-FP64 and mixed solves; an FP32
+        // preconditioner with the FP64 operator runs on this stream
+        if (p->batch && pc == FE_PC_MULTIGRID && opts.restart <= 64 && pc32 == mixed) {
             BJob job;
             job.p = p;
             job.mg = w->mg;
@@ -796,37 +815,59 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
         set_error("fe_adjoint_solve: invalid options");
         return FE_EINVAL;
     }
-    int rc = ensure_ws(p, opts.restart, false);
+    // the operator is always FP64 here; pc_prec selects the preconditioner's
+    // precision (krylov_op_prec does not apply)
+    const bool pc32 = opts.pc_prec == FE_FP32;
+    int rc = ensure_ws(p, opts.restart, pc32);
     if (rc) return rc;
     SolverWs *w = p->ws;
     fe_solve_report rep;
     std::memset(&rep, 0, sizeof(rep));
     int pc = FE_PC_BJACOBI;
-    rc = choose_precond(p, opts, false, &pc);
+    rc = choose_precond(p, opts, pc32, &pc);
     if (rc) return rc;
     if (pc == FE_PC_MULTIGRID) {
         rc = mg_set_design(w->mg, p, gamma, s_elem, st);
         if (rc == FE_OK) rc = mg_setup_begin(w->mg, p, x, st);
         if (rc) return rc;
     }
-    FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
-    FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
+    if (pc32) {
+        FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, p->ndof, st)));
+        FE_CHECK_HIP((launch_blockdiag<float>(p->geo, w->x32, gamma, s_elem, p->nmask, w->D32,
+                                              reinterpret_cast<float *>(p->slots25), st)));
+        FE_CHECK_HIP(launch_invert_blocks32(w->D32, p->nn, st));
+    } else {
+        FE_CHECK_HIP(launch_blockdiag(p->geo, x, gamma, s_elem, p->nmask, w->D, p->slots25, st));
+        FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
+    }
     if (pc == FE_PC_MULTIGRID) {
-        rc = mg_setup_finish(w->mg, p, w->D, nullptr, nullptr, st);
+        rc = mg_setup_finish(w->mg, p, w->D, pc32 ? w->D32 : nullptr, pc32 ? w->x32 : nullptr, st);
         if (rc) return rc;
     }
     LinSys L;
-    L.z32 = false;
+    L.z32 = pc32;
+    L.op32 = false;
     L.prec = [&](const double *v, void *z) -> hipError_t {
-        if (pc == FE_PC_MULTIGRID)
-            return mg_apply64(w->mg, v, (double *)z, true, st) == FE_OK ? hipSuccess
-                                                                         : hipErrorUnknown;
+        if (pc == FE_PC_MULTIGRID) {
+            const int r = pc32 ? mg_apply32(w->mg, v, (float *)z, true, st)
+                               : mg_apply64(w->mg, v, (double *)z, true, st);
+            return r == FE_OK ? hipSuccess : hipErrorUnknown;
+        }
+        if (pc32)
+            return launch_block_apply<float, double, float>(w->D32, v, (float *)z, p->nn, true,
+                                                            nullptr, st);
         return launch_block_apply<double, double, double>(w->D, v, (double *)z, p->nn, true,
                                                           nullptr, st);
     };
     L.op_z = [&](const void *z, double *out) -> hipError_t {
-        return launch_elem<double, double>(OP_JTV, p->geo, x, (const double *)z, gamma, s_elem,
-                                           p->nmask, out, p->slots, st);
+        const double *z64 = (const double *)z;
+        if (pc32) {  // FP32 z_j widened into the otherwise unused FP64 columns
+            hipError_t e = launch_cast<float, double>((const float *)z, w->Z, p->ndof, st);
+            if (e != hipSuccess) return e;
+            z64 = w->Z;
+        }
+        return launch_elem<double, double>(OP_JTV, p->geo, x, z64, gamma, s_elem, p->nmask, out,
+                                           p->slots, st);
     };
     L.op64 = [&](const double *v, double *out) -> hipError_t {
         return launch_elem<double, double>(OP_JTV, p->geo, x, v, gamma, s_elem, p->nmask, out,

@@ -52,7 +52,8 @@ class FeSolveOpts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("precond", ctypes.c_int), ("mg_nu", ctypes.c_int),
                 ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double),
                 ("ramp_steps", ctypes.c_int),
-                ("mg_assembled_nodes", ctypes.c_int), ("mg_nu_post", ctypes.c_int)]
+                ("mg_assembled_nodes", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
+                ("pc_prec", ctypes.c_int)]
 
 
 class FeSolveReport(ctypes.Structure):
@@ -222,6 +223,8 @@ def solve_opts(**kw) -> FeSolveOpts:
     for k, v in kw.items():
         if k == "krylov_op_prec" and isinstance(v, str):
             v = FE_FP32 if v in ("fp32", "mixed") else FE_FP64
+        if k == "pc_prec" and isinstance(v, str):
+            v = {"fp64": FE_FP64, "fp32": FE_FP32}[v]
         if k == "precond" and isinstance(v, str):
             v = {"auto": FE_PC_AUTO, "bjacobi": FE_PC_BJACOBI, "multigrid": FE_PC_MULTIGRID,
                  "mg": FE_PC_MULTIGRID}[v]

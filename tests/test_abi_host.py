@@ -54,6 +54,32 @@ def test_bad_grid_is_rejected_before_any_device_call(fe):
     assert rc == fe.FE_EINVAL
 
 
+def test_solve_option_defaults_through_the_binding(fe):
+    """fe_solve_opts_default fills the C struct; reading every field back
+    through the ctypes mirror checks that the two layouts agree (a field out of
+    place would read another field's bytes)."""
+    o = fe.solve_opts()
+    want = dict(rtol_newton=1e-8, rtol_lin=1e-5, max_newton=50, restart=60, max_lin=3000,
+                n_refine=3, krylov_op_prec=fe.FE_FP64, ls_lambda_min=0.05, verbose=0,
+                precond=fe.FE_PC_AUTO, mg_nu=2, mg_omega=0.6, atol_newton=0.0, ramp_steps=0,
+                mg_assembled_nodes=-1, mg_nu_post=1, pc_prec=fe.FE_FP64)
+    assert [f[0] for f in fe.FeSolveOpts._fields_] == list(want)
+    for k, v in want.items():
+        assert getattr(o, k) == v, k
+    assert fe.solve_opts(pc_prec="fp32").pc_prec == fe.FE_FP32
+    assert fe.solve_opts(krylov_op_prec="mixed").krylov_op_prec == fe.FE_FP32
+
+
+def test_fp32_preconditioner_footprint(fe):
+    """An FP32 preconditioner adds the FP32 copies (Krylov vectors z_j, state,
+    blocks and the multigrid levels' FP32 vectors) to the footprint, as mixed
+    mode does."""
+    f64 = fe.fe_solve_footprint_bytes(32, 32, 32, 0.1, fe.solve_opts())
+    f32 = fe.fe_solve_footprint_bytes(32, 32, 32, 0.1, fe.solve_opts(pc_prec="fp32"))
+    fmx = fe.fe_solve_footprint_bytes(32, 32, 32, 0.1, fe.solve_opts(krylov_op_prec="mixed"))
+    assert f64 < f32 == fmx
+
+
 def test_null_handle_is_rejected(fe):
     L = fe.lib()
     assert L.fe_residual(None, None, None, None, None, None) == fe.FE_EINVAL
