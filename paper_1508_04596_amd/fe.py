@@ -686,6 +686,8 @@ def topopt_opts(**kw) -> FeTopoptOpts:
             for kk, vv in v.items():
                 if kk == "krylov_op_prec" and isinstance(vv, str):
                     vv = FE_FP32 if vv in ("fp32", "mixed") else FE_FP64
+                if kk == "pc_prec" and isinstance(vv, str):
+                    vv = {"fp64": FE_FP64, "fp32": FE_FP32}[vv]
                 setattr(sub, kk, vv)
         elif k in ("iters_per_step", "q_f", "q_alpha", "alpha_max"):
             arr = getattr(o, k)

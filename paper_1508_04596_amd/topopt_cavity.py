@@ -25,6 +25,8 @@ def main():
     ap.add_argument("--vf", type=float, default=0.05)
     ap.add_argument("--rtol", type=float, default=1e-4, help="Newton tolerance (relative)")
     ap.add_argument("--mixed", action="store_true", help="FP32 Krylov operator in the state solves")
+    ap.add_argument("--pc32", action="store_true",
+                    help="FP32 preconditioner under the FP64 operator in the state and adjoint solves")
     ap.add_argument("--save", default="", help="write the final design (npy)")
     args = ap.parse_args()
 
@@ -37,9 +39,11 @@ def main():
     dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
     design = dev(p.design.astype(np.uint8), torch.uint8)
     gfix, s = dev(p.gamma), dev(p.s)
+    pc = "fp32" if args.pc32 else "fp64"
     opts = fe.topopt_opts(vf=args.vf, n_steps=len(iters), iters_per_step=iters,
-                          state=dict(rtol_newton=args.rtol,
-                                     krylov_op_prec="mixed" if args.mixed else "fp64"))
+                          state=dict(rtol_newton=args.rtol, pc_prec=pc,
+                                     krylov_op_prec="mixed" if args.mixed else "fp64"),
+                          adjoint=dict(pc_prec=pc))
     T = fe.TopOpt(prob, design, gfix, s, opts)
     rho = dev(np.where(p.design, 1.0 - args.vf, 0.0))
     x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")

@@ -107,12 +107,16 @@ def cavity_setup(fe, N=20, Gr=1e3, s0=10.0, seed=4):
     return p, prob, rho
 
 
-def test_design_gradient_parity(fe):
+@pytest.mark.parametrize("pc_prec", ["fp64", "fp32"])
+def test_design_gradient_parity(fe, pc_prec):
+    """The design gradient through filter, state and adjoint solves matches the
+    oracle's, also with the FP32 preconditioner in both solves (the operator
+    and the Krylov process stay FP64, so the same bars hold)."""
     p, prob, rho = cavity_setup(fe)
     design = dev(p.design.astype(np.uint8), torch.uint8)
     gfix, s = dev(p.gamma), dev(p.s)
-    opts = fe.topopt_opts(vf=0.05, state=dict(rtol_newton=1e-12, ramp_steps=0),
-                          adjoint=dict(rtol_lin=1e-12))
+    opts = fe.topopt_opts(vf=0.05, state=dict(rtol_newton=1e-12, ramp_steps=0, pc_prec=pc_prec),
+                          adjoint=dict(rtol_lin=1e-12, pc_prec=pc_prec))
     T = fe.TopOpt(prob, design, gfix, s, opts)
     x = torch.zeros(p.n_dof, dtype=torch.float64, device="cuda")
     f, g, df, dg, rec = T.evaluate(dev(rho), x)
