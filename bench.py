@@ -51,7 +51,7 @@ PEAK_HBM = 8.0e12
 # scaled by what the same counter reads for torch's double->float copy of a
 # 1,373,125-entry vector (10,985,000 B read, 5,492,500 B written): reads
 # x 1.951, writes x 1.000.  Workloads without counters report null.
-ELEM_COUNTERS_KIB = {2: (14235.69, 17217.09), 3: (474298.5, 537484.2)}
+ELEM_COUNTERS_KIB = {2: (14235.56, 17217.22), 3: (474297.2, 537499.9)}
 FETCH_SCALE, WRITE_SCALE = 1.951, 1.000
 
 
@@ -62,7 +62,7 @@ def elem_traffic_bytes(config):
 
 # SHA-256 of csrc/fe_elem.hip when those counters were taken: any other source
 # of the element kernel reports traffic as null instead of a stale figure.
-ELEM_TRAFFIC_SRC_SHA256 = "bd823b2899c8aedc0a9ffff1ce7e1b6fed40a382440cf86e0a638cc1111f5d19"
+ELEM_TRAFFIC_SRC_SHA256 = "8a83cf2f44759beb6b4460b9132ff4ec9a6524d8e8fe4e43b018195342b39045"
 SOLVES = "Newton to 1e-8 FP64, mixed and FP64 with an FP32 preconditioner"
 WORKLOADS = {
     2: "C2: 64x64x64 elements (1,373,125 DOF), Gr=1e4, 40% solid smoothed random design; "

@@ -456,10 +456,11 @@ __device__ __forceinline__ int opaque_tid()
 // and its mask byte): the box position and the global node index are worked
 // out once for five values.  Fixed trip count, branch-free loads (nodes
 // outside the box or the grid load node 0 and are replaced by 0), all issued
-// before the first wait.
-template <typename T, bool HASV>
+// before the first wait.  The direction may be stored in another type (Tv)
+// than the state; it is converted to T as it is staged.
+template <typename T, bool HASV, typename Tv = T>
 __device__ __forceinline__ void stage_by_node(const Geo &g, const TileIdx &t,
-                                              const T *__restrict__ x, const T *__restrict__ v,
+                                              const T *__restrict__ x, const Tv *__restrict__ v,
                                               const uint8_t *__restrict__ nmask, T (*sx)[BOXN],
                                               T (*sv)[BOXN], int tid)
 {
@@ -480,11 +481,11 @@ __device__ __forceinline__ void stage_by_node(const Geo &g, const TileIdx &t,
             xv[it][f] = in ? xl : T(0);
         }
         if (HASV) {
-            const T *vp = v + NF * gn;
+            const Tv *vp = v + NF * gn;
             const int m = in ? (int)nmask[gn] : 0x1f;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const T vl = vp[f];
+                const T vl = (T)vp[f];
                 vv[it][f] = ((m >> f) & 1) ? T(0) : vl;
             }
         }
@@ -504,9 +505,9 @@ __device__ __forceinline__ void stage_by_node(const Geo &g, const TileIdx &t,
 
 // Stage one value (node and field) per thread and iteration, fixed trip count,
 // branch-free as above.
-template <typename T, bool HASV>
+template <typename T, bool HASV, typename Tv = T>
 __device__ __forceinline__ void stage_by_value(const Geo &g, const TileIdx &t,
-                                               const T *__restrict__ x, const T *__restrict__ v,
+                                               const T *__restrict__ x, const Tv *__restrict__ v,
                                                const uint8_t *__restrict__ nmask, T (*sx)[BOXN],
                                                T (*sv)[BOXN], int tid)
 {
@@ -525,7 +526,7 @@ __device__ __forceinline__ void stage_by_value(const Geo &g, const TileIdx &t,
         xv[it] = in ? xl : T(0);
         vv[it] = T(0);
         if (HASV) {
-            const T vl = v[NF * gn + f];
+            const T vl = (T)v[NF * gn + f];
             const int m = nmask[gn];
             const bool keep = in & (((m >> f) & 1) == 0);
             vv[it] = keep ? vl : T(0);
@@ -548,15 +549,15 @@ __device__ __forceinline__ void stage_by_value(const Geo &g, const TileIdx &t,
 // 709 -> 675 us).  The FP64 kernels stage by value: by node, J v and J^T w did
 // not change and the residual, whose body then no longer fits two waves per
 // SIMD, ran 18-23 % slower.
-template <typename T, int NVO, bool HASV>
+template <typename T, int NVO, bool HASV, typename Tv = T>
 __device__ __forceinline__ void stage(const Geo &g, const TileIdx &t, const T *__restrict__ x,
-                                      const T *__restrict__ v, const uint8_t *__restrict__ nmask,
+                                      const Tv *__restrict__ v, const uint8_t *__restrict__ nmask,
                                       T (*sx)[BOXN], T (*sv)[BOXN], T *so)
 {
     if constexpr (sizeof(T) == 4)
-        stage_by_node<T, HASV>(g, t, x, v, nmask, sx, sv, opaque_tid());
+        stage_by_node<T, HASV, Tv>(g, t, x, v, nmask, sx, sv, opaque_tid());
     else
-        stage_by_value<T, HASV>(g, t, x, v, nmask, sx, sv, (int)threadIdx.x);
+        stage_by_value<T, HASV, Tv>(g, t, x, v, nmask, sx, sv, (int)threadIdx.x);
     if (NVO > 0)
         for (int idx = threadIdx.x; idx < BOXN * NVO; idx += NTHR) so[idx] = T(0);
 }
@@ -909,9 +910,10 @@ __device__ __forceinline__ void elem_jtv(const EC<T> &c, const T (*sx)[BOXN], co
 
 // ---- tile kernel: element loop + ordered LDS accumulation + face slots ---------
 
-template <typename Tin, typename Tout, int OP>
+// Tv: the direction's storage type (default the state's); it is staged as Tin.
+template <typename Tin, typename Tout, int OP, typename Tv = Tin>
 __device__ __forceinline__ void elem_tile(const Geo &g, const Tin *__restrict__ x,
-                                          const Tin *__restrict__ v,
+                                          const Tv *__restrict__ v,
                                           const double *__restrict__ gamma,
                                           const double *__restrict__ src,
                                           const uint8_t *__restrict__ nmask,
@@ -921,7 +923,7 @@ __device__ __forceinline__ void elem_tile(const Geo &g, const Tin *__restrict__ 
     using T = Tin;
     __shared__ TileSmem<T> S;
     const TileIdx t = tile_index(g, blk, nblk);
-    stage<T, NF, OP != OP_RES>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
+    stage<T, NF, OP != OP_RES, Tv>(g, t, x, (OP == OP_RES) ? nullptr : v, nmask, S.x,
                  (OP == OP_RES) ? nullptr : S.v, &S.o[0][0]);
     __syncthreads();
 
@@ -1001,6 +1003,20 @@ __global__ __launch_bounds__(NTHR) void k_elem(Geo g, const Tin *__restrict__ x,
 {
     elem_tile<Tin, Tout, OP>(g, x, v, gamma, src, nmask, out, slots, (int)blockIdx.x,
                              (int)gridDim.x);
+}
+
+// The FP64 operator (J v or J^T w) with the direction stored in FP32.
+template <int OP>
+__global__ __launch_bounds__(NTHR) void k_elem_dir32(Geo g, const double *__restrict__ x,
+                                                     const float *__restrict__ v,
+                                                     const double *__restrict__ gamma,
+                                                     const double *__restrict__ src,
+                                                     const uint8_t *__restrict__ nmask,
+                                                     double *__restrict__ out,
+                                                     double *__restrict__ slots)
+{
+    elem_tile<double, double, OP, float>(g, x, v, gamma, src, nmask, out, slots,
+                                         (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Tiles containing node coordinate I along one direction, in increasing order.
@@ -1718,6 +1734,29 @@ template hipError_t launch_elem<float, float>(ElemOp, const Geo &, const float *
 template hipError_t launch_elem<float, double>(ElemOp, const Geo &, const float *, const float *,
                                                const double *, const double *, const uint8_t *,
                                                double *, double *, hipStream_t, hipEvent_t, hipEvent_t);
+
+hipError_t launch_elem_dir32(ElemOp op, const Geo &g, const double *x, const float *v,
+                             const double *gamma, const double *s, const uint8_t *nmask,
+                             double *out, double *slots, hipStream_t st)
+{
+    const dim3 grid((unsigned)n_tiles(g)), block(NTHR);
+    const int64_t nn = n_nodes(g);
+    const dim3 cgrid((unsigned)((nn + 255) / 256)), cblock(256);
+    if (op == OP_JV) {
+        hipLaunchKernelGGL((k_elem_dir32<OP_JV>), grid, block, 0, st, g, x, v, gamma, s, nmask,
+                           out, slots);
+        hipLaunchKernelGGL((k_combine<float, double, NF, OP_JV>), cgrid, cblock, 0, st, g,
+                           (const double *)slots, nmask, v, out);
+    } else if (op == OP_JTV) {
+        hipLaunchKernelGGL((k_elem_dir32<OP_JTV>), grid, block, 0, st, g, x, v, gamma, s, nmask,
+                           out, slots);
+        hipLaunchKernelGGL((k_combine<float, double, NF, OP_JTV>), cgrid, cblock, 0, st, g,
+                           (const double *)slots, nmask, v, out);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st)

@@ -96,6 +96,13 @@ hipError_t launch_elem(ElemOp op, const Geo &g, const Tin *x, const Tin *v, cons
                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_dRdgamma(const Geo &g, const double *x, const double *lam, const double *gamma,
                            const double *s, const uint8_t *nmask, double *gout, hipStream_t st);
+// J v (OP_JV) or J^T w (OP_JTV) in FP64 at an FP64 state x with the direction
+// stored in FP32 (each value widened as it is staged; the masked entries of the
+// output copy it): the operator of a solve whose preconditioner returns FP32
+// vectors, without a separate widening pass.
+hipError_t launch_elem_dir32(ElemOp op, const Geo &g, const double *x, const float *v,
+                             const double *gamma, const double *s, const uint8_t *nmask,
+                             double *out, double *slots, hipStream_t st);
 // One smoother sweep with the operator fused: x += omega D^{-1} (b - J x) (J^T
 // and D^{-T} when tr), J at state xs; t (node vector) and slots are work space.
 template <typename T>

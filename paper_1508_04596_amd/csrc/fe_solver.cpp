@@ -187,7 +187,7 @@ double givens_estimate(const std::vector<double> &col, int c, const std::vector<
 // ends with the true FP64 residual b - A x, and cycles continue while it is
 // above the target, at most n_refine cycles beyond the first convergence.
 // With an FP32 preconditioner and the FP64 operator (z32 without op32) only
-// the storage of z_j differs from an FP64 solve.
+// the storage of z_j differs from an FP64 solve (the operator widens it).
 //
 // Orthogonalisation is classical Gram-Schmidt with two projections per basis
 // vector, the second one delayed by a step (launch_dgs_step): step j
@@ -421,6 +421,8 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->pc_prec = FE_FP64;
 }
 
+static bool valid_prec(fe_prec q) { return q == FE_FP64 || q == FE_FP32; }
+
 // Resolve the preconditioner choice and make the multigrid hierarchy ready.
 static int choose_precond(fe_problem *p, const fe_solve_opts &o, bool mixed, int *pc)
 {
@@ -538,16 +540,11 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         if (mixed)
             return launch_elem<float, double>(OP_JV, p->geo, w->x32, (const float *)z, gamma,
                                               s_elem, p->nmask, out, p->slots, st);
-        const double *z64 = (const double *)z;
-        if (pc32) {
-            // FP32 z_j, FP64 operator: z_j widened into w->Z (whose FP64
-            // columns are otherwise unused when z_j is stored in FP32)
-            hipError_t e = launch_cast<float, double>((const float *)z, w->Z, p->ndof, st);
-            if (e != hipSuccess) return e;
-            z64 = w->Z;
-        }
-        return launch_elem<double, double>(OP_JV, p->geo, x, z64, gamma, s_elem, p->nmask, out,
-                                           p->slots, st);
+        if (pc32)  // FP32 z_j, widened as the FP64 operator stages it
+            return launch_elem_dir32(OP_JV, p->geo, x, (const float *)z, gamma, s_elem, p->nmask,
+                                     out, p->slots, st);
+        return launch_elem<double, double>(OP_JV, p->geo, x, (const double *)z, gamma, s_elem,
+                                           p->nmask, out, p->slots, st);
     };
     L.op64 = [&](const double *v, double *out) -> hipError_t {
         return launch_elem<double, double>(OP_JV, p->geo, x, v, gamma, s_elem, p->nmask, out,
@@ -727,9 +724,9 @@ int newton_solve(fe_problem *p, const double *gamma, const double *s_elem, doubl
     if (opts_in) opts = *opts_in;
     if (opts.restart < 1 || opts.restart > 64 || opts.max_newton < 0 || opts.max_lin < 1 ||
         !(opts.rtol_newton >= 0) || !(opts.rtol_lin > 0) || opts.ramp_steps < 0 ||
-        opts.ramp_steps > 64) {
+        opts.ramp_steps > 64 || !valid_prec(opts.krylov_op_prec) || !valid_prec(opts.pc_prec)) {
         set_error("newton_solve: invalid options (restart 1..64, max_lin >= 1, rtol_lin > 0, "
-                  "ramp_steps 0..64)");
+                  "ramp_steps 0..64, krylov_op_prec and pc_prec FE_FP64 or FE_FP32)");
         return FE_EINVAL;
     }
     if (opts.ramp_steps == 0) return newton_core(p, gamma, s_elem, x, opts, report, st);
@@ -811,8 +808,10 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
     fe_solve_opts opts;
     fe_solve_opts_default(&opts);
     if (opts_in) opts = *opts_in;
-    if (opts.restart < 1 || opts.restart > 64 || opts.max_lin < 1 || !(opts.rtol_lin > 0)) {
-        set_error("fe_adjoint_solve: invalid options");
+    if (opts.restart < 1 || opts.restart > 64 || opts.max_lin < 1 || !(opts.rtol_lin > 0) ||
+        !valid_prec(opts.pc_prec)) {
+        set_error("fe_adjoint_solve: invalid options (restart 1..64, max_lin >= 1, rtol_lin > 0, "
+                  "pc_prec FE_FP64 or FE_FP32)");
         return FE_EINVAL;
     }
     // the operator is always FP64 here; pc_prec selects the preconditioner's
@@ -860,14 +859,11 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
                                                           nullptr, st);
     };
     L.op_z = [&](const void *z, double *out) -> hipError_t {
-        const double *z64 = (const double *)z;
-        if (pc32) {  // FP32 z_j widened into the otherwise unused FP64 columns
-            hipError_t e = launch_cast<float, double>((const float *)z, w->Z, p->ndof, st);
-            if (e != hipSuccess) return e;
-            z64 = w->Z;
-        }
-        return launch_elem<double, double>(OP_JTV, p->geo, x, z64, gamma, s_elem, p->nmask, out,
-                                           p->slots, st);
+        if (pc32)  // FP32 z_j, widened as the FP64 operator stages it
+            return launch_elem_dir32(OP_JTV, p->geo, x, (const float *)z, gamma, s_elem,
+                                     p->nmask, out, p->slots, st);
+        return launch_elem<double, double>(OP_JTV, p->geo, x, (const double *)z, gamma, s_elem,
+                                           p->nmask, out, p->slots, st);
     };
     L.op64 = [&](const double *v, double *out) -> hipError_t {
         return launch_elem<double, double>(OP_JTV, p->geo, x, v, gamma, s_elem, p->nmask, out,

@@ -51,6 +51,6 @@ def test_traffic_per_workload():
     sys.path.insert(0, ROOT)
     import bench
     t2, t3 = bench.elem_traffic_bytes(2), bench.elem_traffic_bytes(3)
-    assert t2 == pytest.approx(1024 * (14235.69 * 1.951 + 17217.09))
+    assert t2 == pytest.approx(1024 * (14235.56 * 1.951 + 17217.22))
     assert t3 > 30 * t2  # 32,000 tiles against 1,024
     assert bench.elem_traffic_bytes(4) is None

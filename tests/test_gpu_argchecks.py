@@ -50,3 +50,23 @@ def test_short_tensors_raise_before_launch(setup):
     # the unmodified call still works after the rejected ones
     r = fe.fe_residual(prob, x, g, s)
     assert torch.isfinite(r).all()
+
+
+def test_unknown_precision_options_are_rejected(setup):
+    """krylov_op_prec and pc_prec take FE_FP64 or FE_FP32 only: any other value
+    is an error (FE_EINVAL) before any device work, not a silent FP64 solve."""
+    p, prob, g, s, dev = setup
+    x = torch.zeros(p.n_dof, dtype=torch.float64, device=dev)
+    for field in ("krylov_op_prec", "pc_prec"):
+        o = fe.solve_opts()
+        setattr(o, field, 7)
+        with pytest.raises(fe.FeError) as ei:
+            fe.newton_solve(prob, g, s, x, o)
+        assert ei.value.code == fe.FE_EINVAL and field in str(ei.value)
+    o = fe.solve_opts()
+    o.pc_prec = -1
+    with pytest.raises(fe.FeError) as ei:
+        fe.fe_adjoint_solve(prob, x, g, s, x.clone(), opts=o)
+    assert ei.value.code == fe.FE_EINVAL and "pc_prec" in str(ei.value)
+    torch.cuda.synchronize()
+    assert not x.any()
