@@ -4,9 +4,10 @@ A basis vector's second projection happens in the step after it was formed, so
 the last Hessenberg column of a cycle is finished from the candidate's dot
 products alone, at convergence, at the restart length and at the iteration
 cap.  These solves run restart lengths from 3 to 64 (the dot pass covers up to
-32 basis vectors per launch, so 33 and 64 take two launches), in FP64 and in
-mixed precision, and check every converged Newton solve with the oracle's
-residual; the iteration cap must hold exactly, also with cycles of one step.
+32 basis vectors per launch, so 33 and 64 take two launches), in FP64, in
+mixed precision and with the FP32 preconditioner under the FP64 operator, and
+check every converged Newton solve with the oracle's residual; the iteration
+cap must hold exactly, also with cycles of one step.
 """
 import numpy as np
 import pytest
@@ -56,13 +57,19 @@ def _solve(fe, p, **kw):
 CASES = [("multigrid", 3, 16), ("multigrid", 7, 16), ("bjacobi", 33, 8), ("bjacobi", 64, 8)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def _prec_opts(prec):
+    """fp64, mixed (FP32 operator and preconditioner) or pc32 (FP32
+    preconditioner under the FP64 operator, z_j stored in FP32)."""
+    return dict(pc_prec="fp32") if prec == "pc32" else dict(krylov_op_prec=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "pc32"])
 @pytest.mark.parametrize("pc,restart,n", CASES)
 def test_restart_lengths_reach_the_oracle_bar(fe, pc, restart, n, prec):
     p = inputs.config(1) if n == 8 else inputs.scaled_config(n, n, n, 1e4, seed=71)
     print(f"[fgmres] {n}^3 {pc} restart {restart} {prec}", flush=True)
-    xs, rep = _solve(fe, p, rtol_newton=1e-8, krylov_op_prec=prec, precond=pc, restart=restart,
-                     max_lin=4000)
+    xs, rep = _solve(fe, p, rtol_newton=1e-8, precond=pc, restart=restart, max_lin=4000,
+                     **_prec_opts(prec))
     its = rep["lin_its"][:rep["newton_its"]]
     r0 = np.linalg.norm(oracle.residual(p, np.zeros(p.n_dof), mask="solve"))
     r = np.linalg.norm(oracle.residual(p, xs, mask="solve"))
@@ -73,13 +80,14 @@ def test_restart_lengths_reach_the_oracle_bar(fe, pc, restart, n, prec):
         assert max(its) > 32, "the second column group was not reached"
 
 
+@pytest.mark.parametrize("prec", ["fp64", "pc32"])
 @pytest.mark.parametrize("restart,cap", [(1, 7), (4, 9), (64, 10), (5, 5)])
-def test_iteration_cap_is_exact(fe, restart, cap):
+def test_iteration_cap_is_exact(fe, restart, cap, prec):
     """Every linear solve stops at exactly max_lin iterations when it cannot
     converge in fewer (block-Jacobi on C1 needs far more)."""
     p = inputs.config(1)
     xs, rep = _solve(fe, p, rtol_newton=1e-8, precond="bjacobi", restart=restart, max_lin=cap,
-                     max_newton=2, allow_not_converged=True)
+                     max_newton=2, allow_not_converged=True, **_prec_opts(prec))
     its = rep["lin_its"][:rep["newton_its"]]
     print(f"[fgmres] restart {restart} cap {cap}: lin {its}")
     assert rep["newton_its"] >= 1
