@@ -106,6 +106,10 @@ def main():
     ap.add_argument("--serve-burst-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-sizes", type=str, default="16,24,32,48",
                     help="grid sizes n (n^3 elements) the serving trace draws from, comma-separated")
+    ap.add_argument("--serve-prec", default="pc32", choices=("pc32", "mixed", "fp64"),
+                    help="precision of the served solves: pc32 (FP64 operator, FP32 V-cycle; "
+                         "the fastest), mixed (FP32 operator and V-cycle, FP64 true residuals) "
+                         "or fp64")
     ap.add_argument("--serve-only", action="store_true",
                     help="diagnostic: run only the serving legs and print their JSON")
     ap.add_argument("--config", type=int, default=2, choices=(2, 3, 4),
@@ -288,26 +292,29 @@ def serving_legs(fe, inputs, args):
     kernel over all running requests); then a burst that keeps many requests
     in flight, on both."""
     sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+    pr = args.serve_prec
     serve = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
-                        args.serve_max_active, args.serve_rate, sizes=sizes)
+                        args.serve_max_active, args.serve_rate, sizes=sizes, prec=pr)
     serve["batched"] = serve_trace(fe, inputs, args.serve_requests, args.serve_budget_gb,
                                    args.serve_batched_max_active, args.serve_rate, batched=True,
-                                   sizes=sizes)
+                                   sizes=sizes, prec=pr)
     if args.serve_burst_rate > 0:
         serve["burst"] = {
             "default": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
-                                   args.serve_max_active, args.serve_burst_rate, sizes=sizes),
+                                   args.serve_max_active, args.serve_burst_rate, sizes=sizes,
+                                   prec=pr),
             "batched": serve_trace(fe, inputs, args.serve_requests, args.serve_burst_budget_gb,
                                    args.serve_batched_max_active, args.serve_burst_rate,
-                                   batched=True, sizes=sizes)}
+                                   batched=True, sizes=sizes, prec=pr)}
     return serve
 
 
 def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False,
-                sizes=(16, 24, 32, 48)):
+                sizes=(16, 24, 32, 48), prec="pc32"):
     """Serving workload: n requests with Poisson arrivals (20/s by default), grids uniform
     over sizes^3 ({16,24,32,48}^3 by default), log10 Gr uniform in [3,5], 40 %-solid
-    smoothed random designs, mixed precision to 1e-8; latency = completion - arrival.
+    smoothed random designs, solved to 1e-8 (``prec``: mixed, pc32 = FP64 operator with the
+    FP32 V-cycle, or fp64); latency = completion - arrival.
     ``batched``: the lockstep server (one launch per kernel over all running requests)."""
     import time as _t
     reqs = inputs.serving_trace(n_requests=n, rate_per_s=rate, seed=4000, sizes=sizes)
@@ -316,7 +323,8 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False,
     if (n, sizes) not in _SERVE_PROBS:
         _SERVE_PROBS[(n, sizes)] = [inputs.request_problem(r) for r in reqs]
     probs = _SERVE_PROBS[(n, sizes)]
-    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec="mixed")
+    opts = (fe.solve_opts(rtol_newton=1e-8, pc_prec="fp32") if prec == "pc32" else
+            fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec))
     lat, tickets, statuses = [], [], []
     with fe.Server(int(budget_gb * (1 << 30)), max_active=max_active, batched=batched) as srv:
         # warm-up, not timed: one request of each grid size (first use of the
@@ -343,7 +351,7 @@ def serve_trace(fe, inputs, n, budget_gb, max_active, rate=20.0, batched=False,
         steps, launches = steps - steps0, launches - launches0
     lat = np.array([d - a for a, _, d in times])
     makespan = max(d for _, _, d in times) - min(a for a, _, _ in times)
-    return {"requests": n, "sizes": list(sizes), "rate_per_s": rate, "budget_gb": budget_gb,
+    return {"requests": n, "sizes": list(sizes), "prec": prec, "rate_per_s": rate, "budget_gb": budget_gb,
             "max_active": max_active, "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "solves_per_s": n / makespan, "all_converged": all(s == 0 for s in statuses),
             "mode": "batched" if batched else "default",

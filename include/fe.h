@@ -180,9 +180,7 @@ typedef struct {
                                solution meets the same FP64 tolerance; only the iteration count
                                can change.  Ignored when krylov_op_prec = FE_FP32 (the
                                preconditioner is FP32 there already); also used by
-                               fe_adjoint_solve.  The lockstep engine of the batched server runs
-                               only all-FP64 and mixed solves; a request with this option runs
-                               its linear solves on its own stream instead. */
+                               fe_adjoint_solve and by the batched server's lockstep engine. */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

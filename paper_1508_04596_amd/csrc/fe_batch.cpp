@@ -53,7 +53,7 @@ enum Kind {
     K_ST_D, K_ST_F, K_SM0_D, K_SM0_F, K_SM1_D, K_SM1_F,
     K_RS_D, K_RS_F, K_RSS_D, K_RSS_F, K_PR_D, K_PR_F,
     K_CP_D, K_CP_F, K_CS_D, K_CS_F,
-    K_SS_D, K_SS_F, K_SM0C, K_CPY_D, K_CPY_F,
+    K_SS_D, K_SS_F, K_SM0C, K_CPY_D, K_CPY_F, K_WIDEN,
     K_COUNT
 };
 using LaunchFn = hipError_t (*)(const BLaunch &, hipStream_t);
@@ -75,7 +75,7 @@ const LaunchFn kLaunch[K_COUNT] = {
     blaunch_coarse_part<double>, blaunch_coarse_part<float>,
     blaunch_coarse_sum<double>, blaunch_coarse_sum<float>,
     blaunch_stencil_smooth<double>, blaunch_stencil_smooth<float>, blaunch_smooth0_cast,
-    blaunch_copy<double>, blaunch_copy<float>,
+    blaunch_copy<double>, blaunch_copy<float>, blaunch_widen,
 };
 
 // Kind of a templated kernel for T = double / float.
@@ -369,7 +369,7 @@ void BatchEngine::plan(Solve &S)
         emit_norm_scale(P, 8, J, res, J.b, J.V);
         break;
     case J_CEND: {
-        if (J.mixed) {
+        if (J.mixed || J.pc32) {  // z_j stored in FP32
             BComb<float> c{J.Z32, n, S.kk, n, J.x, {}};
             std::copy(S.y.begin(), S.y.begin() + S.kk, c.y);
             P.add(key(0, 0, 4), K_COMB32, c, belt_blocks(n));
@@ -397,6 +397,16 @@ void BatchEngine::plan(Solve &S)
             const BElem<float, double> a{p->geo, J.x32, zj, J.gamma, J.s, p->nmask, vn, p->slots};
             P.add(key(3, 0, 0), K_EJV_FD, a, belem_blocks(p->geo));
             P.add(key(3, 0, 1), K_CJV_FD, a, bnode_blocks(p->geo));
+        } else if (J.pc32) {
+            // FP32 V-cycle into the FP32 column, widened into the (otherwise
+            // unused) FP64 column after the cycle's last phase, FP64 J z
+            float *zj = J.Z32 + (int64_t)S.j * n;
+            double *zw = J.Z + (int64_t)S.j * n;
+            emit_vcycle<float>(P, J.mg, vj, zj);
+            P.add(key(2, MAXD, 50), K_WIDEN, BWiden{zj, zw, n}, belt_blocks(n));
+            const BElem<double, double> a{p->geo, J.xlin, zw, J.gamma, J.s, p->nmask, vn, p->slots};
+            P.add(key(3, 0, 0), K_EJV_DD, a, belem_blocks(p->geo));
+            P.add(key(3, 0, 1), K_CJV_DD, a, bnode_blocks(p->geo));
         } else {
             double *zj = J.Z + (int64_t)S.j * n;
             emit_vcycle<double>(P, J.mg, vj, zj);

@@ -176,6 +176,11 @@ struct BCast {
     float *b;
     int64_t n;
 };
+struct BWiden {  // b = (double) a
+    const float *a;
+    double *b;
+    int64_t n;
+};
 struct BAxpby {  // y = a x + b y
     int64_t n;
     double a;
@@ -253,6 +258,7 @@ struct BDgsUpdate {  // from the reduced dot products in res: sigma, h, omega (t
 inline int belt_blocks(int64_t n) { return (int)((n + 255) / 256); }
 hipError_t blaunch_fill(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_cast(const BLaunch &L, hipStream_t st);
+hipError_t blaunch_widen(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_axpby(const BLaunch &L, hipStream_t st);
 hipError_t blaunch_scale(const BLaunch &L, hipStream_t st);
 template <typename Tz>

@@ -50,6 +50,15 @@ __global__ __launch_bounds__(256) void kb_cast(const BCast *__restrict__ tab, co
     if (i < a.n) a.b[i] = (float)a.a[i];
 }
 
+__global__ __launch_bounds__(256) void kb_widen(const BWiden *__restrict__ tab,
+                                                const int *__restrict__ off, int n)
+{
+    const int e = batch_entry(off, n);
+    const BWiden &a = tab[e];
+    const int64_t i = (int64_t)(blockIdx.x - (unsigned)off[e]) * 256 + threadIdx.x;
+    if (i < a.n) a.b[i] = (double)a.a[i];
+}
+
 __global__ __launch_bounds__(256) void kb_axpby(const BAxpby *__restrict__ tab,
                                                 const int *__restrict__ off, int n)
 {
@@ -320,6 +329,7 @@ __global__ __launch_bounds__(256) void kb_dgs_update(const BDgsUpdate *__restric
     }
 FE_BVLAUNCH(blaunch_fill, kb_fill, BFill)
 FE_BVLAUNCH(blaunch_cast, kb_cast, BCast)
+FE_BVLAUNCH(blaunch_widen, kb_widen, BWiden)
 FE_BVLAUNCH(blaunch_axpby, kb_axpby, BAxpby)
 FE_BVLAUNCH(blaunch_scale, kb_scale, BScale)
 FE_BVLAUNCH(blaunch_dots, kb_dots, BDots)

@@ -217,6 +217,7 @@ struct BJob {
     fe_problem *p = nullptr;
     Mg *mg = nullptr;                 // multigrid hierarchy, set up for this Newton step
     bool mixed = false;               // FP32 V-cycle and J z (GMRES-IR), FP64 otherwise
+    bool pc32 = false;                // (not mixed) FP32 V-cycle, z_j kept in FP32, FP64 J z
     const double *b = nullptr;        // right-hand side
     double *x = nullptr;              // solution (set to 0 first)
     const double *xlin = nullptr;     // linearisation state

@@ -595,13 +595,12 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         FE_CHECK_HIP(launch_axpby(n, -1.0, R, 0.0, w->rhs, st));
         FE_CHECK_HIP(hipEventRecord(e1, st));
         LinStats ls;
-        // the lockstep engine runs all-FP64 and mixed solves; an FP32
-        // preconditioner with the FP64 operator runs on this stream
-        if (p->batch && pc == FE_PC_MULTIGRID && opts.restart <= 64 && pc32 == mixed) {
+        if (p->batch && pc == FE_PC_MULTIGRID && opts.restart <= 64) {
             BJob job;
             job.p = p;
             job.mg = w->mg;
             job.mixed = mixed;
+            job.pc32 = pc32 && !mixed;
             job.b = w->rhs;
             job.x = w->delta;
             job.xlin = x;

@@ -81,11 +81,18 @@ def _submit(fe, srv, p, opts):
     return srv.submit(p.nx, p.ny, p.nz, p.h, ph, p.gamma, p.s, opts)
 
 
-@pytest.mark.parametrize("prec,n_req", [("mixed", 12), ("fp64", 6)])
+def _opts(fe, prec, **kw):
+    """fp64, mixed, or pc32 (FP32 preconditioner under the FP64 operator)."""
+    if prec == "pc32":
+        return fe.solve_opts(rtol_newton=1e-8, pc_prec="fp32", **kw)
+    return fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, **kw)
+
+
+@pytest.mark.parametrize("prec,n_req", [("mixed", 12), ("fp64", 6), ("pc32", 6)])
 def test_batched_server_alone_and_in_the_mix(fe, prec, n_req):
     reqs = inputs.serving_trace(n_requests=n_req, seed=4100)
     probs = [inputs.request_problem(r) for r in reqs]
-    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec)
+    opts = _opts(fe, prec)
     alone = {}
     steps_alone = 0
     with fe.Server(4 << 30, max_active=1, batched=True) as srv:
@@ -142,7 +149,7 @@ def test_batched_server_with_requests_that_have_no_multigrid(fe):
         assert np.array_equal(x, alone[i][0]), f"request {i} differs alone vs in the mix"
 
 
-@pytest.mark.parametrize("prec,restart", [("mixed", 5), ("fp64", 8)])
+@pytest.mark.parametrize("prec,restart", [("mixed", 5), ("fp64", 8), ("pc32", 8)])
 def test_batched_server_short_restarts(fe, prec, restart):
     """Cycles that end at the restart length: the engine finishes a cycle's last
     Hessenberg column from the candidate's dot products alone (the delayed
@@ -151,7 +158,7 @@ def test_batched_server_short_restarts(fe, prec, restart):
     GMRES with so short a cycle does not converge on them.)"""
     reqs = inputs.serving_trace(n_requests=4, seed=4200, sizes=(16, 24))
     probs = [inputs.request_problem(r) for r in reqs]
-    opts = fe.solve_opts(rtol_newton=1e-8, krylov_op_prec=prec, restart=restart)
+    opts = _opts(fe, prec, restart=restart)
     alone = []
     with fe.Server(2 << 30, max_active=1, batched=True) as srv:
         for p in probs:

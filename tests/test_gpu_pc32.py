@@ -103,9 +103,10 @@ def test_adjoint_with_fp32_preconditioner(fe, pc):
 
 
 def test_fp32_preconditioner_requests_on_the_batched_server(fe):
-    """The lockstep engine takes all-FP64 and mixed solves; a request with an
-    FP32 preconditioner and the FP64 operator runs its linear solves on its own
-    stream, beside lockstep requests, and reaches the oracle bar."""
+    """Requests with the FP32 preconditioner share the lockstep engine's steps
+    with all-FP64 and mixed requests (their FP64 J z in the same batched
+    launches as the FP64 requests', their V-cycles in those of the mixed ones)
+    and reach the oracle bar."""
     reqs = inputs.serving_trace(n_requests=4, seed=4300, sizes=(16, 24))
     probs = [inputs.request_problem(r) for r in reqs]
     kinds = ["fp32", "fp64", "fp32", "mixed"]
