@@ -127,7 +127,12 @@ struct BSmooth0Cast {  // b32 = (float) v, x = omega D^{-1} b32
     float omega;
 };
 inline int bstencil_blocks(int64_t nn) { return (int)((NF * nn + 63) / 64); }
-inline int bstencil_smooth_blocks(int64_t nn) { return (int)((nn + 63) / 64); }
+// nodes per workgroup of the one-kernel stencil sweep (k_stencil_smooth)
+constexpr int STENCIL_SMOOTH_NODES = 32;
+inline int bstencil_smooth_blocks(int64_t nn)
+{
+    return (int)((nn + STENCIL_SMOOTH_NODES - 1) / STENCIL_SMOOTH_NODES);
+}
 inline int bsmooth_blocks(int64_t nn) { return (int)((nn + 255) / 256); }
 inline int brestrict_blocks(int64_t nn_c) { return (int)((NF * nn_c + 255) / 256); }
 inline int brestrict_smooth_blocks(int64_t nn_c) { return (int)((nn_c + 50) / 51); }

@@ -293,10 +293,14 @@ __global__ __launch_bounds__(576) void k_stencil_apply(int nx, int ny, int nz, c
 }
 
 // One damped block-Jacobi sweep on an assembled level in one kernel:
-// x_out = x_in + omega D^{-1} (b - A x_in) (A^T and D^{-T} when TR) for 64 nodes
-// per workgroup.  Wave p sums the offsets d = 3p .. 3p + 2 for all five row
-// fields, the nine partials of a row are added in wave order (as in
-// k_stencil_apply), and the node's update is that of k_smooth, so x_out is
+// x_out = x_in + omega D^{-1} (b - A x_in) (A^T and D^{-T} when TR) for
+// STENCIL_SMOOTH_NODES (32) nodes per workgroup of 9 waves.  Wave p sums the
+// offsets d = 3p .. 3p + 2; lanes 0-31 of a wave hold row fields 0-2 of the 32
+// nodes, lanes 32-63 row fields 3-4, so a lane issues at most 45 stencil loads
+// (with 64 nodes and all five rows per lane it was 75, and the small levels
+// this sweep serves left the GPU short of waves).  Each row's partial is the
+// same sum as before, the nine partials of a row are added in wave order (as
+// in k_stencil_apply), and the node's update is that of k_smooth, so x_out is
 // bitwise the result of the two-kernel sweep.  x_out must not alias x_in
 // (other workgroups read x_in at their neighbours).
 template <typename T, bool TR>
@@ -306,23 +310,26 @@ __device__ __forceinline__ void stencil_smooth_nodes(int nx, int ny, int nz, con
                                                      const T *__restrict__ xin,
                                                      T *__restrict__ xout, T omega, unsigned blk)
 {
-    __shared__ T part[9][NF][64];
-    __shared__ T sD[64 * 25];
+    constexpr int SN = STENCIL_SMOOTH_NODES;
+    __shared__ T part[9][NF][SN];
+    __shared__ T sD[SN * 25];
     const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
-    const int64_t n0 = (int64_t)blk * 64;
-    // the workgroup's 64 nodal blocks, coalesced (entries past nn repeat the last)
+    const int ln = lane & (SN - 1), half = lane >> 5;  // node of the block, row half
+    const int g0 = half ? 3 : 0, ng = half ? NF - 3 : 3;
+    const int64_t n0 = (int64_t)blk * SN;
+    // the workgroup's nodal blocks, coalesced (entries past nn repeat the last)
     {
         const int64_t left = nn - n0;
-        const int cnt = (int)(left < 64 ? left : 64) * 25;
+        const int cnt = (int)(left < SN ? left : SN) * 25;
         const T *src = D + n0 * 25;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < (SN * 25 + 575) / 576; ++k) {
             const int q = (int)threadIdx.x + 576 * k;
-            if (q < 64 * 25) sD[q] = src[q < cnt ? q : cnt - 1];
+            if (q < SN * 25) sD[q] = src[q < cnt ? q : cnt - 1];
         }
     }
-    const int64_t N = n0 + lane;
+    const int64_t N = n0 + ln;
     const bool live = N < nn;
     const int64_t Nc = live ? N : nn - 1;
     const int I = (int)(Nc % (nx + 1));
@@ -342,30 +349,33 @@ __device__ __forceinline__ void stencil_smooth_nodes(int nx, int ny, int nz, con
         for (int f = 0; f < NF; ++f) xm[c][f] = xin[NF * Mc[c] + f];
     }
 #pragma unroll
-    for (int g = 0; g < NF; ++g) {
-        T acc = T(0);
+    for (int gg = 0; gg < 3; ++gg) {
+        if (gg < ng) {
+            const int g = g0 + gg;
+            T acc = T(0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int d = 3 * p + c;
+            for (int c = 0; c < 3; ++c) {
+                const int d = 3 * p + c;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const T a = TR ? S[((26 - d) * 25 + f * NF + g) * nn + Mc[c]]
-                               : S[(d * 25 + g * NF + f) * nn + Nc];
-                const T t = a * xm[c][f];
-                acc += inc[c] ? t : T(0);
+                for (int f = 0; f < NF; ++f) {
+                    const T a = TR ? S[((26 - d) * 25 + f * NF + g) * nn + Mc[c]]
+                                   : S[(d * 25 + g * NF + f) * nn + Nc];
+                    const T t = a * xm[c][f];
+                    acc += inc[c] ? t : T(0);
+                }
             }
+            part[p][g][ln] = acc;
         }
-        part[p][g][lane] = acc;
     }
     __syncthreads();
-    if (p == 0 && live) {
-        const T *Dn = sD + lane * 25;
+    if (p == 0 && half == 0 && live) {
+        const T *Dn = sD + ln * 25;
         T rr[NF];
 #pragma unroll
         for (int g = 0; g < NF; ++g) {
-            T sum = part[0][g][lane];
+            T sum = part[0][g][ln];
 #pragma unroll
-            for (int w = 1; w < 9; ++w) sum += part[w][g][lane];
+            for (int w = 1; w < 9; ++w) sum += part[w][g][ln];
             rr[g] = b[NF * N + g] - sum;
         }
 #pragma unroll
@@ -973,11 +983,11 @@ hipError_t mg_stencil_smooth(int nx, int ny, int nz, const T *S, const T *D, con
 {
     const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     if (transpose)
-        hipLaunchKernelGGL((k_stencil_smooth<T, true>), dim3(nblk(n, 64)), dim3(576), 0, st, nx, ny,
-                           nz, S, D, b, xin, xout, omega);
+        hipLaunchKernelGGL((k_stencil_smooth<T, true>), dim3(nblk(n, STENCIL_SMOOTH_NODES)),
+                           dim3(576), 0, st, nx, ny, nz, S, D, b, xin, xout, omega);
     else
-        hipLaunchKernelGGL((k_stencil_smooth<T, false>), dim3(nblk(n, 64)), dim3(576), 0, st, nx, ny,
-                           nz, S, D, b, xin, xout, omega);
+        hipLaunchKernelGGL((k_stencil_smooth<T, false>), dim3(nblk(n, STENCIL_SMOOTH_NODES)),
+                           dim3(576), 0, st, nx, ny, nz, S, D, b, xin, xout, omega);
     return hipGetLastError();
 }
 
