@@ -295,6 +295,7 @@ int mg_set_design(Mg *mg, fe_problem *p, const double *gamma, const double *s, h
         FE_CHECK_HIP(mg_coarsen_elem(C.grid, F.grid, F.s, C.s, st));
         FE_CHECK_HIP(mg_inject_mask(C.grid, F.grid, F.nmask, C.nmask, st));
     }
+    mg->coarse_ready = false;  // the coarsest matrix depends on the design
     return FE_OK;
 }
 
@@ -441,6 +442,9 @@ int mg_setup_begin(Mg *mg, fe_problem *p, const double *x, hipStream_t st)
         MgLevel &C = mg->lev[l], &F = mg->lev[l - 1];
         FE_CHECK_HIP(mg_inject_state(C.grid, F.grid, F.x, C.x, st));
     }
+    // with a kept factorisation the coarsest level is not probed again
+    mg->skip_coarse = mg->reuse_coarse && mg->coarse_ready;
+    if (mg->skip_coarse) return FE_OK;
     // the 135 probing products J p_(colour,field) in FP64 from the coarsest
     // level's element Jacobians (two launches), copied to the host
     MgLevel &C = mg->lev.back();
@@ -494,6 +498,7 @@ int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, 
             FE_CHECK_HIP(launch_invert_blocks(L.D, mg->mixed ? L.D32 : nullptr, L.nn, st));
         }
     }
+    if (mg->skip_coarse) return FE_OK;  // the kept factorisation serves this step
     // (the event also orders the previous set-up's copy out of hfac before the
     // factorisation below rewrites it)
     FE_CHECK_HIP(hipEventSynchronize(mg->probe_ready));
@@ -511,6 +516,7 @@ int mg_setup_finish(Mg *mg, fe_problem *p, const double *D0, const float *D032, 
     FE_CHECK_HIP(hipMemcpyAsync(mg->dmap, mg->hmap, sizeof(int) * 2 * mg->nc, hipMemcpyHostToDevice, st));
     const double *Lc = mg->dfac, *Uc = Lc + n * mg->kl, *Ud = Uc + n * w;
     if (n > 0) FE_CHECK_HIP(mg_coarse_inverse((int)n, mg->kl, mg->ku, Lc, Uc, Ud, mg->dpiv, mg->Xinv, st));
+    mg->coarse_ready = true;
     return FE_OK;
 }
 

@@ -57,6 +57,10 @@ struct Mg {
     double *probe = nullptr;      // element Jacobians (coarsest or assembled level), 1600 per element
     double *probe_out = nullptr;  // 135 probing products, [q][n_dof]
     double *hbuf = nullptr;
+    // The coarsest level's factorisation (Xinv, index maps) can be kept from
+    // one Newton step to the next: reuse_coarse is set by the caller for a
+    // set-up; coarse_ready says a factorisation of the current design exists.
+    bool reuse_coarse = false, coarse_ready = false, skip_coarse = false;
 };
 
 // Dense row-major n_dof x n_dof J of a grid from its 135 probing products

@@ -419,6 +419,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->mg_assembled_nodes = -1;
     o->mg_nu_post = 1;
     o->pc_prec = FE_FP64;
+    o->mg_coarse_reuse = 1;
 }
 
 static bool valid_prec(fe_prec q) { return q == FE_FP64 || q == FE_FP32; }
@@ -563,6 +564,7 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         // the multigrid's coarsest-level work starts first, so that its host
         // factorisation overlaps the block diagonals below
         if (pc == FE_PC_MULTIGRID) {
+            w->mg->reuse_coarse = opts.mg_coarse_reuse != 0 && rep.newton_its > 0;
             rc = mg_setup_begin(w->mg, p, x, st);
             if (rc) {
                 rep.status = rc;
@@ -826,6 +828,7 @@ int fe_adjoint_solve(fe_problem *p, const double *x, const double *gamma, const 
     if (rc) return rc;
     if (pc == FE_PC_MULTIGRID) {
         rc = mg_set_design(w->mg, p, gamma, s_elem, st);
+        w->mg->reuse_coarse = false;
         if (rc == FE_OK) rc = mg_setup_begin(w->mg, p, x, st);
         if (rc) return rc;
     }

@@ -53,7 +53,7 @@ class FeSolveOpts(ctypes.Structure):
                 ("mg_omega", ctypes.c_double), ("atol_newton", ctypes.c_double),
                 ("ramp_steps", ctypes.c_int),
                 ("mg_assembled_nodes", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
-                ("pc_prec", ctypes.c_int)]
+                ("pc_prec", ctypes.c_int), ("mg_coarse_reuse", ctypes.c_int)]
 
 
 class FeSolveReport(ctypes.Structure):
