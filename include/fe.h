@@ -181,12 +181,13 @@ typedef struct {
                                can change.  Ignored when krylov_op_prec = FE_FP32 (the
                                preconditioner is FP32 there already); also used by
                                fe_adjoint_solve and by the batched server's lockstep engine. */
-    int mg_coarse_reuse;    /* multigrid: 1 (default) keeps the coarsest level's factorisation of
-                               a Newton solve's first step for its later steps (the V-cycle's
-                               coarse correction then uses the Jacobian at that first state;
-                               flexible GMRES admits the changed preconditioner), which saves the
-                               probing, the host factorisation and the inverse in those steps;
-                               0 refactors it every Newton step.  Every Newton solve (each
+    int mg_coarse_reuse;    /* multigrid: 1 (default) keeps the coarsest level's factorisation
+                               from one Newton step to the next once the previous step has cut
+                               |R| at least 100-fold (the state then changes little; the V-cycle's
+                               coarse correction uses the Jacobian at the state it was formed at,
+                               and flexible GMRES admits the changed preconditioner), which saves
+                               the probing, the host factorisation and the inverse in those
+                               steps; 0 refactors it every Newton step.  Every Newton solve (each
                                heat-source ramping stage included) and every adjoint solve
                                factorises anew at its start. */
 } fe_solve_opts;

@@ -511,6 +511,7 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
     FE_CHECK_HIP((launch_elem<double, double>(OP_RES, p->geo, x, (const double *)nullptr, gamma,
                                               s_elem, p->nmask, R, p->slots, st)));
     double r0, rn;
+    double rn_before = 0.0;  // |R| before the last Newton step
     rc = norm2(p, R, st, &r0);
     if (rc) return rc;
     rep.res0 = r0;
@@ -559,12 +560,16 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
             break;
         }
         if (rep.newton_its >= opts.max_newton) break;
+        const double rn_step = rn;  // |R| at the start of this Newton step
         hipEvent_t e0 = w->ev[4], e1 = w->ev[5];
         FE_CHECK_HIP(hipEventRecord(e0, st));
         // the multigrid's coarsest-level work starts first, so that its host
         // factorisation overlaps the block diagonals below
         if (pc == FE_PC_MULTIGRID) {
-            w->mg->reuse_coarse = opts.mg_coarse_reuse != 0 && rep.newton_its > 0;
+            // the coarsest factorisation is kept once Newton converges fast (the
+            // last step cut |R| at least 100-fold: the state now changes little)
+            w->mg->reuse_coarse = opts.mg_coarse_reuse != 0 && rep.newton_its > 0 &&
+                                  rn <= 0.01 * rn_before;
             rc = mg_setup_begin(w->mg, p, x, st);
             if (rc) {
                 rep.status = rc;
@@ -686,6 +691,7 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) rep.t_res_s += ms * 1e-3;
         rep.newton_its++;
         if (rep.newton_its <= 64) rep.res_hist[rep.newton_its] = rn;
+        rn_before = rn_step;
         rep.lambda_last = lam;
         if (opts.verbose)
             fprintf(stderr, "newton %2d  |R| %.6e  rel %.3e  lambda %.3f  lin_its %d%s\n",

@@ -243,10 +243,11 @@ def test_newton_degenerate_designs(fe, design, prec):
 @pytest.mark.parametrize("case", ["16^3", "cavity 32"])
 def test_coarse_factorisation_reuse(fe, case):
     """mg_coarse_reuse = 1 (the default) keeps the coarsest level's factorisation
-    of a Newton solve's first step for its later steps.  The preconditioner then
-    differs from step to step, which flexible GMRES admits: both settings reach
-    the oracle's bar with the same Newton steps, and the kept factorisation costs
-    at most a few more FGMRES iterations (none on the smooth problem)."""
+    from one Newton step to the next once a step has cut |R| 100-fold.  The
+    preconditioner then differs from step to step, which flexible GMRES admits:
+    both settings reach the oracle's bar with the same Newton steps, and the
+    kept factorisation costs at most a few FGMRES iterations (none on the
+    smooth problem)."""
     p = (inputs.scaled_config(16, 16, 16, 1e4, seed=5016) if case == "16^3" else
          inputs.cavity_problem(32, 1e5))
     print(f"[coarse-reuse] {case}", flush=True)
