@@ -181,15 +181,16 @@ typedef struct {
                                can change.  Ignored when krylov_op_prec = FE_FP32 (the
                                preconditioner is FP32 there already); also used by
                                fe_adjoint_solve and by the batched server's lockstep engine. */
-    int mg_coarse_reuse;    /* multigrid: 1 (default) keeps the coarsest level's factorisation
-                               from one Newton step to the next once the previous step has cut
-                               |R| at least 100-fold (the state then changes little; the V-cycle's
-                               coarse correction uses the Jacobian at the state it was formed at,
-                               and flexible GMRES admits the changed preconditioner), which saves
-                               the probing, the host factorisation and the inverse in those
-                               steps; 0 refactors it every Newton step.  Every Newton solve (each
-                               heat-source ramping stage included) and every adjoint solve
-                               factorises anew at its start. */
+    int mg_coarse_reuse;    /* preconditioner set-up kept from one Newton step to the next once
+                               the previous step has cut |R| at least 100-fold (the state then
+                               changes little; flexible GMRES admits the preconditioner formed at
+                               the earlier state): 2 (default) keeps all of it (the nodal blocks
+                               and assembled stencils of every level, the coarse levels' states
+                               and the coarsest factorisation); 1 keeps the coarsest level's
+                               factorisation only (no probing, host factorisation or inverse);
+                               0 rebuilds everything every Newton step.  Every Newton solve (each
+                               heat-source ramping stage included) and every adjoint solve builds
+                               its set-up anew at its start. */
 } fe_solve_opts;
 
 /* Preconditioners of the Krylov solves: nodal 5x5 block-Jacobi, or a matrix-free

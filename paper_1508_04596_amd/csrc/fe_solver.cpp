@@ -419,7 +419,7 @@ void fe_solve_opts_default(fe_solve_opts *o)
     o->mg_assembled_nodes = -1;
     o->mg_nu_post = 1;
     o->pc_prec = FE_FP64;
-    o->mg_coarse_reuse = 1;
+    o->mg_coarse_reuse = 2;
 }
 
 static bool valid_prec(fe_prec q) { return q == FE_FP64 || q == FE_FP32; }
@@ -563,13 +563,15 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         const double rn_step = rn;  // |R| at the start of this Newton step
         hipEvent_t e0 = w->ev[4], e1 = w->ev[5];
         FE_CHECK_HIP(hipEventRecord(e0, st));
+        // once Newton converges fast (the last step cut |R| at least 100-fold:
+        // the state now changes little) the coarsest factorisation is kept, or
+        // with mg_coarse_reuse = 2 the whole preconditioner set-up
+        const bool fast = rep.newton_its > 0 && rn <= 0.01 * rn_before;
+        const bool keep_all = opts.mg_coarse_reuse >= 2 && fast;
         // the multigrid's coarsest-level work starts first, so that its host
         // factorisation overlaps the block diagonals below
-        if (pc == FE_PC_MULTIGRID) {
-            // the coarsest factorisation is kept once Newton converges fast (the
-            // last step cut |R| at least 100-fold: the state now changes little)
-            w->mg->reuse_coarse = opts.mg_coarse_reuse != 0 && rep.newton_its > 0 &&
-                                  rn <= 0.01 * rn_before;
+        if (pc == FE_PC_MULTIGRID && !keep_all) {
+            w->mg->reuse_coarse = opts.mg_coarse_reuse != 0 && fast;
             rc = mg_setup_begin(w->mg, p, x, st);
             if (rc) {
                 rep.status = rc;
@@ -577,11 +579,13 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
                 return rc;
             }
         }
-        if (pc32) {
+        // the FP32 state is refreshed every step: the FP32 operator of mixed
+        // mode reads it
+        if (pc32) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+        if (keep_all) {
+        } else if (pc32) {
             // the FP32 preconditioner uses FP32 blocks only: they are formed and
-            // inverted in FP32 from the FP32 state (which the FP32 operator of
-            // mixed mode also reads)
-            FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
+            // inverted in FP32 from the FP32 state
             FE_CHECK_HIP((launch_blockdiag<float>(p->geo, w->x32, gamma, s_elem, p->nmask, w->D32,
                                                   reinterpret_cast<float *>(p->slots25), st)));
             FE_CHECK_HIP(launch_invert_blocks32(w->D32, p->nn, st));
@@ -590,7 +594,7 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
                                                    p->slots25, st)));
             FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
         }
-        if (pc == FE_PC_MULTIGRID) {
+        if (pc == FE_PC_MULTIGRID && !keep_all) {
             rc = mg_setup_finish(w->mg, p, w->D, pc32 ? w->D32 : nullptr,
                                  pc32 ? w->x32 : nullptr, st);
             if (rc) {

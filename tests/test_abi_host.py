@@ -63,7 +63,7 @@ def test_solve_option_defaults_through_the_binding(fe):
                 n_refine=3, krylov_op_prec=fe.FE_FP64, ls_lambda_min=0.05, verbose=0,
                 precond=fe.FE_PC_AUTO, mg_nu=2, mg_omega=0.6, atol_newton=0.0, ramp_steps=0,
                 mg_assembled_nodes=-1, mg_nu_post=1, pc_prec=fe.FE_FP64,
-                mg_coarse_reuse=1)
+                mg_coarse_reuse=2)
     assert [f[0] for f in fe.FeSolveOpts._fields_] == list(want)
     for k, v in want.items():
         assert getattr(o, k) == v, k
