@@ -582,14 +582,13 @@ static int newton_core(fe_problem *p, const double *gamma, const double *s_elem,
         // the FP32 state is refreshed every step: the FP32 operator of mixed
         // mode reads it
         if (pc32) FE_CHECK_HIP((launch_cast<double, float>(x, w->x32, n, st)));
-        if (keep_all) {
-        } else if (pc32) {
+        if (!keep_all && pc32) {
             // the FP32 preconditioner uses FP32 blocks only: they are formed and
             // inverted in FP32 from the FP32 state
             FE_CHECK_HIP((launch_blockdiag<float>(p->geo, w->x32, gamma, s_elem, p->nmask, w->D32,
                                                   reinterpret_cast<float *>(p->slots25), st)));
             FE_CHECK_HIP(launch_invert_blocks32(w->D32, p->nn, st));
-        } else {
+        } else if (!keep_all) {
             FE_CHECK_HIP((launch_blockdiag<double>(p->geo, x, gamma, s_elem, p->nmask, w->D,
                                                    p->slots25, st)));
             FE_CHECK_HIP(launch_invert_blocks(w->D, nullptr, p->nn, st));
